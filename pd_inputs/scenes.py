@@ -1,0 +1,152 @@
+"""Seeded scene descriptions: mesh, Dirichlet set, collision-prone region,
+collision proxies, material constant and obstacle motion.
+
+Everything here is an *input* to the method.  The obstacle schedules only say
+where the spheres are at each step; testing proxies against them is part of
+the method and lives in the oracle and in the GPU kernels separately.
+"""
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+import numpy as np
+
+from .grid import kuhn_grid, layer_mask
+
+YOUNG_E = 1.0e5
+POISSON_NU = 0.45
+
+
+def lame_mu(E=YOUNG_E, nu=POISSON_NU):
+    """Shear modulus mu = E / (2 (1 + nu)); lambda is not used by the method."""
+    return E / (2.0 * (1.0 + nu))
+
+
+@dataclass
+class SphereSchedule:
+    """Rigid spheres pushed into the top face.
+
+    centers(step) -> (3, ns) float64, radii -> (ns,) float64.
+    """
+    base_xy: np.ndarray            # (2, ns)
+    radii: np.ndarray              # (ns,)
+    top_z: float
+    depth_rate: np.ndarray         # (ns,) penetration depth per step
+    drift: Optional[np.ndarray] = None   # (2, ns) lateral drift per step
+
+    def centers(self, step):
+        xy = self.base_xy.copy()
+        if self.drift is not None:
+            xy = xy + self.drift * step
+        z = self.top_z + self.radii - self.depth_rate * step
+        return np.vstack([xy, z[None, :]]).astype(np.float64)
+
+
+@dataclass
+class Scene:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    mu: float
+    rest: np.ndarray               # (3, n) float64
+    tets: np.ndarray               # (4, T) int32
+    dirichlet: np.ndarray          # (n,) bool
+    region: np.ndarray             # (n,) bool  collision-prone nodes x2
+    proxies: np.ndarray            # (np,) int64 global ids of proxy nodes (conforming)
+    k_pen: float
+    spheres: Optional[SphereSchedule] = None
+    outer_iters: int = 10
+    inner_iters: int = 1
+    steps: int = 10
+    seed: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self):
+        return self.rest.shape[1]
+
+    @property
+    def n_tets(self):
+        return self.tets.shape[1]
+
+    def region_ids(self):
+        """Region nodes that are unknowns, ascending global id (region-local order)."""
+        return np.nonzero(self.region & ~self.dirichlet)[0]
+
+    def proxy_local(self):
+        """Proxy positions in region-local numbering."""
+        rid = self.region_ids()
+        pos = np.full(self.n_nodes, -1, dtype=np.int64)
+        pos[rid] = np.arange(rid.size)
+        loc = pos[self.proxies]
+        assert (loc >= 0).all()
+        return loc.astype(np.int32)
+
+
+def _grid_scene(name, nx, ny, nz, h, region_layers, seed, k_pen, **kw):
+    rest, tets = kuhn_grid(nx, ny, nz, h)
+    dirichlet = layer_mask(nx, ny, nz, [0])
+    region = layer_mask(nx, ny, nz, region_layers)
+    proxies = np.nonzero(layer_mask(nx, ny, nz, [nz]))[0].astype(np.int64)
+    return Scene(name=name, nx=nx, ny=ny, nz=nz, h=h, mu=lame_mu(), rest=rest, tets=tets,
+                 dirichlet=dirichlet, region=region, proxies=proxies, k_pen=k_pen,
+                 seed=seed, **kw)
+
+
+def scene_cube8(seed=1):
+    """8x8x8 unit cube (h = 1/8), bottom pinned, region = top face (81 nodes),
+    one sphere of radius 0.3 pushed 0.01 per step into the top face at a
+    seeded lateral offset; k = 1e6; 10 steps of 10 PD iterations."""
+    nx = ny = nz = 8
+    h = 1.0 / 8
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-h, h, size=2)
+    sph = SphereSchedule(base_xy=np.array([[0.5 + off[0]], [0.5 + off[1]]]),
+                         radii=np.array([0.3]), top_z=1.0, depth_rate=np.array([0.01]))
+    return _grid_scene("cube8", nx, ny, nz, h, [nz], seed, 1.0e6, spheres=sph,
+                       outer_iters=10, inner_iters=1, steps=10)
+
+
+def scene_slab56(seed=2, drift=False):
+    """56x56x32 cells (h = 1), bottom pinned, region = top two node layers
+    (6,498 nodes), proxies = top face; 16 seeded spheres (centres U[2,54]^2,
+    radius U[0.5,2]) pressed in at depth_i(s) = d_i r_i s / 100 with
+    d_i ~ U[0.2,0.8]; k = 1e6; 100 steps of 10 PD iterations.
+    With drift=True every sphere also moves laterally U[-0.25,0.25]^2 per step."""
+    nx, ny, nz = 56, 56, 32
+    rng = np.random.default_rng(seed)
+    ns = 16
+    xy = rng.uniform(2.0, 54.0, size=(2, ns))
+    r = rng.uniform(0.5, 2.0, size=ns)
+    d = rng.uniform(0.2, 0.8, size=ns)
+    dr = rng.uniform(-0.25, 0.25, size=(2, ns)) if drift else None
+    sph = SphereSchedule(base_xy=xy, radii=r, top_z=float(nz), depth_rate=d * r / 100.0,
+                         drift=dr)
+    return _grid_scene("slab56", nx, ny, nz, 1.0, [nz - 1, nz], seed, 1.0e6, spheres=sph,
+                       outer_iters=10, inner_iters=1, steps=100)
+
+
+def scene_small(nx, ny, nz, h=1.0, region_top_layers=2, seed=7, n_spheres=2,
+                depth_frac=0.02, k_pen=1.0e6):
+    """Small grids for exhaustive checks: region = the top `region_top_layers`
+    node layers, proxies = top face, a few seeded spheres."""
+    rng = np.random.default_rng(seed)
+    layers = list(range(nz + 1 - region_top_layers, nz + 1))
+    xy = np.vstack([rng.uniform(0.2 * nx * h, 0.8 * nx * h, n_spheres),
+                    rng.uniform(0.2 * ny * h, 0.8 * ny * h, n_spheres)])
+    r = rng.uniform(0.6, 1.5, n_spheres) * h
+    sph = SphereSchedule(base_xy=xy, radii=r, top_z=nz * h,
+                         depth_rate=np.full(n_spheres, depth_frac * h * 5))
+    return _grid_scene(f"small{nx}x{ny}x{nz}", nx, ny, nz, h, layers, seed, k_pen,
+                       spheres=sph, outer_iters=3, inner_iters=1, steps=3)
+
+
+def random_penalty_set(rng, n_proxy, m_region, lo=0.01, hi=0.05):
+    """Solver-benchmark penalty set: a random subset of proxies (between lo*m
+    and hi*m of them) with target offsets drawn U[0, 0.5] downward along z.
+    Returns (proxy positions, depth offsets)."""
+    cnt = int(rng.integers(int(np.ceil(lo * m_region)), int(np.floor(hi * m_region)) + 1))
+    cnt = min(cnt, n_proxy)
+    sel = np.sort(rng.choice(n_proxy, size=cnt, replace=False))
+    depth = rng.uniform(0.0, 0.5, size=cnt)
+    return sel, depth
