@@ -1,0 +1,177 @@
+/*
+ * pdschur.h -- C ABI of the MI355X (gfx950) hot path of localized-collision
+ * Projective Dynamics (Wang, Tao, Brandt, Cutting, Sifakis: "Optimized
+ * Processing of Localized Collisions in Projective Dynamics", SCA 2020).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every call returns pd_status (PD_OK = 0).  No C++ exception crosses the
+ *   ABI.  A failed call leaves a message retrievable with pd_last_error().
+ * - "dev" pointers are device memory owned by the caller (contiguous, float64
+ *   unless stated).  "host" pointers are host memory read during the call.
+ * - Vectors over nodes are coordinate-major: [3][len] (all x, then all y,
+ *   then all z).  Global arrays have len = n_nodes; region arrays have len = m.
+ * - Region-local index = rank of the node among the collision-prone free
+ *   nodes in ascending global id.
+ * - Work is enqueued on the HIP stream given to pd_schur_build.  Calls return
+ *   after enqueueing, except pd_schur_build and a pd_global_solve with a
+ *   non-NULL info pointer, which synchronize the stream.
+ * - Invalid sizes or NULL pointers -> PD_ERR_INVALID with no side effect.  A
+ *   HIP runtime failure -> PD_ERR_HIP and the context refuses further work.
+ * - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef PDSCHUR_H
+#define PDSCHUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_ctx pd_ctx;
+
+typedef enum {
+  PD_OK = 0,
+  PD_ERR_INVALID = -1,     /* bad argument; nothing was enqueued */
+  PD_ERR_HIP = -2,         /* HIP runtime error (sticky) */
+  PD_ERR_OOM = -3,         /* device allocation failed */
+  PD_ERR_NOT_SPD = -4,     /* non-positive pivot in a Cholesky factorization */
+  PD_ERR_IR_STALLED = -5,  /* iterative refinement did not reach its tolerance */
+  PD_ERR_STATE = -6        /* call order violated (e.g. backsub before condense) */
+} pd_status;
+
+typedef enum {
+  PD_FP64 = 0,     /* FP64 factor and solve */
+  PD_FP32_IR = 1,  /* FP32 factor, refinement with an FP64 residual */
+  PD_BF16_IR = 2   /* BF16-operand / FP32-accumulate factor, FP64-residual refinement */
+} pd_precision;
+
+/* Tetrahedral mesh and partition (Sec. 3.2 and Sec. 4.2 of the paper). */
+typedef struct {
+  int64_t n_nodes;
+  int64_t n_tets;
+  const double *rest;       /* host [3][n_nodes] rest positions */
+  const int32_t *tets;      /* host [4][n_tets] vertex ids, det(D_m) > 0 required */
+  const uint8_t *region;    /* host [n_nodes] 1 = collision-prone node (x2) */
+  const uint8_t *dirichlet; /* host [n_nodes] 1 = prescribed node (not an unknown) */
+  double mu;                /* shear modulus; lambda is dropped (Sec. 3.2) */
+} pd_mesh;
+
+typedef struct {
+  int32_t ir_iters;      /* refinement steps taken (0 for PD_FP64) */
+  int32_t bad_pivot;     /* 1-based index of the first non-positive pivot, else 0 */
+  int32_t fell_back;     /* 1 if the call refactored in FP64 after a stall */
+  int32_t reserved;
+  double rel_residual;   /* max over x,y,z of ||g - (S+P)u|| / ||g|| (FP64) */
+} pd_solve_info;
+
+/* Builds everything that stays constant while the mesh deforms (Sec. 4.3,
+ * eq. par_chol and eq. k22 without collisions):
+ *  - element shape operators and volumes, the scalar stiffness K
+ *    (one of the three identical coordinate blocks, Sec. 3.2);
+ *  - the partition: x2 = region & !dirichlet, x1 = other free nodes,
+ *    E_beta = tets with all four vertices in x2, E_alpha = the rest (Sec. 4.5);
+ *  - the interior factor: x1 is ordered by breadth-first distance from x2 and
+ *    eliminated level by level (dense FP64 on the GPU);
+ *  - the dense Schur complement S = K22 - K21 K11^-1 K12 (m x m, FP64).
+ * Synchronous.  *out receives a context freed by pd_destroy.
+ * Errors: PD_ERR_INVALID for out-of-range vertex ids, an empty region or a
+ * non-positive rest volume; PD_ERR_NOT_SPD if an interior level block is not
+ * positive definite (e.g. an interior component with no Dirichlet node). */
+pd_status pd_schur_build(const pd_mesh *mesh, void *hip_stream, pd_ctx **out);
+
+/* Sizes: m = |x2|, n1 = |x1|, E_beta and E_alpha tet counts, interior levels. */
+pd_status pd_query(const pd_ctx *ctx, int64_t *m, int64_t *n1, int64_t *n_beta,
+                   int64_t *n_alpha, int64_t *n_levels);
+
+/* host [m] <- global ids of the region nodes in region-local order. */
+pd_status pd_region_nodes(const pd_ctx *ctx, int32_t *ids);
+
+/* dev [m][m] column-major <- S (both triangles).  Enqueued copy. */
+pd_status pd_get_schur(pd_ctx *ctx, double *S);
+
+/* dev x2 [3][m] <- positions of the region nodes taken from x [3][n_nodes]. */
+pd_status pd_region_gather(pd_ctx *ctx, const double *x, double *x2);
+
+/* Local step and forces on E_alpha (Alg. 1 steps 1-2): R_e = polar(F_e(x))
+ * (Sec. 3.2, orthogonal Procrustes, det R = +1), P = 2 mu (F - R) and
+ * f = -sum_e Vol_e P B_e on every node.  x, f: dev [3][n_nodes]; R_alpha:
+ * dev [9][n_alpha] row-major 3x3 per tet or NULL.  Forces on Dirichlet
+ * nodes are written too (they are not used by the solve). */
+pd_status pd_local_step_full(pd_ctx *ctx, const double *x, double *R_alpha, double *f);
+
+/* Forward substitution through the interior factor (Alg. 1 step 3;
+ * Sec. 4.4 Step 1): y2 = f2 - A21 A11^-1 f1, with f taken from f [3][n_nodes].
+ * y2: dev [3][m].  Keeps A11^-1 f1 in the context for pd_backsub. */
+pd_status pd_condense_rhs(pd_ctx *ctx, const double *f, double *y2);
+
+/* Collision detection against rigid spheres for conforming proxies (paper
+ * Sec. 3.3).  A proxy (region-local node id prox[j]) is in collision iff
+ * ||p - c_s|| < r_s; its target is c_s + r_s (p - c_s)/||p - c_s|| (+z at
+ * the centre); the deepest sphere wins, ties to the lowest index.
+ * Writes one penalty per proxy in the fixed-width layout of
+ * pd_collision_update: idx [n_prox][8] (slot 0 = prox[j], others -1),
+ * w [n_prox][8], c [n_prox] (k or 0 when free), t [3][n_prox].
+ * prox: dev int32 [n_prox]; spheres: dev [4][n_sph] (cx, cy, cz, r). */
+pd_status pd_detect_spheres(pd_ctx *ctx, int32_t n_prox, const int32_t *prox,
+                            int32_t n_sph, const double *spheres, double k,
+                            const double *x2, int32_t *idx, double *w, double *c,
+                            double *t);
+
+/* Penalty update (Sec. 3.3 eq. E_col_C and Sec. 4.3 eq. k22): stores the
+ * penalty set for the next pd_global_solve, whose matrix becomes
+ * H = S + W^T C W, and writes f_col = -W^T C (W x2 - t) (dev [3][m]).
+ * Penalty j touches up to 8 region nodes idx[j][s] (region-local, -1 =
+ * unused, entries within one penalty distinct) with weights w[j][s] and
+ * stiffness c[j] >= 0 (0 = inactive); t is dev [3][n_pen].  The arrays are
+ * copied; the caller may reuse them after the call.  Marks the factor stale. */
+pd_status pd_collision_update(pd_ctx *ctx, int32_t n_pen, const int32_t *idx,
+                              const double *w, const double *c, const double *t,
+                              const double *x2, double *f_col);
+
+/* Local step on E_beta (Alg. 1 step 4.2, Sec. 4.5) at region positions
+ * x2 (dev [3][m]): R_beta (dev [9][n_beta], FP64 or FP32 per rot_fp32, or
+ * NULL) and f_beta (dev [3][m]) = forces of the E_beta tets on region nodes. */
+pd_status pd_local_step_region(pd_ctx *ctx, const double *x2, void *R_beta,
+                               double *f_beta, int rot_fp32);
+
+/* g = ft + f_beta + f_col (Alg. 1 step 4.4), all dev [3][m]; f_beta or f_col
+ * may be NULL (treated as zero). */
+pd_status pd_assemble_rhs(pd_ctx *ctx, const double *ft, const double *f_beta,
+                          const double *f_col, double *g);
+
+/* Dense solve of H u = g with H = S + W^T C W (Alg. 1 steps 4.3 and 4.5,
+ * Sec. 4.4 Step 2): refactors H if the penalty set changed, then solves the
+ * three coordinate right-hand sides.  g, u: dev [3][m].
+ * PD_FP64: FP64 Cholesky.  PD_FP32_IR / PD_BF16_IR: low-precision factor and
+ * iterative refinement with the residual g - H u in FP64 until
+ * rel_residual <= 1e-8 (then PD_ERR_IR_STALLED if not reached: u holds the
+ * best iterate; the call refactors in FP64 and reports fell_back = 1).
+ * info (host) may be NULL; when given, the call synchronizes and fills it. */
+pd_status pd_global_solve(pd_ctx *ctx, const double *g, double *u, pd_precision prec,
+                          pd_solve_info *info);
+
+/* Inner update (Alg. 1 steps 4.6-4.7): x2 += u2, delta2 += u2 and
+ * ft -= Sigma_alpha u2 with Sigma_alpha = S - A22^(beta).  All dev [3][m]. */
+pd_status pd_inner_update(pd_ctx *ctx, const double *u2, double *x2, double *delta2,
+                          double *ft);
+
+/* Back substitution (Alg. 1 step 5, Sec. 4.4 Step 3):
+ * x1 += A11^-1 (f1 - A12 delta2) using f1 of the last pd_condense_rhs, and
+ * x2 += delta2, both written into x (dev [3][n_nodes]).  PD_ERR_STATE if no
+ * pd_condense_rhs preceded it. */
+pd_status pd_backsub(pd_ctx *ctx, const double *delta2, double *x);
+
+/* Last error message of the context (valid until the next call on it).
+ * With ctx = NULL: the message of the last failed pd_schur_build on this thread. */
+const char *pd_last_error(const pd_ctx *ctx);
+
+/* Frees every device and host resource of the context. */
+pd_status pd_destroy(pd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDSCHUR_H */

@@ -1,0 +1,231 @@
+"""ctypes binding of include/pdschur.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libpdschur.so"
+
+PD_OK, PD_ERR_INVALID, PD_ERR_HIP, PD_ERR_OOM, PD_ERR_NOT_SPD, PD_ERR_IR_STALLED, PD_ERR_STATE = \
+    0, -1, -2, -3, -4, -5, -6
+PD_FP64, PD_FP32_IR, PD_BF16_IR = 0, 1, 2
+_NAMES = {0: "PD_OK", -1: "PD_ERR_INVALID", -2: "PD_ERR_HIP", -3: "PD_ERR_OOM",
+          -4: "PD_ERR_NOT_SPD", -5: "PD_ERR_IR_STALLED", -6: "PD_ERR_STATE"}
+
+
+class PDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class pd_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("rest", C.c_void_p),
+                ("tets", C.c_void_p), ("region", C.c_void_p), ("dirichlet", C.c_void_p),
+                ("mu", C.c_double)]
+
+
+class pd_solve_info(C.Structure):
+    _fields_ = [("ir_iters", C.c_int32), ("bad_pivot", C.c_int32), ("fell_back", C.c_int32),
+                ("reserved", C.c_int32), ("rel_residual", C.c_double)]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "pd_schur_build": [C.POINTER(pd_mesh), _P, C.POINTER(_P)],
+    "pd_query": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                 C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+    "pd_region_nodes": [_P, _P],
+    "pd_get_schur": [_P, _P],
+    "pd_region_gather": [_P, _P, _P],
+    "pd_local_step_full": [_P, _P, _P, _P],
+    "pd_condense_rhs": [_P, _P, _P],
+    "pd_detect_spheres": [_P, C.c_int32, _P, C.c_int32, _P, C.c_double, _P, _P, _P, _P, _P],
+    "pd_collision_update": [_P, C.c_int32, _P, _P, _P, _P, _P, _P],
+    "pd_local_step_region": [_P, _P, _P, _P, C.c_int],
+    "pd_assemble_rhs": [_P, _P, _P, _P, _P],
+    "pd_global_solve": [_P, _P, _P, C.c_int, C.POINTER(pd_solve_info)],
+    "pd_inner_update": [_P, _P, _P, _P, _P],
+    "pd_backsub": [_P, _P, _P],
+    "pd_destroy": [_P],
+}
+
+_lib = None
+
+
+def library_path():
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def load_library():
+    """Load libpdschur.so; raises if it is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not built; run paper_2008_01541_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.pd_last_error.argtypes = [_P]
+    lib.pd_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+class PDContext:
+    """One built mesh (pd_schur_build) and its per-iteration entry points."""
+
+    def __init__(self, rest, tets, region, dirichlet, mu, stream=None):
+        import torch
+        lib = load_library()
+        self._lib = lib
+        rest = np.ascontiguousarray(rest, dtype=np.float64)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        region = np.ascontiguousarray(region, dtype=np.uint8)
+        dirichlet = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+        n = rest.shape[1]
+        T = tets.shape[1]
+        if rest.shape != (3, n) or tets.shape != (4, T) or region.shape != (n,) or \
+                dirichlet.shape != (n,):
+            raise ValueError("mesh arrays have inconsistent shapes")
+        self._keep = (rest, tets, region, dirichlet)
+        mesh = pd_mesh(n, T, rest.ctypes.data, tets.ctypes.data, region.ctypes.data,
+                       dirichlet.ctypes.data, float(mu))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        ctx = C.c_void_p()
+        st = lib.pd_schur_build(C.byref(mesh), C.c_void_p(stream.cuda_stream), C.byref(ctx))
+        if st != PD_OK:
+            raise PDError(st, lib.pd_last_error(None).decode())
+        self._ctx = ctx
+        m, n1, nb, na, nl = (C.c_int64() for _ in range(5))
+        self._chk(lib.pd_query(ctx, C.byref(m), C.byref(n1), C.byref(nb), C.byref(na),
+                               C.byref(nl)))
+        self.n, self.m, self.n1 = n, m.value, n1.value
+        self.n_beta, self.n_alpha, self.n_levels = nb.value, na.value, nl.value
+        ids = np.empty(self.m, dtype=np.int32)
+        self._chk(lib.pd_region_nodes(ctx, ids.ctypes.data))
+        self.region_ids = ids
+
+    def _chk(self, st):
+        if st != PD_OK:
+            raise PDError(st, self._lib.pd_last_error(self._ctx).decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.pd_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- entry points (names as in the C ABI) ------------------------------
+    def get_schur(self, S):
+        import torch
+        self._chk(self._lib.pd_get_schur(self._ctx, _ptr(S, torch.float64, self.m * self.m, "S")))
+
+    def region_gather(self, x, x2):
+        import torch
+        self._chk(self._lib.pd_region_gather(self._ctx, _ptr(x, torch.float64, 3 * self.n, "x"),
+                                             _ptr(x2, torch.float64, 3 * self.m, "x2")))
+
+    def local_step_full(self, x, f, R_alpha=None):
+        import torch
+        self._chk(self._lib.pd_local_step_full(
+            self._ctx, _ptr(x, torch.float64, 3 * self.n, "x"),
+            _ptr(R_alpha, torch.float64, 9 * self.n_alpha, "R_alpha"),
+            _ptr(f, torch.float64, 3 * self.n, "f")))
+
+    def condense_rhs(self, f, y2):
+        import torch
+        self._chk(self._lib.pd_condense_rhs(self._ctx, _ptr(f, torch.float64, 3 * self.n, "f"),
+                                            _ptr(y2, torch.float64, 3 * self.m, "y2")))
+
+    def detect_spheres(self, prox, spheres, k, x2, idx, w, c, t):
+        import torch
+        npx = prox.numel()
+        nsph = spheres.numel() // 4
+        self._chk(self._lib.pd_detect_spheres(
+            self._ctx, npx, _ptr(prox, torch.int32, npx, "prox"), nsph,
+            _ptr(spheres, torch.float64, 4 * nsph, "spheres"), float(k),
+            _ptr(x2, torch.float64, 3 * self.m, "x2"), _ptr(idx, torch.int32, 8 * npx, "idx"),
+            _ptr(w, torch.float64, 8 * npx, "w"), _ptr(c, torch.float64, npx, "c"),
+            _ptr(t, torch.float64, 3 * npx, "t")))
+
+    def collision_update(self, idx, w, c, t, x2, f_col):
+        import torch
+        npen = c.numel()
+        self._chk(self._lib.pd_collision_update(
+            self._ctx, npen, _ptr(idx, torch.int32, 8 * npen, "idx"),
+            _ptr(w, torch.float64, 8 * npen, "w"), _ptr(c, torch.float64, npen, "c"),
+            _ptr(t, torch.float64, 3 * npen, "t"), _ptr(x2, torch.float64, 3 * self.m, "x2"),
+            _ptr(f_col, torch.float64, 3 * self.m, "f_col")))
+
+    def local_step_region(self, x2, f_beta, R_beta=None, rot_fp32=False):
+        import torch
+        rdt = torch.float32 if rot_fp32 else torch.float64
+        self._chk(self._lib.pd_local_step_region(
+            self._ctx, _ptr(x2, torch.float64, 3 * self.m, "x2"),
+            _ptr(R_beta, rdt, 9 * self.n_beta, "R_beta"),
+            _ptr(f_beta, torch.float64, 3 * self.m, "f_beta"), 1 if rot_fp32 else 0))
+
+    def assemble_rhs(self, ft, f_beta, f_col, g):
+        import torch
+        self._chk(self._lib.pd_assemble_rhs(
+            self._ctx, _ptr(ft, torch.float64, 3 * self.m, "ft"),
+            _ptr(f_beta, torch.float64, 3 * self.m, "f_beta"),
+            _ptr(f_col, torch.float64, 3 * self.m, "f_col"), _ptr(g, torch.float64, 3 * self.m, "g")))
+
+    def global_solve(self, g, u, prec=PD_FP64, want_info=False):
+        import torch
+        info = pd_solve_info() if want_info else None
+        st = self._lib.pd_global_solve(self._ctx, _ptr(g, torch.float64, 3 * self.m, "g"),
+                                       _ptr(u, torch.float64, 3 * self.m, "u"), int(prec),
+                                       C.byref(info) if info is not None else None)
+        if info is not None:
+            res = dict(ir_iters=info.ir_iters, bad_pivot=info.bad_pivot,
+                       fell_back=info.fell_back, rel_residual=info.rel_residual, status=st)
+            if st != PD_OK and st != PD_ERR_IR_STALLED:
+                self._chk(st)
+            return res
+        self._chk(st)
+        return None
+
+    def inner_update(self, u2, x2, delta2, ft):
+        import torch
+        self._chk(self._lib.pd_inner_update(
+            self._ctx, _ptr(u2, torch.float64, 3 * self.m, "u2"),
+            _ptr(x2, torch.float64, 3 * self.m, "x2"),
+            _ptr(delta2, torch.float64, 3 * self.m, "delta2"),
+            _ptr(ft, torch.float64, 3 * self.m, "ft")))
+
+    def backsub(self, delta2, x):
+        import torch
+        self._chk(self._lib.pd_backsub(self._ctx, _ptr(delta2, torch.float64, 3 * self.m, "delta2"),
+                                       _ptr(x, torch.float64, 3 * self.n, "x")))

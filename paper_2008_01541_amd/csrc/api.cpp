@@ -1,0 +1,871 @@
+// Host side of the C ABI: validation, partition, breadth-first interior levels,
+// assembly plans, the level-by-level elimination that produces the Schur
+// complement, and the per-iteration entry points.  All arithmetic on mesh
+// data runs in the HIP kernels; the host only builds integer index structures.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/pdschur.h"
+#include "common.h"
+
+using namespace pdk;
+
+namespace {
+
+struct DevAlloc {
+  std::vector<void*> ptrs;
+  ~DevAlloc() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct pd_ctx {
+  hipStream_t st = nullptr;
+  std::string err;
+  bool broken = false;
+
+  int64_t n = 0, T = 0, m = 0, n1 = 0, nbeta = 0, nalpha = 0;
+  int K = 0;
+  double mu = 0.0;
+
+  std::vector<int32_t> region_ids;   // global ids of x2, ascending
+  std::vector<int64_t> lev_off;      // [K+1] offsets into the interior ordering
+  std::vector<int64_t> lev_mat_off;  // [K] offsets (doubles) of Z_k in levmat
+  std::vector<int64_t> B_ptr_off, B_nnz_off, Bt_ptr_off, Bt_nnz_off, Brows_off, Brows_cnt;
+  int64_t maxw = 0;
+  int ntm = 0;                        // tiles of the m x m system
+
+  DevAlloc mem;
+  // mesh subsets
+  int32_t* d_tets_alpha = nullptr;   // [4][nalpha] global ids
+  double* d_Bm_alpha = nullptr;      // [9][nalpha]
+  double* d_vol_alpha = nullptr;
+  int32_t* d_tets_beta = nullptr;    // [4][nbeta] region-local ids
+  double* d_Bm_beta = nullptr;
+  double* d_vol_beta = nullptr;
+  double* d_fe = nullptr;            // [12][max(nalpha, nbeta)]
+  int32_t *d_inc_a_ptr = nullptr, *d_inc_a = nullptr;
+  int32_t *d_inc_b_ptr = nullptr, *d_inc_b = nullptr;
+  int32_t* d_region_ids = nullptr;
+  int32_t* d_lev_nodes = nullptr;    // [n1] global ids in level order
+  double* d_levmat = nullptr;        // Z_k = S_k^-1, full symmetric, per level
+  int32_t *d_Bptr = nullptr, *d_Bcol = nullptr, *d_Btptr = nullptr, *d_Btcol = nullptr;
+  double *d_Bval = nullptr, *d_Btval = nullptr;
+  int32_t* d_Brows = nullptr;
+  int32_t *d_Abptr = nullptr, *d_Abcol = nullptr;
+  double* d_Abval = nullptr;
+  // dense system
+  double* d_S = nullptr;
+  double* d_H = nullptr;
+  double* d_linv = nullptr;
+  double* d_y = nullptr;
+  double* d_res = nullptr;
+  double* d_norms = nullptr;
+  int* d_info = nullptr;
+  int* d_err = nullptr;
+  unsigned long long* d_ticket = nullptr;
+  int* d_flags = nullptr;
+  // sweeps
+  double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
+  bool have_condense = false;
+  // penalties
+  int32_t n_pen = 0, pen_cap = 0;
+  int32_t* d_pidx = nullptr;
+  double *d_pw = nullptr, *d_pc = nullptr, *d_pt = nullptr;
+  bool stale = true;
+
+  pd_status fail(pd_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    err = buf;
+    if (s == PD_ERR_HIP) broken = true;
+    return s;
+  }
+  template <typename TT>
+  pd_status alloc(TT** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void**)p, count * sizeof(TT)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(PD_ERR_OOM, "device allocation of %zu bytes failed", count * sizeof(TT));
+    }
+    mem.ptrs.push_back((void*)*p);
+    return PD_OK;
+  }
+  template <typename TT>
+  pd_status upload(TT** p, const std::vector<TT>& h) {
+    pd_status s = alloc(p, h.size());
+    if (s != PD_OK) return s;
+    if (!h.empty() && hipMemcpy(*p, h.data(), h.size() * sizeof(TT), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(PD_ERR_HIP, "host-to-device copy failed");
+    return PD_OK;
+  }
+  pd_status check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return PD_OK;
+  }
+};
+
+#define CK(expr)                             \
+  do {                                       \
+    pd_status _s = (expr);                   \
+    if (_s != PD_OK) return _s;              \
+  } while (0)
+
+#define HIPCK(ctx, expr)                                                                 \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess) return (ctx)->fail(PD_ERR_HIP, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+namespace {
+
+// Gather plan: dst[dst_off[i]] = sum of vals[src[e]] for e in [ptr[i], ptr[i+1]).
+struct Plan {
+  std::vector<int64_t> ptr{0}, src, dst;
+  void add_group(const int64_t* s, int64_t cnt, int64_t d) {
+    for (int64_t i = 0; i < cnt; ++i) src.push_back(s[i]);
+    ptr.push_back((int64_t)src.size());
+    dst.push_back(d);
+  }
+};
+
+pd_status run_plan(pd_ctx* c, const Plan& P, const double* vals, double* dst) {
+  if (P.dst.empty()) return PD_OK;
+  int64_t *dp, *ds, *dd;
+  CK(c->upload(&dp, P.ptr));
+  CK(c->upload(&ds, P.src));
+  CK(c->upload(&dd, P.dst));
+  gather_assign((int64_t)P.dst.size(), dp, ds, vals, dd, dst, c->st);
+  CK(c->check("gather_assign"));
+  HIPCK(c, hipStreamSynchronize(c->st));
+  // free the plan right away (it can be large)
+  for (void* p : {(void*)dp, (void*)ds, (void*)dd}) {
+    auto it = std::find(c->mem.ptrs.begin(), c->mem.ptrs.end(), p);
+    if (it != c->mem.ptrs.end()) c->mem.ptrs.erase(it);
+    (void)hipFree(p);
+  }
+  return PD_OK;
+}
+
+void free_now(pd_ctx* c, void* p) {
+  auto it = std::find(c->mem.ptrs.begin(), c->mem.ptrs.end(), p);
+  if (it != c->mem.ptrs.end()) c->mem.ptrs.erase(it);
+  (void)hipFree(p);
+}
+
+struct CSRBuild {
+  std::vector<int32_t> ptr, col;
+  std::vector<int64_t> plan_idx;  // position in the plan for each entry
+};
+
+pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
+  const int64_t n = M->n_nodes, T = M->n_tets;
+  c->n = n;
+  c->T = T;
+  c->mu = M->mu;
+  const int32_t* tets = M->tets;
+  // ---- validation
+  for (int64_t i = 0; i < 4 * T; ++i)
+    if (tets[i] < 0 || tets[i] >= n) return c->fail(PD_ERR_INVALID, "tet vertex id out of range");
+  for (int64_t e = 0; e < T; ++e)
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b)
+        if (tets[a * T + e] == tets[b * T + e])
+          return c->fail(PD_ERR_INVALID, "tet %lld repeats a vertex", (long long)e);
+  if (!(M->mu > 0.0) || !std::isfinite(M->mu)) return c->fail(PD_ERR_INVALID, "mu must be positive");
+
+  // ---- partition (Sec. 4.2): x2 = region & free, x1 = other free nodes
+  std::vector<int8_t> cls(n);   // 0 dirichlet, 1 interior (x1), 2 region (x2)
+  for (int64_t i = 0; i < n; ++i)
+    cls[i] = M->dirichlet[i] ? 0 : (M->region[i] ? 2 : 1);
+  for (int64_t i = 0; i < n; ++i)
+    if (cls[i] == 2) c->region_ids.push_back((int32_t)i);
+  c->m = (int64_t)c->region_ids.size();
+  if (c->m == 0) return c->fail(PD_ERR_INVALID, "the collision-prone region has no free node");
+  std::vector<int32_t> rloc(n, -1);
+  for (int64_t r = 0; r < c->m; ++r) rloc[c->region_ids[r]] = (int32_t)r;
+
+  // E_beta = tets with all four vertices in x2 (Sec. 4.5), E_alpha = the rest
+  std::vector<int32_t> alpha, beta;
+  for (int64_t e = 0; e < T; ++e) {
+    bool all2 = true;
+    for (int a = 0; a < 4; ++a) all2 = all2 && cls[tets[a * T + e]] == 2;
+    (all2 ? beta : alpha).push_back((int32_t)e);
+  }
+  c->nalpha = (int64_t)alpha.size();
+  c->nbeta = (int64_t)beta.size();
+
+  // ---- free-node adjacency and breadth-first levels of x1 from x2
+  std::vector<int64_t> adj_ptr(n + 1, 0);
+  {
+    std::vector<std::pair<int32_t, int32_t>> pairs;
+    pairs.reserve((size_t)T * 12);
+    for (int64_t e = 0; e < T; ++e)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+          if (a == b) continue;
+          const int32_t u = tets[a * T + e], v = tets[b * T + e];
+          if (cls[u] != 0 && cls[v] != 0) pairs.emplace_back(u, v);
+        }
+    std::sort(pairs.begin(), pairs.end());
+    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+    std::vector<int32_t> adj(pairs.size());
+    for (size_t i = 0; i < pairs.size(); ++i) {
+      adj_ptr[pairs[i].first + 1]++;
+      adj[i] = pairs[i].second;
+    }
+    for (int64_t i = 0; i < n; ++i) adj_ptr[i + 1] += adj_ptr[i];
+    std::vector<int32_t> dist(n, -1), frontier, next;
+    for (int32_t r : c->region_ids) {
+      for (int64_t k = adj_ptr[r]; k < adj_ptr[r + 1]; ++k) {
+        const int32_t v = adj[k];
+        if (cls[v] == 1 && dist[v] < 0) {
+          dist[v] = 1;
+          frontier.push_back(v);
+        }
+      }
+    }
+    int dmax = frontier.empty() ? 0 : 1;
+    while (!frontier.empty()) {
+      next.clear();
+      for (int32_t u : frontier)
+        for (int64_t k = adj_ptr[u]; k < adj_ptr[u + 1]; ++k) {
+          const int32_t v = adj[k];
+          if (cls[v] == 1 && dist[v] < 0) {
+            dist[v] = dist[u] + 1;
+            next.push_back(v);
+          }
+        }
+      if (!next.empty()) dmax = dist[next[0]];
+      frontier.swap(next);
+    }
+    // level index: unreachable interior nodes first (level 0, no coupling),
+    // then distance dmax .. 1 (far to near)
+    bool any_unreach = false;
+    for (int64_t i = 0; i < n; ++i)
+      if (cls[i] == 1 && dist[i] < 0) any_unreach = true;
+    const int base = any_unreach ? 1 : 0;
+    c->K = base + dmax;
+    std::vector<std::vector<int32_t>> levels(c->K);
+    for (int64_t i = 0; i < n; ++i) {
+      if (cls[i] != 1) continue;
+      const int lv = dist[i] < 0 ? 0 : base + (dmax - dist[i]);
+      levels[lv].push_back((int32_t)i);
+    }
+    c->lev_off.assign(c->K + 1, 0);
+    std::vector<int32_t> lev_nodes;
+    for (int k = 0; k < c->K; ++k) {
+      c->lev_off[k + 1] = c->lev_off[k] + (int64_t)levels[k].size();
+      lev_nodes.insert(lev_nodes.end(), levels[k].begin(), levels[k].end());
+      c->maxw = std::max<int64_t>(c->maxw, (int64_t)levels[k].size());
+    }
+    c->n1 = c->lev_off[c->K];
+    CK(c->upload(&c->d_lev_nodes, lev_nodes));
+  }
+  const int K = c->K;
+  const int64_t m = c->m;
+  // level id and local index of every free node; region = level K
+  std::vector<int32_t> lvl(n, -1), loc(n, -1);
+  {
+    std::vector<int32_t> h(c->n1);
+    HIPCK(c, hipMemcpy(h.data(), c->d_lev_nodes, c->n1 * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int k = 0; k < K; ++k)
+      for (int64_t p = c->lev_off[k]; p < c->lev_off[k + 1]; ++p) {
+        lvl[h[p]] = k;
+        loc[h[p]] = (int32_t)(p - c->lev_off[k]);
+      }
+    for (int64_t r = 0; r < m; ++r) {
+      lvl[c->region_ids[r]] = K;
+      loc[c->region_ids[r]] = (int32_t)r;
+    }
+  }
+  auto width = [&](int k) -> int64_t { return k == K ? m : c->lev_off[k + 1] - c->lev_off[k]; };
+  for (int64_t w = 0; w < 1; ++w) {}
+  if (c->maxw > 46340 || m > 46340) return c->fail(PD_ERR_INVALID, "dense block too large");
+
+  // ---- element geometry and stiffness on the GPU
+  double *d_rest, *d_Bm, *d_vol, *d_Ke;
+  int32_t* d_tets;
+  {
+    std::vector<double> rest(M->rest, M->rest + 3 * n);
+    std::vector<int32_t> tv(tets, tets + 4 * T);
+    CK(c->upload(&d_rest, rest));
+    CK(c->upload(&d_tets, tv));
+  }
+  CK(c->alloc(&d_Bm, 9 * T));
+  CK(c->alloc(&d_vol, T));
+  CK(c->alloc(&d_Ke, 16 * T));
+  tet_geometry(d_rest, n, d_tets, T, d_Bm, d_vol, c->st);
+  element_stiffness(d_Bm, d_vol, T, c->mu, d_Ke, c->st);
+  CK(c->check("geometry"));
+  {
+    std::vector<double> vol(T);
+    HIPCK(c, hipMemcpyAsync(vol.data(), d_vol, T * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCK(c, hipStreamSynchronize(c->st));
+    for (int64_t e = 0; e < T; ++e)
+      if (!(vol[e] > 0.0))
+        return c->fail(PD_ERR_INVALID, "tet %lld has non-positive rest volume", (long long)e);
+  }
+
+  // ---- assembly plans: every K entry between free nodes, grouped by (row, col)
+  // in the level ordering, with its element-matrix contributions in fixed order.
+  struct Contrib {
+    int32_t lr, lc;   // level of row / col node
+    int32_t r, cc;    // local indices
+    int64_t src;
+  };
+  int64_t lev_mat_total = 0;
+  c->lev_mat_off.assign(K, 0);
+  for (int k = 0; k < K; ++k) {
+    c->lev_mat_off[k] = lev_mat_total;
+    lev_mat_total += width(k) * width(k);
+  }
+  CK(c->alloc(&c->d_levmat, lev_mat_total));
+  CK(c->alloc(&c->d_S, m * m));
+  HIPCK(c, hipMemsetAsync(c->d_levmat, 0, lev_mat_total * sizeof(double), c->st));
+  HIPCK(c, hipMemsetAsync(c->d_S, 0, m * m * sizeof(double), c->st));
+  {
+    // node-major bucketing of contributions
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t e = 0; e < T; ++e)
+      for (int a = 0; a < 4; ++a) {
+        const int32_t u = tets[a * T + e];
+        if (cls[u] == 0) continue;
+        for (int b = 0; b < 4; ++b)
+          if (cls[tets[b * T + e]] != 0) cnt[u + 1]++;
+      }
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<std::pair<int32_t, int64_t>> ent(cnt[n]);   // (col node, src)
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t e = 0; e < T; ++e)
+      for (int a = 0; a < 4; ++a) {
+        const int32_t u = tets[a * T + e];
+        if (cls[u] == 0) continue;
+        for (int b = 0; b < 4; ++b) {
+          const int32_t v = tets[b * T + e];
+          if (cls[v] != 0) ent[pos[u]++] = {v, (int64_t)(a * 4 + b) * T + e};
+        }
+      }
+    Plan pl_lev, pl_S, pl_B, pl_Bt;
+    // CSR structures of B_k (rows level k+1 -> cols level k) and B_k^T
+    std::vector<std::vector<int32_t>> Bptr(K), Bcol(K), Btptr(K), Btcol(K);
+    for (int k = 0; k < K; ++k) {
+      Bptr[k].assign(width(k + 1) + 1, 0);
+      Btptr[k].assign(width(k) + 1, 0);
+    }
+    // process rows in level order so CSR rows fill sequentially
+    std::vector<int32_t> row_nodes;
+    {
+      std::vector<int32_t> h(c->n1);
+      HIPCK(c, hipMemcpy(h.data(), c->d_lev_nodes, c->n1 * sizeof(int32_t), hipMemcpyDeviceToHost));
+      row_nodes = h;
+      row_nodes.insert(row_nodes.end(), c->region_ids.begin(), c->region_ids.end());
+    }
+    std::vector<int64_t> Bval_plan_pos, Btval_plan_pos;
+    std::vector<std::vector<int64_t>> Bsrc_groups;  // not used
+    for (int32_t u : row_nodes) {
+      auto b = ent.begin() + cnt[u], e = ent.begin() + cnt[u + 1];
+      // sort by (level, local col, src) for a fixed, ordered layout
+      std::sort(b, e, [&](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
+        if (lvl[x.first] != lvl[y.first]) return lvl[x.first] < lvl[y.first];
+        if (loc[x.first] != loc[y.first]) return loc[x.first] < loc[y.first];
+        return x.second < y.second;
+      });
+      const int lu = lvl[u];
+      const int64_t ru = loc[u];
+      for (auto it = b; it != e;) {
+        auto jt = it;
+        std::vector<int64_t> srcs;
+        while (jt != e && jt->first == it->first) srcs.push_back((jt++)->second);
+        const int32_t v = it->first;
+        const int lv = lvl[v];
+        const int64_t cv = loc[v];
+        if (lv == lu) {
+          if (lu == K) pl_S.add_group(srcs.data(), (int64_t)srcs.size(), ru + cv * m);
+          else pl_lev.add_group(srcs.data(), (int64_t)srcs.size(),
+                                c->lev_mat_off[lu] + ru + cv * width(lu));
+        } else if (lv == lu - 1) {   // row in level k+1, col in level k: B_k
+          const int k = lv;
+          Bcol[k].push_back((int32_t)cv);
+          Bptr[k][ru + 1]++;
+          pl_B.add_group(srcs.data(), (int64_t)srcs.size(), -1 - k);  // fixed up below
+        } else if (lv == lu + 1) {   // row in level k, col in level k+1: B_k^T
+          const int k = lu;
+          Btcol[k].push_back((int32_t)cv);
+          Btptr[k][ru + 1]++;
+          pl_Bt.add_group(srcs.data(), (int64_t)srcs.size(), -1 - k);
+        } else {
+          return c->fail(PD_ERR_INVALID, "internal: coupling across non-adjacent levels");
+        }
+        it = jt;
+      }
+    }
+    // CSR offsets and plan destinations (entries were appended in row order per level)
+    c->B_ptr_off.assign(K + 1, 0);
+    c->B_nnz_off.assign(K + 1, 0);
+    c->Bt_ptr_off.assign(K + 1, 0);
+    c->Bt_nnz_off.assign(K + 1, 0);
+    std::vector<int32_t> allBptr, allBcol, allBtptr, allBtcol;
+    for (int k = 0; k < K; ++k) {
+      for (size_t i = 1; i < Bptr[k].size(); ++i) Bptr[k][i] += Bptr[k][i - 1];
+      for (size_t i = 1; i < Btptr[k].size(); ++i) Btptr[k][i] += Btptr[k][i - 1];
+      c->B_ptr_off[k + 1] = c->B_ptr_off[k] + (int64_t)Bptr[k].size();
+      c->B_nnz_off[k + 1] = c->B_nnz_off[k] + (int64_t)Bcol[k].size();
+      c->Bt_ptr_off[k + 1] = c->Bt_ptr_off[k] + (int64_t)Btptr[k].size();
+      c->Bt_nnz_off[k + 1] = c->Bt_nnz_off[k] + (int64_t)Btcol[k].size();
+      allBptr.insert(allBptr.end(), Bptr[k].begin(), Bptr[k].end());
+      allBcol.insert(allBcol.end(), Bcol[k].begin(), Bcol[k].end());
+      allBtptr.insert(allBtptr.end(), Btptr[k].begin(), Btptr[k].end());
+      allBtcol.insert(allBtcol.end(), Btcol[k].begin(), Btcol[k].end());
+    }
+    // destinations: entries of B_k appear in the plan in level-major row order,
+    // exactly the CSR order, so the j-th entry of level k goes to nnz_off[k] + j.
+    {
+      std::vector<int64_t> next(K, 0);
+      for (auto& d : pl_B.dst) {
+        const int k = -1 - (int)d;
+        d = c->B_nnz_off[k] + next[k]++;
+      }
+      std::fill(next.begin(), next.end(), 0);
+      for (auto& d : pl_Bt.dst) {
+        const int k = -1 - (int)d;
+        d = c->Bt_nnz_off[k] + next[k]++;
+      }
+    }
+    // nonempty rows of each B_k (the rows that receive the elimination update)
+    std::vector<int32_t> brows;
+    c->Brows_off.assign(K + 1, 0);
+    c->Brows_cnt.assign(K, 0);
+    for (int k = 0; k < K; ++k) {
+      c->Brows_off[k] = (int64_t)brows.size();
+      for (int64_t r = 0; r + 1 < (int64_t)Bptr[k].size(); ++r)
+        if (Bptr[k][r + 1] > Bptr[k][r]) brows.push_back((int32_t)r);
+      c->Brows_cnt[k] = (int64_t)brows.size() - c->Brows_off[k];
+    }
+    c->Brows_off[K] = (int64_t)brows.size();
+    CK(c->upload(&c->d_Bptr, allBptr));
+    CK(c->upload(&c->d_Bcol, allBcol));
+    CK(c->upload(&c->d_Btptr, allBtptr));
+    CK(c->upload(&c->d_Btcol, allBtcol));
+    CK(c->upload(&c->d_Brows, brows));
+    CK(c->alloc(&c->d_Bval, std::max<int64_t>(1, c->B_nnz_off[K])));
+    CK(c->alloc(&c->d_Btval, std::max<int64_t>(1, c->Bt_nnz_off[K])));
+    CK(run_plan(c, pl_lev, d_Ke, c->d_levmat));
+    CK(run_plan(c, pl_S, d_Ke, c->d_S));
+    CK(run_plan(c, pl_B, d_Ke, c->d_Bval));
+    CK(run_plan(c, pl_Bt, d_Ke, c->d_Btval));
+  }
+
+  // ---- A22^(beta): region-local CSR assembled from the E_beta tets only
+  {
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> rows(m);
+    for (int32_t e : beta)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+          rows[rloc[tets[a * T + e]]].push_back({rloc[tets[b * T + e]], (int64_t)(a * 4 + b) * T + e});
+    Plan pl;
+    std::vector<int32_t> ptr(m + 1, 0), col;
+    for (int64_t r = 0; r < m; ++r) {
+      auto& R = rows[r];
+      std::sort(R.begin(), R.end());
+      for (size_t i = 0; i < R.size();) {
+        size_t j = i;
+        std::vector<int64_t> srcs;
+        while (j < R.size() && R[j].first == R[i].first) srcs.push_back(R[j++].second);
+        pl.add_group(srcs.data(), (int64_t)srcs.size(), (int64_t)col.size());
+        col.push_back(R[i].first);
+        i = j;
+      }
+      ptr[r + 1] = (int32_t)col.size();
+    }
+    CK(c->upload(&c->d_Abptr, ptr));
+    CK(c->upload(&c->d_Abcol, col));
+    CK(c->alloc(&c->d_Abval, std::max<size_t>(1, col.size())));
+    CK(run_plan(c, pl, d_Ke, c->d_Abval));
+  }
+
+  // ---- level-by-level elimination of x1 (one-way dissection in BFS levels):
+  //   S_0 = D_0;  Z_k = S_k^-1;  S_{k+1} = D_{k+1} - B_k Z_k B_k^T;  S = S_K.
+  c->ntm = (int)((m + NB - 1) / NB);
+  const int64_t ntmax = (std::max<int64_t>(c->maxw, m) + NB - 1) / NB;
+  CK(c->alloc(&c->d_linv, ntmax * NB * NB));
+  CK(c->alloc(&c->d_info, 1));
+  CK(c->alloc(&c->d_err, 1));
+  CK(c->alloc(&c->d_ticket, 4));
+  CK(c->alloc(&c->d_flags, 4 * (int64_t)c->ntm));
+  HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
+  HIPCK(c, hipMemsetAsync(c->d_err, 0, sizeof(int), c->st));
+  HIPCK(c, hipMemsetAsync(c->d_ticket, 0, 4 * sizeof(unsigned long long), c->st));
+  HIPCK(c, hipMemsetAsync(c->d_flags, 0, 4 * (int64_t)c->ntm * sizeof(int), c->st));
+  if (K > 0) {
+    double *d_M, *d_X, *d_U;
+    int64_t maxrows = 0;
+    for (int k = 0; k < K; ++k) maxrows = std::max(maxrows, c->Brows_cnt[k]);
+    CK(c->alloc(&d_M, c->maxw * c->maxw));
+    CK(c->alloc(&d_X, c->maxw * c->maxw));
+    CK(c->alloc(&d_U, c->maxw * std::max<int64_t>(1, maxrows)));
+    for (int k = 0; k < K; ++k) {
+      const int w = (int)width(k);
+      double* A = c->d_levmat + c->lev_mat_off[k];
+      potrf_tiled(A, w, w, c->d_linv, c->d_info, c->st);
+      trtri_from_factor(A, w, w, c->d_linv, d_M, d_X, w, c->st);
+      HIPCK(c, hipMemsetAsync(A, 0, (size_t)w * w * sizeof(double), c->st));
+      lauum_full(d_X, w, w, A, w, c->st);
+      HIPCK(c, hipMemsetAsync(d_X, 0, (size_t)w * w * sizeof(double), c->st));
+      double* Nx = (k + 1 < K) ? c->d_levmat + c->lev_mat_off[k + 1] : c->d_S;
+      const int ldn = (int)width(k + 1);
+      const int nr = (int)c->Brows_cnt[k];
+      const int32_t* rows = c->d_Brows + c->Brows_off[k];
+      const int32_t* bp = c->d_Bptr + c->B_ptr_off[k];
+      const int32_t* bc = c->d_Bcol + c->B_nnz_off[k];
+      const double* bv = c->d_Bval + c->B_nnz_off[k];
+      dense_times_sparse_t(A, w, nr, rows, bp, bc, bv, d_U, c->st);
+      sub_sparse_times_dense(Nx, ldn, nr, rows, bp, bc, bv, d_U, w, c->st);
+      CK(c->check("level elimination"));
+    }
+    HIPCK(c, hipStreamSynchronize(c->st));
+    free_now(c, d_M);
+    free_now(c, d_X);
+    free_now(c, d_U);
+    int info = 0;
+    HIPCK(c, hipMemcpy(&info, c->d_info, sizeof(int), hipMemcpyDeviceToHost));
+    if (info != 0)
+      return c->fail(PD_ERR_NOT_SPD, "interior level block not positive definite (pivot %d)", info);
+  }
+
+  // ---- per-iteration data: E_alpha / E_beta tets, incidence lists, buffers
+  {
+    std::vector<int32_t> ta(4 * c->nalpha), tb_g(4 * c->nbeta), tb(4 * c->nbeta);
+    for (int64_t s = 0; s < c->nalpha; ++s)
+      for (int a = 0; a < 4; ++a) ta[a * c->nalpha + s] = tets[a * T + alpha[s]];
+    for (int64_t s = 0; s < c->nbeta; ++s)
+      for (int a = 0; a < 4; ++a) {
+        tb_g[a * c->nbeta + s] = tets[a * T + beta[s]];
+        tb[a * c->nbeta + s] = rloc[tets[a * T + beta[s]]];
+      }
+    CK(c->upload(&c->d_tets_alpha, ta));
+    CK(c->alloc(&c->d_Bm_alpha, 9 * c->nalpha));
+    CK(c->alloc(&c->d_vol_alpha, c->nalpha));
+    tet_geometry(d_rest, n, c->d_tets_alpha, c->nalpha, c->d_Bm_alpha, c->d_vol_alpha, c->st);
+    int32_t* d_tbg;
+    CK(c->upload(&d_tbg, tb_g));
+    CK(c->alloc(&c->d_Bm_beta, 9 * c->nbeta));
+    CK(c->alloc(&c->d_vol_beta, c->nbeta));
+    tet_geometry(d_rest, n, d_tbg, c->nbeta, c->d_Bm_beta, c->d_vol_beta, c->st);
+    CK(c->upload(&c->d_tets_beta, tb));
+    CK(c->check("subset geometry"));
+    // incidence lists (node -> slot*4 + vertex), ordered by slot then vertex
+    auto incidence = [&](const std::vector<int32_t>& tl, int64_t cnt, int64_t nodes,
+                         std::vector<int32_t>& ptr, std::vector<int32_t>& ent) {
+      ptr.assign(nodes + 1, 0);
+      for (int64_t s = 0; s < cnt; ++s)
+        for (int a = 0; a < 4; ++a) ptr[tl[a * cnt + s] + 1]++;
+      for (int64_t i = 0; i < nodes; ++i) ptr[i + 1] += ptr[i];
+      ent.assign(ptr[nodes], 0);
+      std::vector<int32_t> p(ptr.begin(), ptr.end() - 1);
+      for (int64_t s = 0; s < cnt; ++s)
+        for (int a = 0; a < 4; ++a) ent[p[tl[a * cnt + s]]++] = (int32_t)(s * 4 + a);
+    };
+    std::vector<int32_t> ptr, ent;
+    incidence(ta, c->nalpha, n, ptr, ent);
+    CK(c->upload(&c->d_inc_a_ptr, ptr));
+    CK(c->upload(&c->d_inc_a, ent));
+    incidence(tb, c->nbeta, m, ptr, ent);
+    CK(c->upload(&c->d_inc_b_ptr, ptr));
+    CK(c->upload(&c->d_inc_b, ent));
+    CK(c->upload(&c->d_region_ids, c->region_ids));
+    CK(c->alloc(&c->d_fe, 12 * std::max<int64_t>(1, std::max(c->nalpha, c->nbeta))));
+    HIPCK(c, hipStreamSynchronize(c->st));
+    free_now(c, d_tbg);
+  }
+  free_now(c, d_Ke);
+  free_now(c, d_Bm);
+  free_now(c, d_vol);
+  free_now(c, d_rest);
+  free_now(c, d_tets);
+  CK(c->alloc(&c->d_H, m * m));
+  CK(c->alloc(&c->d_y, 3 * m));
+  CK(c->alloc(&c->d_res, 3 * m));
+  CK(c->alloc(&c->d_norms, 8));
+  CK(c->alloc(&c->d_fhat, 3 * std::max<int64_t>(1, c->n1)));
+  CK(c->alloc(&c->d_v, 3 * std::max<int64_t>(1, c->n1)));
+  CK(c->alloc(&c->d_xs, 3 * std::max<int64_t>(1, c->n1)));
+  CK(c->alloc(&c->d_tmp, 3 * std::max<int64_t>(1, c->maxw)));
+  HIPCK(c, hipStreamSynchronize(c->st));
+  return PD_OK;
+}
+
+pd_status ensure_pen_cap(pd_ctx* c, int32_t n) {
+  if (n <= c->pen_cap) return PD_OK;
+  int32_t cap = std::max<int32_t>(n, 2 * c->pen_cap);
+  for (void* p : {(void*)c->d_pidx, (void*)c->d_pw, (void*)c->d_pc, (void*)c->d_pt})
+    if (p) {
+      HIPCK(c, hipStreamSynchronize(c->st));
+      free_now(c, p);
+    }
+  CK(c->alloc(&c->d_pidx, 8 * (int64_t)cap));
+  CK(c->alloc(&c->d_pw, 8 * (int64_t)cap));
+  CK(c->alloc(&c->d_pc, cap));
+  CK(c->alloc(&c->d_pt, 3 * (int64_t)cap));
+  c->pen_cap = cap;
+  return PD_OK;
+}
+
+bool bad_ctx(const pd_ctx* c) { return c == nullptr; }
+
+thread_local std::string g_build_error;
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+pd_status pd_schur_build(const pd_mesh* mesh, void* hip_stream, pd_ctx** out) {
+  if (!out) return PD_ERR_INVALID;
+  *out = nullptr;
+  if (!mesh || !mesh->rest || !mesh->tets || !mesh->region || !mesh->dirichlet ||
+      mesh->n_nodes <= 0 || mesh->n_tets <= 0 || mesh->n_nodes > INT32_MAX ||
+      mesh->n_tets > (INT32_MAX / 4))
+    return PD_ERR_INVALID;
+  pd_ctx* c = new pd_ctx();
+  c->st = (hipStream_t)hip_stream;
+  pd_status s = build_impl(c, mesh);
+  if (s != PD_OK) {
+    (void)hipStreamSynchronize(c->st);
+    // keep the message reachable through a static copy, then free the context
+    g_build_error = c->err;
+    delete c;
+    return s;
+  }
+  *out = c;
+  return PD_OK;
+}
+
+pd_status pd_query(const pd_ctx* c, int64_t* m, int64_t* n1, int64_t* n_beta, int64_t* n_alpha,
+                   int64_t* n_levels) {
+  if (bad_ctx(c)) return PD_ERR_INVALID;
+  if (m) *m = c->m;
+  if (n1) *n1 = c->n1;
+  if (n_beta) *n_beta = c->nbeta;
+  if (n_alpha) *n_alpha = c->nalpha;
+  if (n_levels) *n_levels = c->K;
+  return PD_OK;
+}
+
+pd_status pd_region_nodes(const pd_ctx* c, int32_t* ids) {
+  if (bad_ctx(c) || !ids) return PD_ERR_INVALID;
+  std::memcpy(ids, c->region_ids.data(), c->m * sizeof(int32_t));
+  return PD_OK;
+}
+
+pd_status pd_get_schur(pd_ctx* c, double* S) {
+  if (bad_ctx(c) || !S) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  HIPCK(c, hipMemcpyAsync(S, c->d_S, c->m * c->m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  return PD_OK;
+}
+
+pd_status pd_region_gather(pd_ctx* c, const double* x, double* x2) {
+  if (bad_ctx(c) || !x || !x2) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  gather_rows3(c->m, c->d_region_ids, x, c->n, x2, c->m, c->st);
+  return c->check("pd_region_gather");
+}
+
+pd_status pd_local_step_full(pd_ctx* c, const double* x, double* R_alpha, double* f) {
+  if (bad_ctx(c) || !x || !f) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  local_step(c->nalpha, c->d_tets_alpha, c->nalpha, c->d_Bm_alpha, c->d_vol_alpha, c->nalpha, x,
+             c->n, c->mu, c->d_fe, R_alpha, 0, c->st);
+  node_gather3(c->n, c->d_inc_a_ptr, c->d_inc_a, c->d_fe, c->nalpha, nullptr, f, c->n, 0, c->st);
+  return c->check("pd_local_step_full");
+}
+
+pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
+  if (bad_ctx(c) || !f || !y2) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  const int64_t n1 = c->n1, m = c->m;
+  gather_rows3(n1, c->d_lev_nodes, f, c->n, c->d_fhat, n1, c->st);
+  gather_rows3(m, c->d_region_ids, f, c->n, y2, m, c->st);
+  for (int k = 0; k < c->K; ++k) {
+    const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
+    symv3(c->d_levmat + c->lev_mat_off[k], (int)w, (int)w, c->d_fhat + off, (int)n1, 1.0, 0.0,
+          c->d_v + off, (int)n1, c->st);
+    const int32_t* bp = c->d_Bptr + c->B_ptr_off[k];
+    const int32_t* bc = c->d_Bcol + c->B_nnz_off[k];
+    const double* bv = c->d_Bval + c->B_nnz_off[k];
+    if (k + 1 < c->K) {
+      const int64_t off2 = c->lev_off[k + 1], w2 = c->lev_off[k + 2] - off2;
+      csr_spmv3(w2, bp, bc, bv, c->d_v + off, n1, -1.0, c->d_fhat + off2, n1, c->d_fhat + off2, n1,
+                c->st);
+    } else {
+      csr_spmv3(m, bp, bc, bv, c->d_v + off, n1, -1.0, y2, m, y2, m, c->st);
+    }
+  }
+  c->have_condense = true;
+  return c->check("pd_condense_rhs");
+}
+
+pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
+  if (bad_ctx(c) || !delta2 || !x) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  if (!c->have_condense) return c->fail(PD_ERR_STATE, "pd_backsub needs a preceding pd_condense_rhs");
+  const int64_t n1 = c->n1, m = c->m;
+  if (n1 > 0) {
+    HIPCK(c, hipMemcpyAsync(c->d_xs, c->d_v, 3 * n1 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    for (int k = c->K - 1; k >= 0; --k) {
+      const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
+      const int32_t* tp = c->d_Btptr + c->Bt_ptr_off[k];
+      const int32_t* tc = c->d_Btcol + c->Bt_nnz_off[k];
+      const double* tv = c->d_Btval + c->Bt_nnz_off[k];
+      const double* xn = (k + 1 < c->K) ? c->d_xs + c->lev_off[k + 1] : delta2;
+      const int64_t ldxn = (k + 1 < c->K) ? n1 : m;
+      csr_spmv3(w, tp, tc, tv, xn, ldxn, 1.0, c->d_tmp, c->maxw, nullptr, 0, c->st);
+      symv3(c->d_levmat + c->lev_mat_off[k], (int)w, (int)w, c->d_tmp, (int)c->maxw, -1.0, 1.0,
+            c->d_xs + off, (int)n1, c->st);
+    }
+    scatter_add_rows3(n1, c->d_lev_nodes, c->d_xs, n1, x, c->n, c->st);
+  }
+  scatter_add_rows3(m, c->d_region_ids, delta2, m, x, c->n, c->st);
+  return c->check("pd_backsub");
+}
+
+pd_status pd_detect_spheres(pd_ctx* c, int32_t n_prox, const int32_t* prox, int32_t n_sph,
+                            const double* spheres, double k, const double* x2, int32_t* idx,
+                            double* w, double* cc, double* t) {
+  if (bad_ctx(c) || n_prox < 0 || n_sph < 0 || (n_prox > 0 && (!prox || !x2 || !idx || !w || !cc || !t)) ||
+      (n_sph > 0 && !spheres) || !(k >= 0.0))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  detect_spheres(n_prox, prox, n_sph, spheres, k, x2, (int)c->m, idx, w, cc, t, c->st);
+  return c->check("pd_detect_spheres");
+}
+
+pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, const double* w,
+                              const double* cc, const double* t, const double* x2, double* f_col) {
+  if (bad_ctx(c) || n_pen < 0 || !x2 || !f_col || (n_pen > 0 && (!idx || !w || !cc || !t)))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  CK(ensure_pen_cap(c, std::max<int32_t>(n_pen, 1)));
+  if (n_pen > 0) {
+    HIPCK(c, hipMemcpyAsync(c->d_pidx, idx, 8 * (size_t)n_pen * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st));
+    HIPCK(c, hipMemcpyAsync(c->d_pw, w, 8 * (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    HIPCK(c, hipMemcpyAsync(c->d_pc, cc, (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    HIPCK(c, hipMemcpyAsync(c->d_pt, t, 3 * (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  }
+  c->n_pen = n_pen;
+  penalty_apply(n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 1.0, x2, (int)c->m, nullptr, 0, f_col,
+                c->st);
+  c->stale = true;
+  return c->check("pd_collision_update");
+}
+
+pd_status pd_local_step_region(pd_ctx* c, const double* x2, void* R_beta, double* f_beta,
+                               int rot_fp32) {
+  if (bad_ctx(c) || !x2 || !f_beta) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  if (c->nbeta == 0) {
+    HIPCK(c, hipMemsetAsync(f_beta, 0, 3 * c->m * sizeof(double), c->st));
+    return PD_OK;
+  }
+  local_step(c->nbeta, c->d_tets_beta, c->nbeta, c->d_Bm_beta, c->d_vol_beta, c->nbeta, x2, c->m,
+             c->mu, c->d_fe, R_beta, rot_fp32 ? 1 : 0, c->st);
+  node_gather3(c->m, c->d_inc_b_ptr, c->d_inc_b, c->d_fe, c->nbeta, nullptr, f_beta, c->m, 0, c->st);
+  return c->check("pd_local_step_region");
+}
+
+pd_status pd_assemble_rhs(pd_ctx* c, const double* ft, const double* f_beta, const double* f_col,
+                          double* g) {
+  if (bad_ctx(c) || !ft || !g) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  axpy3_sum((int)c->m, ft, f_beta, f_col, g, c->st);
+  return c->check("pd_assemble_rhs");
+}
+
+pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision prec,
+                          pd_solve_info* info) {
+  if (bad_ctx(c) || !g || !u) return PD_ERR_INVALID;
+  if (prec != PD_FP64) return c->fail(PD_ERR_INVALID, "precision mode not available");
+  if (c->broken) return PD_ERR_HIP;
+  const int m = (int)c->m;
+  if (c->stale) {
+    copy_lower_tiles(c->d_S, m, c->d_H, m, m, c->st);
+    if (c->n_pen > 0)
+      penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, nullptr, m, c->d_H, m,
+                    nullptr, c->st);
+    HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
+    potrf_tiled(c->d_H, m, m, c->d_linv, c->d_info, c->st);
+    c->stale = false;
+  }
+  trsv3_forward(c->d_H, m, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags, c->d_err, c->st);
+  trsv3_backward(c->d_H, m, m, c->d_linv, c->d_y, m, u, m, c->d_ticket + 1, c->d_flags + c->ntm,
+                 c->d_err, c->st);
+  CK(c->check("pd_global_solve"));
+  int hinfo = 0, herr = 0;
+  if (info) {
+    // residual r = g - S u - P u in FP64
+    HIPCK(c, hipMemcpyAsync(c->d_res, g, 3 * (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    symv3(c->d_S, m, m, u, m, -1.0, 1.0, c->d_res, m, c->st);
+    if (c->n_pen > 0) {
+      penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, u, m, nullptr, 0, c->d_y,
+                    c->st);
+      axpy3_sum(m, c->d_res, c->d_y, nullptr, c->d_res, c->st);
+    }
+    colnorm2_3(m, c->d_res, c->d_norms, c->st);
+    colnorm2_3(m, g, c->d_norms + 3, c->st);
+    double nrm[6];
+    HIPCK(c, hipMemcpyAsync(nrm, c->d_norms, 6 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCK(c, hipMemcpyAsync(&hinfo, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCK(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCK(c, hipStreamSynchronize(c->st));
+    double rr = 0.0;
+    for (int v = 0; v < 3; ++v)
+      if (nrm[3 + v] > 0) rr = std::max(rr, std::sqrt(nrm[v] / nrm[3 + v]));
+    info->ir_iters = 0;
+    info->bad_pivot = hinfo;
+    info->fell_back = 0;
+    info->reserved = 0;
+    info->rel_residual = rr;
+    if (herr) return c->fail(PD_ERR_HIP, "triangular solve dependency wait timed out");
+    if (hinfo) return c->fail(PD_ERR_NOT_SPD, "non-positive pivot at %d", hinfo);
+  }
+  return PD_OK;
+}
+
+pd_status pd_inner_update(pd_ctx* c, const double* u2, double* x2, double* delta2, double* ft) {
+  if (bad_ctx(c) || !u2 || !x2 || !delta2 || !ft) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  const int m = (int)c->m;
+  inner_update(m, u2, x2, delta2, c->st);
+  symv3(c->d_S, m, m, u2, m, -1.0, 1.0, ft, m, c->st);
+  if (c->nbeta > 0) csr_spmv3(m, c->d_Abptr, c->d_Abcol, c->d_Abval, u2, m, 1.0, ft, m, ft, m, c->st);
+  return c->check("pd_inner_update");
+}
+
+const char* pd_last_error(const pd_ctx* c) {
+  if (!c) return g_build_error.c_str();
+  return c->err.c_str();
+}
+
+pd_status pd_destroy(pd_ctx* c) {
+  if (!c) return PD_ERR_INVALID;
+  (void)hipStreamSynchronize(c->st);
+  delete c;
+  return PD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal definitions shared by the HIP kernels and the host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdk {
+
+// Dense tiles are NB x NB doubles, column-major; matrices are lower triangular
+// where it matters (Cholesky factors), or full symmetric.
+constexpr int NB = 64;
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// ---- launchers (all asynchronous on `st`) --------------------------------
+
+// dense FP64
+void copy_lower_tiles(const double* S, int lds, double* H, int ldh, int n, hipStream_t st);
+void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStream_t st);
+void trtri_from_factor(const double* L, int ldl, int n, const double* linv_ws, double* M,
+                       double* X, int ldx, hipStream_t st);
+void lauum_full(const double* X, int ldx, int n, double* Z, int ldz, hipStream_t st);
+void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const double* g,
+                   int ldg, double* y, int ldy, unsigned long long* ticket, int* flags,
+                   int* err, hipStream_t st);
+void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
+                    int ldy, double* x, int ldx, unsigned long long* ticket, int* flags,
+                    int* err, hipStream_t st);
+// y = alpha * A v + beta * y for symmetric A (full storage), 3 right-hand sides.
+void symv3(const double* A, int lda, int n, const double* v, int ldv, double alpha,
+           double beta, double* y, int ldy, hipStream_t st);
+
+// FEM / sparse
+void tet_geometry(const double* rest, int64_t n, const int32_t* tets, int64_t T,
+                  double* Bm, double* vol, hipStream_t st);
+void element_stiffness(const double* Bm, const double* vol, int64_t T, double mu,
+                       double* Ke, hipStream_t st);
+void gather_assign(int64_t count, const int64_t* ptr, const int64_t* src, const double* vals,
+                   const int64_t* dst_off, double* dst, hipStream_t st);
+void local_step(int64_t T, const int32_t* tets, int64_t ldt, const double* Bm,
+                const double* vol, int64_t ldb, const double* x, int64_t ldx, double mu,
+                double* fe, void* R, int rot_fp32, hipStream_t st);
+void node_gather3(int64_t count, const int32_t* ptr, const int32_t* ent, const double* fe,
+                  int64_t ldfe, const int32_t* node_of_row, double* f, int64_t ldf,
+                  int accumulate, hipStream_t st);
+void gather_rows3(int64_t count, const int32_t* ids, const double* src, int64_t lds,
+                  double* dst, int64_t ldd, hipStream_t st);
+void scatter_add_rows3(int64_t count, const int32_t* ids, const double* src, int64_t lds,
+                       double* dst, int64_t ldd, hipStream_t st);
+void csr_spmv3(int64_t rows, const int32_t* ptr, const int32_t* col, const double* val,
+               const double* v, int64_t ldv, double alpha, double* y, int64_t ldy,
+               const double* base, int64_t ldbase, hipStream_t st);
+void dense_times_sparse_t(const double* Z, int w, int nr, const int32_t* rows,
+                          const int32_t* ptr, const int32_t* col, const double* val,
+                          double* U, hipStream_t st);
+void sub_sparse_times_dense(double* Next, int ldn, int nr, const int32_t* rows,
+                            const int32_t* ptr, const int32_t* col, const double* val,
+                            const double* U, int ldu, hipStream_t st);
+void detect_spheres(int n_prox, const int32_t* prox, int n_sph, const double* sph, double k,
+                    const double* x2, int m, int32_t* idx, double* w, double* c, double* t,
+                    hipStream_t st);
+// Row a of H (lower part) += (W^T C W)[a, :]  when H != NULL;
+// fcol[:, a] = -(W^T C (W x2 - tscale * t))[a]  when fcol != NULL.
+void penalty_apply(int n_pen, const int32_t* idx, const double* w, const double* c,
+                   const double* t, double tscale, const double* x2, int m, double* H,
+                   int ldh, double* fcol, hipStream_t st);
+// out[v] = sum_i a[v][i]^2 for the three columns (out: 3 doubles, device).
+void colnorm2_3(int m, const double* a, double* out, hipStream_t st);
+void axpy3_sum(int m, const double* a, const double* b, const double* c, double* out,
+               hipStream_t st);
+void inner_update(int m, const double* u, double* x2, double* d2, hipStream_t st);
+
+}  // namespace pdk

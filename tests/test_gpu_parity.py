@@ -1,0 +1,207 @@
+"""GPU path (through the C ABI) against the CPU FP64 oracle, element by element
+on seeded inputs.  Tolerance for the FP64 path: 1e-10 relative."""
+import numpy as np
+import pytest
+
+import pd_inputs as P
+from oracle import collision as ocol, fem as ofem, pd as opd, schur as osch
+from gpu_util import SMALL_SCENES, dev, gpu_context, host, oracle_model, rel
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.mark.parametrize("name", list(SMALL_SCENES))
+def test_schur_matches_oracle(torch_cuda, name):
+    sc = SMALL_SCENES[name]()
+    om = oracle_model(sc)
+    ctx = gpu_context(sc)
+    assert ctx.m == om.m and ctx.n1 == om.i1.size and ctx.n_beta == om.beta.sum()
+    assert np.array_equal(ctx.region_ids, om.i2)
+    S = torch_cuda.empty(ctx.m * ctx.m, dtype=torch_cuda.float64, device="cuda")
+    ctx.get_schur(S)
+    Sg = host(S, (ctx.m, ctx.m)).T          # column-major -> row index first
+    So = om.schur()
+    assert rel(Sg, So) <= TOL
+    assert np.abs(Sg - Sg.T).max() <= 1e-12 * np.abs(So).max()
+
+
+@pytest.mark.parametrize("name", ["cube8", "g9x7x6", "g16x15x8"])
+def test_local_steps_match_oracle(torch_cuda, name):
+    sc = SMALL_SCENES[name]()
+    om = oracle_model(sc, build_schur=False)
+    ctx = gpu_context(sc)
+    rng = np.random.default_rng(21)
+    x = sc.rest + 0.15 * sc.h * rng.normal(size=sc.rest.shape)
+    x[:, sc.dirichlet] = sc.rest[:, sc.dirichlet]
+    xd = dev(x)
+    f = torch_cuda.empty(3 * sc.n_nodes, dtype=torch_cuda.float64, device="cuda")
+    Ra = torch_cuda.empty(9 * ctx.n_alpha, dtype=torch_cuda.float64, device="cuda")
+    ctx.local_step_full(xd, f, Ra)
+    R_or = om.rotations(x, om.alpha)
+    f_or = om.forces(x, R_or, om.alpha)
+    assert rel(host(f, (3, -1)), f_or) <= TOL
+    Rg = host(Ra, (9, -1)).T.reshape(-1, 3, 3)
+    assert np.abs(Rg - R_or).max() <= 1e-12
+    if ctx.n_beta:
+        x2 = dev(x[:, om.i2])
+        fb = torch_cuda.empty(3 * ctx.m, dtype=torch_cuda.float64, device="cuda")
+        Rb = torch_cuda.empty(9 * ctx.n_beta, dtype=torch_cuda.float64, device="cuda")
+        ctx.local_step_region(x2, fb, Rb)
+        R_b = om.rotations(x, om.beta)
+        fb_or = om.forces(x, R_b, om.beta)[:, om.i2]
+        assert rel(host(fb, (3, -1)), fb_or) <= TOL
+        assert np.abs(host(Rb, (9, -1)).T.reshape(-1, 3, 3) - R_b).max() <= 1e-12
+        # FP32 rotations: within 1e-6 of the FP64 ones
+        Rb32 = torch_cuda.empty(9 * ctx.n_beta, dtype=torch_cuda.float32, device="cuda")
+        ctx.local_step_region(x2, fb, Rb32, rot_fp32=True)
+        assert np.abs(host(Rb32, (9, -1)).T.reshape(-1, 3, 3) - R_b).max() <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["cube8", "g4x3x5", "g16x15x8"])
+def test_condense_and_backsub_match_oracle(torch_cuda, name):
+    sc = SMALL_SCENES[name]()
+    om = oracle_model(sc, build_schur=False)
+    ctx = gpu_context(sc)
+    rng = np.random.default_rng(5)
+    f = rng.normal(size=(3, sc.n_nodes))
+    y2 = torch_cuda.empty(3 * ctx.m, dtype=torch_cuda.float64, device="cuda")
+    ctx.condense_rhs(dev(f), y2)
+    w1, y2_or = osch.forward_sub(om.lu11, om.A21, f[:, om.i1].T, f[:, om.i2].T)
+    assert rel(host(y2, (3, -1)), y2_or.T) <= TOL
+    d2 = rng.normal(size=(3, ctx.m))
+    x0 = rng.normal(size=(3, sc.n_nodes))
+    xd = dev(x0)
+    ctx.backsub(dev(d2), xd)
+    x_or = x0.copy()
+    x_or[:, om.i1] += osch.back_sub(om.lu11, om.A12, f[:, om.i1].T, d2.T).T
+    x_or[:, om.i2] += d2
+    assert rel(host(xd, (3, -1)), x_or) <= TOL
+
+
+@pytest.mark.parametrize("name", ["cube8", "g9x7x6", "g16x15x8"])
+def test_penalty_solve_matches_oracle(torch_cuda, name):
+    sc = SMALL_SCENES[name]()
+    om = oracle_model(sc)
+    ctx = gpu_context(sc)
+    rng = np.random.default_rng(8)
+    m = ctx.m
+    # general penalties (non-conforming weights, shared nodes) plus inactive ones
+    npen = 12
+    idx = np.full((npen, 8), -1, dtype=np.int32)
+    w = np.zeros((npen, 8))
+    for j in range(npen):
+        k = 1 + j % 4
+        idx[j, :k] = rng.choice(m, size=k, replace=False)
+        w[j, :k] = rng.uniform(-1, 1, size=k)
+    c = rng.uniform(1e3, 1e6, size=npen)
+    c[::5] = 0.0
+    t = rng.normal(size=(3, npen))
+    x2 = sc.rest[:, om.i2] + 0.05 * rng.normal(size=(3, m))
+    fcol = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), dev(x2), fcol)
+    fcol_or = ocol.penalty_force(m, idx, w, c, t, x2)
+    assert rel(host(fcol, (3, -1)), fcol_or) <= TOL
+    g = rng.normal(size=(3, m))
+    u = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    info = ctx.global_solve(dev(g), u, want_info=True)
+    import scipy.linalg as sla
+    H = om.schur() + ocol.penalty_matrix(m, idx, w, c)
+    u_or = sla.cho_solve(sla.cho_factor(H, lower=True), g.T).T
+    assert rel(host(u, (3, -1)), u_or) <= TOL
+    assert info["rel_residual"] <= 1e-12 and info["bad_pivot"] == 0
+    # second solve with the same factor (no refactorization)
+    g2 = rng.normal(size=(3, m))
+    ctx.global_solve(dev(g2), u)
+    u2_or = sla.cho_solve(sla.cho_factor(H, lower=True), g2.T).T
+    assert rel(host(u, (3, -1)), u2_or) <= TOL
+
+
+def _run_alg1_pair(torch, sc, outer, inner, steps):
+    from paper_2008_01541_amd.driver import Alg1Runner
+    om = oracle_model(sc)
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen)
+    x_or = sc.rest.copy()
+    worst = 0.0
+    for s in range(1, steps + 1):
+        cen, rad = sc.spheres.centers(s), sc.spheres.radii
+        run.set_spheres(cen, rad)
+        det = opd.sphere_detector(om, sc.proxy_local(), cen, rad, sc.k_pen)
+        for it in range(outer):
+            run.outer_iteration(n_inner=inner)
+            x_or = opd.alg1_outer_iteration(om, x_or, det, n_inner=inner)
+            xg = run.positions()
+            disp = np.abs(x_or - sc.rest).max()
+            worst = max(worst, np.abs(xg - x_or).max() / max(disp, 1e-300))
+    return worst, x_or
+
+
+@pytest.mark.parametrize("name,inner", [("cube8", 1), ("g9x7x6", 2), ("g16x15x8", 3)])
+def test_alg1_iterations_match_oracle(torch_cuda, name, inner):
+    sc = SMALL_SCENES[name]()
+    worst, x_or = _run_alg1_pair(torch_cuda, sc, outer=3, inner=inner, steps=2)
+    assert np.abs(x_or - sc.rest).max() > 1e-6 * sc.h      # something moved
+    assert worst <= 1e-9
+
+
+def test_run_twice_bitwise_identical(torch_cuda):
+    sc = SMALL_SCENES["g16x15x8"]()
+    outs = []
+    for _ in range(2):
+        from paper_2008_01541_amd.driver import Alg1Runner
+        run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen)
+        run.set_spheres(sc.spheres.centers(2), sc.spheres.radii)
+        for _ in range(3):
+            run.outer_iteration(n_inner=2)
+        outs.append(run.positions())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_not_spd_reported(torch_cuda):
+    sc = SMALL_SCENES["cube8"]()
+    ctx = gpu_context(sc)
+    m = ctx.m
+    idx = np.full((1, 8), -1, dtype=np.int32)
+    idx[0, 0] = 5
+    w = np.zeros((1, 8)); w[0, 0] = 1.0
+    c = np.array([-1e12])                       # makes H indefinite
+    t = np.zeros((3, 1))
+    fcol = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), dev(np.zeros((3, m))), fcol)
+    from paper_2008_01541_amd import PDError
+    u = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    with pytest.raises(PDError) as e:
+        ctx.global_solve(dev(np.ones((3, m))), u, want_info=True)
+    assert e.value.status == -4
+
+
+def test_backsub_requires_condense(torch_cuda):
+    sc = SMALL_SCENES["cube8"]()
+    ctx = gpu_context(sc)
+    from paper_2008_01541_amd import PDError
+    with pytest.raises(PDError) as e:
+        ctx.backsub(dev(np.zeros((3, ctx.m))), dev(sc.rest.copy()))
+    assert e.value.status == -6
+
+
+def test_invalid_mesh_rejected(torch_cuda):
+    sc = SMALL_SCENES["cube8"]()
+    from paper_2008_01541_amd import PDContext, PDError
+    bad = sc.tets.copy()
+    bad[0, 0] = sc.n_nodes + 3
+    with pytest.raises(PDError) as e:
+        PDContext(sc.rest, bad, sc.region, sc.dirichlet, sc.mu)
+    assert e.value.status == -1
+    flipped = sc.tets.copy()
+    flipped[[1, 2], 0] = flipped[[2, 1], 0]       # inverted rest tet
+    with pytest.raises(PDError):
+        PDContext(sc.rest, flipped, sc.region, sc.dirichlet, sc.mu)
+    with pytest.raises(PDError):
+        PDContext(sc.rest, sc.tets, np.zeros(sc.n_nodes, bool), sc.dirichlet, sc.mu)
