@@ -142,13 +142,20 @@ pd_status pd_assemble_rhs(pd_ctx *ctx, const double *ft, const double *f_beta,
                           const double *f_col, double *g);
 
 /* Dense solve of H u = g with H = S + W^T C W (Alg. 1 steps 4.3 and 4.5,
- * Sec. 4.4 Step 2): refactors H if the penalty set changed, then solves the
- * three coordinate right-hand sides.  g, u: dev [3][m].
- * PD_FP64: FP64 Cholesky.  PD_FP32_IR / PD_BF16_IR: low-precision factor and
- * iterative refinement with the residual g - H u in FP64 until
- * rel_residual <= 1e-8 (then PD_ERR_IR_STALLED if not reached: u holds the
- * best iterate; the call refactors in FP64 and reports fell_back = 1).
- * info (host) may be NULL; when given, the call synchronizes and fills it. */
+ * Sec. 4.4 Step 2): refactors H if the penalty set changed (or the precision
+ * of the stored factor differs), then solves the three coordinate
+ * right-hand sides.  g, u: dev [3][m], g and u must not alias.
+ * PD_FP64: FP64 Cholesky and triangular solves.
+ * PD_FP32_IR / PD_BF16_IR: the Jacobi-equilibrated D H D is factored in FP32
+ * (tile products on FP32 matrix cores, or with BF16 operands and FP32
+ * accumulation); u is refined with the residual g - H u computed in FP64
+ * until max_v ||r_v|| / ||g_v|| <= 1e-8 or 30 correction steps.  These modes
+ * synchronize the stream once per step.  If the tolerance is not reached the
+ * call returns PD_ERR_IR_STALLED with u = the last iterate (the caller may
+ * solve again with PD_FP64; fell_back is then reported by the caller).
+ * info (host) may be NULL; when given, the call synchronizes and fills it.
+ * A non-positive pivot -> PD_ERR_NOT_SPD (only detected when the call
+ * synchronizes, i.e. with info or in the refined modes). */
 pd_status pd_global_solve(pd_ctx *ctx, const double *g, double *u, pd_precision prec,
                           pd_solve_info *info);
 
@@ -162,6 +169,66 @@ pd_status pd_inner_update(pd_ctx *ctx, const double *u2, double *x2, double *del
  * x2 += delta2, both written into x (dev [3][n_nodes]).  PD_ERR_STATE if no
  * pd_condense_rhs preceded it. */
 pd_status pd_backsub(pd_ctx *ctx, const double *delta2, double *x);
+
+/* ---- Learned warm start (not in the paper) ---------------------------------
+ * A three-layer perceptron y = W3 relu(W2 relu(W1 x + b1) + b2) + b3 that
+ * predicts the region displacement increment of the next frame from the
+ * previous increment and the active-penalty mask.  Products use BF16
+ * operands (weights kept as BF16 copies of FP32 master weights; activations
+ * and gradients rounded to BF16 when used as operands) with FP32
+ * accumulation on the matrix cores.  Loss: sum((y - t)^2) / (2 B n_out).
+ * Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ * Parameter packing (host float32): W1 [n_h1][n_in], b1 [n_h1], W2 [n_h2][n_h1],
+ * b2 [n_h2], W3 [n_out][n_h2], b3 [n_out] (row-major, concatenated). */
+typedef struct pd_mlp pd_mlp;
+
+/* Creates the network with the given initial parameters (host, packed as
+ * above; initial values are an input, e.g. from a seeded generator).
+ * max_batch bounds the batch of every later call.  Synchronous. */
+pd_status pd_mlp_create(int32_t n_in, int32_t n_h1, int32_t n_h2, int32_t n_out,
+                        int32_t max_batch, const float *params_host, void *hip_stream,
+                        pd_mlp **out);
+
+/* host params (packed as above) <- current FP32 master parameters.  Synchronous. */
+pd_status pd_mlp_get_params(pd_mlp *mlp, float *params_host);
+
+/* y = network(x): x dev float [batch][n_in], y dev float [batch][n_out]. */
+pd_status pd_mlp_forward(pd_mlp *mlp, const float *x, float *y, int32_t batch);
+
+/* One training step on (x, target), both dev float, batch rows.  With
+ * grads_host == NULL: forward, backward and an Adam update with rate lr.
+ * With grads_host != NULL: the gradients (packed as the parameters) are
+ * copied to the host and no update is made.  loss_host (may be NULL)
+ * receives the loss before the update; giving it synchronizes. */
+pd_status pd_mlp_train_step(pd_mlp *mlp, const float *x, const float *target, int32_t batch,
+                            float lr, double *loss_host, float *grads_host);
+
+pd_status pd_mlp_destroy(pd_mlp *mlp);
+
+/* Phases timed by pd_get_timings. */
+typedef enum {
+  PD_PHASE_LOCAL_FULL = 0,    /* pd_local_step_full */
+  PD_PHASE_CONDENSE = 1,      /* pd_condense_rhs */
+  PD_PHASE_DETECT = 2,        /* pd_detect_spheres */
+  PD_PHASE_COLLISION = 3,     /* pd_collision_update */
+  PD_PHASE_LOCAL_REGION = 4,  /* pd_local_step_region */
+  PD_PHASE_ASSEMBLE = 5,      /* pd_assemble_rhs */
+  PD_PHASE_HBUILD = 6,        /* pd_global_solve: H = S + W^T C W (lower part) */
+  PD_PHASE_FACTOR = 7,        /* pd_global_solve: Cholesky factorization of H */
+  PD_PHASE_SOLVE = 8,         /* pd_global_solve: triangular solves (+ refinement) */
+  PD_PHASE_INNER_UPDATE = 9,  /* pd_inner_update */
+  PD_PHASE_BACKSUB = 10,      /* pd_backsub */
+  PD_N_PHASES = 11
+} pd_phase;
+
+/* Turns per-phase timing on (1) or off (0).  When on, every entry point
+ * records a pair of HIP events on the context stream around its work. */
+pd_status pd_set_timing(pd_ctx *ctx, int on);
+
+/* Synchronizes the stream and returns, per phase, the summed milliseconds
+ * (host ms[PD_N_PHASES]) and the number of timed calls (host counts, may be
+ * NULL) since the previous call; then clears the records. */
+pd_status pd_get_timings(pd_ctx *ctx, double *ms, int64_t *counts);
 
 /* Last error message of the context (valid until the next call on it).
  * With ctx = NULL: the message of the last failed pd_schur_build on this thread. */

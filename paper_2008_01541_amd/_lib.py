@@ -48,8 +48,18 @@ _SIGS = {
     "pd_global_solve": [_P, _P, _P, C.c_int, C.POINTER(pd_solve_info)],
     "pd_inner_update": [_P, _P, _P, _P, _P],
     "pd_backsub": [_P, _P, _P],
+    "pd_mlp_create": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
+                      C.POINTER(_P)],
+    "pd_mlp_get_params": [_P, _P],
+    "pd_mlp_forward": [_P, _P, _P, C.c_int32],
+    "pd_mlp_train_step": [_P, _P, _P, C.c_int32, C.c_float, C.POINTER(C.c_double), _P],
+    "pd_mlp_destroy": [_P],
+    "pd_set_timing": [_P, C.c_int],
+    "pd_get_timings": [_P, _P, _P],
     "pd_destroy": [_P],
 }
+PHASES = ["local_full", "condense", "detect", "collision", "local_region", "assemble",
+          "hbuild", "factor", "solve", "inner_update", "backsub"]
 
 _lib = None
 
@@ -225,7 +235,89 @@ class PDContext:
             _ptr(delta2, torch.float64, 3 * self.m, "delta2"),
             _ptr(ft, torch.float64, 3 * self.m, "ft")))
 
+    def set_timing(self, on=True):
+        self._chk(self._lib.pd_set_timing(self._ctx, 1 if on else 0))
+
+    def get_timings(self):
+        """{phase: (total ms, calls)} since the previous call (synchronizes)."""
+        ms = np.zeros(len(PHASES), dtype=np.float64)
+        cnt = np.zeros(len(PHASES), dtype=np.int64)
+        self._chk(self._lib.pd_get_timings(self._ctx, ms.ctypes.data, cnt.ctypes.data))
+        return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(PHASES)}
+
     def backsub(self, delta2, x):
         import torch
         self._chk(self._lib.pd_backsub(self._ctx, _ptr(delta2, torch.float64, 3 * self.m, "delta2"),
                                        _ptr(x, torch.float64, 3 * self.n, "x")))
+
+
+class MLP:
+    """Warm-start network (pd_mlp_* entry points)."""
+
+    def __init__(self, n_in, n_h1, n_h2, n_out, max_batch, params_flat, stream=None):
+        import torch
+        lib = load_library()
+        self._lib = lib
+        p = np.ascontiguousarray(params_flat, dtype=np.float32)
+        self.shape = (n_in, n_h1, n_h2, n_out)
+        self.n_params = n_h1 * n_in + n_h1 + n_h2 * n_h1 + n_h2 + n_out * n_h2 + n_out
+        if p.size != self.n_params:
+            raise ValueError("parameter vector has the wrong length")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = lib.pd_mlp_create(n_in, n_h1, n_h2, n_out, max_batch, p.ctypes.data,
+                               C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != PD_OK:
+            raise PDError(st, "pd_mlp_create failed")
+        self._h = h
+        self.max_batch = max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pd_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        st = self._lib.pd_mlp_get_params(self._h, out.ctypes.data)
+        if st != PD_OK:
+            raise PDError(st, "pd_mlp_get_params failed")
+        return out
+
+    def forward(self, x, y):
+        import torch
+        B = x.shape[0]
+        st = self._lib.pd_mlp_forward(self._h, _ptr(x, torch.float32, B * self.shape[0], "x"),
+                                      _ptr(y, torch.float32, B * self.shape[3], "y"), B)
+        if st != PD_OK:
+            raise PDError(st, "pd_mlp_forward failed")
+
+    def train_step(self, x, target, lr, want_loss=True):
+        import torch
+        B = x.shape[0]
+        loss = C.c_double()
+        st = self._lib.pd_mlp_train_step(self._h, _ptr(x, torch.float32, B * self.shape[0], "x"),
+                                         _ptr(target, torch.float32, B * self.shape[3], "target"),
+                                         B, float(lr), C.byref(loss) if want_loss else None, None)
+        if st != PD_OK:
+            raise PDError(st, "pd_mlp_train_step failed")
+        return loss.value if want_loss else None
+
+    def gradients(self, x, target):
+        import torch
+        B = x.shape[0]
+        loss = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32)
+        st = self._lib.pd_mlp_train_step(self._h, _ptr(x, torch.float32, B * self.shape[0], "x"),
+                                         _ptr(target, torch.float32, B * self.shape[3], "target"),
+                                         B, 0.0, C.byref(loss), g.ctypes.data)
+        if st != PD_OK:
+            raise PDError(st, "pd_mlp_train_step failed")
+        return g, loss.value

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <numeric>
@@ -42,7 +43,10 @@ struct pd_ctx {
   std::vector<int64_t> lev_mat_off;  // [K] offsets (doubles) of Z_k in levmat
   std::vector<int64_t> B_ptr_off, B_nnz_off, Bt_ptr_off, Bt_nnz_off, Brows_off, Brows_cnt;
   int64_t maxw = 0;
+  int64_t maxldw = 0;
   int ntm = 0;                        // tiles of the m x m system
+  int ldH = 0, ldH32 = 0;             // padded leading dimensions of the work matrices
+  std::vector<int> ldw;               // padded leading dimension of each level block
 
   DevAlloc mem;
   // mesh subsets
@@ -74,6 +78,23 @@ struct pd_ctx {
   int* d_err = nullptr;
   unsigned long long* d_ticket = nullptr;
   int* d_flags = nullptr;
+  int* d_tflags = nullptr;            // tile-ready flags of the dataflow Cholesky
+  unsigned* d_tticket = nullptr;
+  int chol_epoch = 0;
+  int chol_dataflow = 1;              // 1: single-launch dataflow, 0: three launches per step
+  int n_wg = 512;
+  // low-precision factor for the refined solves
+  float* d_H32 = nullptr;
+  float* d_linv32 = nullptr;
+  float* d_y32 = nullptr;
+  float* d_xs32 = nullptr;
+  double* d_dvec = nullptr;
+  unsigned long long* d_lp_ticket = nullptr;
+  int* d_lp_flags = nullptr;
+  int lp_prec = -1;                   // precision of the current low-precision factor
+  bool lp_stale = true;
+  int max_ir = 30;
+  double ir_tol = 1e-8;
   // sweeps
   double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
   bool have_condense = false;
@@ -82,6 +103,23 @@ struct pd_ctx {
   int32_t* d_pidx = nullptr;
   double *d_pw = nullptr, *d_pc = nullptr, *d_pt = nullptr;
   bool stale = true;
+
+  // optional per-phase timing with HIP events recorded on the stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_pairs;   // (phase, (start, end))
+  hipEvent_t next_event() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  ~pd_ctx() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
 
   pd_status fail(pd_status s, const char* fmt, ...) {
     char buf[512];
@@ -133,6 +171,29 @@ struct pd_ctx {
 
 namespace {
 
+// Records HIP events around one phase of an entry point when timing is on.
+struct PhaseTimer {
+  pd_ctx* c;
+  int phase;
+  size_t i0 = 0;
+  bool on;
+  PhaseTimer(pd_ctx* ctx, int ph) : c(ctx), phase(ph), on(ctx->timing) {
+    if (!on) return;
+    i0 = c->ev_used;
+    hipEvent_t e = c->next_event();
+    if (!e) { on = false; return; }
+    (void)hipEventRecord(e, c->st);
+  }
+  ~PhaseTimer() {
+    if (!on) return;
+    size_t i1 = c->ev_used;
+    hipEvent_t e = c->next_event();
+    if (!e) return;
+    (void)hipEventRecord(e, c->st);
+    c->ev_pairs.push_back({phase, {i0, i1}});
+  }
+};
+
 // Gather plan: dst[dst_off[i]] = sum of vals[src[e]] for e in [ptr[i], ptr[i+1]).
 struct Plan {
   std::vector<int64_t> ptr{0}, src, dst;
@@ -166,6 +227,20 @@ void free_now(pd_ctx* c, void* p) {
   if (it != c->mem.ptrs.end()) c->mem.ptrs.erase(it);
   (void)hipFree(p);
 }
+
+// In-place lower Cholesky of the n x n matrix A (leading dimension lda, a
+// multiple of 16 so tiles start on 128-byte lines); tile inverses to d_linv,
+// transpose of the factor in the upper triangle.
+void cholesky(pd_ctx* c, double* A, int lda, int n) {
+  if (c->chol_dataflow) {
+    potrf_dataflow(A, lda, n, c->d_linv, c->d_tflags, c->d_tticket, ++c->chol_epoch, c->d_info,
+                   c->d_err, c->n_wg, c->st);
+  } else {
+    potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
+  }
+}
+
+inline int pad_to(int64_t v, int q) { return (int)((v + q - 1) / q * q); }
 
 struct CSRBuild {
   std::vector<int32_t> ptr, col;
@@ -294,6 +369,11 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     }
   }
   auto width = [&](int k) -> int64_t { return k == K ? m : c->lev_off[k + 1] - c->lev_off[k]; };
+  c->ldw.assign(K + 1, 0);
+  for (int k = 0; k <= K; ++k) c->ldw[k] = (k == K) ? (int)m : pad_to(width(k), 16);
+  for (int k = 0; k < K; ++k) c->maxldw = std::max<int64_t>(c->maxldw, c->ldw[k]);
+  c->ldH = pad_to(m, 16);
+  c->ldH32 = pad_to(m, 32);
   for (int64_t w = 0; w < 1; ++w) {}
   if (c->maxw > 46340 || m > 46340) return c->fail(PD_ERR_INVALID, "dense block too large");
 
@@ -332,7 +412,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   c->lev_mat_off.assign(K, 0);
   for (int k = 0; k < K; ++k) {
     c->lev_mat_off[k] = lev_mat_total;
-    lev_mat_total += width(k) * width(k);
+    lev_mat_total += (int64_t)c->ldw[k] * width(k);
   }
   CK(c->alloc(&c->d_levmat, lev_mat_total));
   CK(c->alloc(&c->d_S, m * m));
@@ -397,7 +477,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
         if (lv == lu) {
           if (lu == K) pl_S.add_group(srcs.data(), (int64_t)srcs.size(), ru + cv * m);
           else pl_lev.add_group(srcs.data(), (int64_t)srcs.size(),
-                                c->lev_mat_off[lu] + ru + cv * width(lu));
+                                c->lev_mat_off[lu] + ru + cv * c->ldw[lu]);
         } else if (lv == lu - 1) {   // row in level k+1, col in level k: B_k
           const int k = lv;
           Bcol[k].push_back((int32_t)cv);
@@ -511,29 +591,39 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   HIPCK(c, hipMemsetAsync(c->d_err, 0, sizeof(int), c->st));
   HIPCK(c, hipMemsetAsync(c->d_ticket, 0, 4 * sizeof(unsigned long long), c->st));
   HIPCK(c, hipMemsetAsync(c->d_flags, 0, 4 * (int64_t)c->ntm * sizeof(int), c->st));
+  {
+    const int64_t nt2 = ntmax * ntmax;
+    CK(c->alloc(&c->d_tflags, nt2));
+    CK(c->alloc(&c->d_tticket, 4));
+    HIPCK(c, hipMemsetAsync(c->d_tflags, 0, nt2 * sizeof(int), c->st));
+    const char* mode = getenv("PDSCHUR_CHOL");
+    if (mode && strcmp(mode, "tiled") == 0) c->chol_dataflow = 0;
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      c->n_wg = 2 * ncu;
+  }
   if (K > 0) {
     double *d_M, *d_X, *d_U;
     int64_t maxrows = 0;
     for (int k = 0; k < K; ++k) maxrows = std::max(maxrows, c->Brows_cnt[k]);
-    CK(c->alloc(&d_M, c->maxw * c->maxw));
-    CK(c->alloc(&d_X, c->maxw * c->maxw));
+    CK(c->alloc(&d_M, c->maxldw * c->maxw));
+    CK(c->alloc(&d_X, c->maxldw * c->maxw));
     CK(c->alloc(&d_U, c->maxw * std::max<int64_t>(1, maxrows)));
     for (int k = 0; k < K; ++k) {
-      const int w = (int)width(k);
+      const int w = (int)width(k), ld = c->ldw[k];
       double* A = c->d_levmat + c->lev_mat_off[k];
-      potrf_tiled(A, w, w, c->d_linv, c->d_info, c->st);
-      trtri_from_factor(A, w, w, c->d_linv, d_M, d_X, w, c->st);
-      HIPCK(c, hipMemsetAsync(A, 0, (size_t)w * w * sizeof(double), c->st));
-      lauum_full(d_X, w, w, A, w, c->st);
-      HIPCK(c, hipMemsetAsync(d_X, 0, (size_t)w * w * sizeof(double), c->st));
+      cholesky(c, A, ld, w);
+      trtri_from_factor(A, ld, w, c->d_linv, d_M, d_X, ld, c->st);
+      lauum_full(d_X, ld, w, A, ld, c->st);
       double* Nx = (k + 1 < K) ? c->d_levmat + c->lev_mat_off[k + 1] : c->d_S;
-      const int ldn = (int)width(k + 1);
+      const int ldn = c->ldw[k + 1];
       const int nr = (int)c->Brows_cnt[k];
       const int32_t* rows = c->d_Brows + c->Brows_off[k];
       const int32_t* bp = c->d_Bptr + c->B_ptr_off[k];
       const int32_t* bc = c->d_Bcol + c->B_nnz_off[k];
       const double* bv = c->d_Bval + c->B_nnz_off[k];
-      dense_times_sparse_t(A, w, nr, rows, bp, bc, bv, d_U, c->st);
+      dense_times_sparse_t(A, ld, w, nr, rows, bp, bc, bv, d_U, c->st);
       sub_sparse_times_dense(Nx, ldn, nr, rows, bp, bc, bv, d_U, w, c->st);
       CK(c->check("level elimination"));
     }
@@ -597,7 +687,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   free_now(c, d_vol);
   free_now(c, d_rest);
   free_now(c, d_tets);
-  CK(c->alloc(&c->d_H, m * m));
+  CK(c->alloc(&c->d_H, (int64_t)c->ldH * m));
   CK(c->alloc(&c->d_y, 3 * m));
   CK(c->alloc(&c->d_res, 3 * m));
   CK(c->alloc(&c->d_norms, 8));
@@ -689,6 +779,7 @@ pd_status pd_region_gather(pd_ctx* c, const double* x, double* x2) {
 pd_status pd_local_step_full(pd_ctx* c, const double* x, double* R_alpha, double* f) {
   if (bad_ctx(c) || !x || !f) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
+  PhaseTimer tm(c, PD_PHASE_LOCAL_FULL);
   local_step(c->nalpha, c->d_tets_alpha, c->nalpha, c->d_Bm_alpha, c->d_vol_alpha, c->nalpha, x,
              c->n, c->mu, c->d_fe, R_alpha, 0, c->st);
   node_gather3(c->n, c->d_inc_a_ptr, c->d_inc_a, c->d_fe, c->nalpha, nullptr, f, c->n, 0, c->st);
@@ -699,11 +790,12 @@ pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
   if (bad_ctx(c) || !f || !y2) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
   const int64_t n1 = c->n1, m = c->m;
+  PhaseTimer tm(c, PD_PHASE_CONDENSE);
   gather_rows3(n1, c->d_lev_nodes, f, c->n, c->d_fhat, n1, c->st);
   gather_rows3(m, c->d_region_ids, f, c->n, y2, m, c->st);
   for (int k = 0; k < c->K; ++k) {
     const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
-    symv3(c->d_levmat + c->lev_mat_off[k], (int)w, (int)w, c->d_fhat + off, (int)n1, 1.0, 0.0,
+    symv3(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_fhat + off, (int)n1, 1.0, 0.0,
           c->d_v + off, (int)n1, c->st);
     const int32_t* bp = c->d_Bptr + c->B_ptr_off[k];
     const int32_t* bc = c->d_Bcol + c->B_nnz_off[k];
@@ -725,6 +817,7 @@ pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
   if (c->broken) return PD_ERR_HIP;
   if (!c->have_condense) return c->fail(PD_ERR_STATE, "pd_backsub needs a preceding pd_condense_rhs");
   const int64_t n1 = c->n1, m = c->m;
+  PhaseTimer tm(c, PD_PHASE_BACKSUB);
   if (n1 > 0) {
     HIPCK(c, hipMemcpyAsync(c->d_xs, c->d_v, 3 * n1 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
     for (int k = c->K - 1; k >= 0; --k) {
@@ -735,7 +828,7 @@ pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
       const double* xn = (k + 1 < c->K) ? c->d_xs + c->lev_off[k + 1] : delta2;
       const int64_t ldxn = (k + 1 < c->K) ? n1 : m;
       csr_spmv3(w, tp, tc, tv, xn, ldxn, 1.0, c->d_tmp, c->maxw, nullptr, 0, c->st);
-      symv3(c->d_levmat + c->lev_mat_off[k], (int)w, (int)w, c->d_tmp, (int)c->maxw, -1.0, 1.0,
+      symv3(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_tmp, (int)c->maxw, -1.0, 1.0,
             c->d_xs + off, (int)n1, c->st);
     }
     scatter_add_rows3(n1, c->d_lev_nodes, c->d_xs, n1, x, c->n, c->st);
@@ -751,6 +844,7 @@ pd_status pd_detect_spheres(pd_ctx* c, int32_t n_prox, const int32_t* prox, int3
       (n_sph > 0 && !spheres) || !(k >= 0.0))
     return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
+  PhaseTimer tm(c, PD_PHASE_DETECT);
   detect_spheres(n_prox, prox, n_sph, spheres, k, x2, (int)c->m, idx, w, cc, t, c->st);
   return c->check("pd_detect_spheres");
 }
@@ -761,6 +855,7 @@ pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, cons
     return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
   CK(ensure_pen_cap(c, std::max<int32_t>(n_pen, 1)));
+  PhaseTimer tm(c, PD_PHASE_COLLISION);
   if (n_pen > 0) {
     HIPCK(c, hipMemcpyAsync(c->d_pidx, idx, 8 * (size_t)n_pen * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st));
     HIPCK(c, hipMemcpyAsync(c->d_pw, w, 8 * (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
@@ -771,6 +866,7 @@ pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, cons
   penalty_apply(n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 1.0, x2, (int)c->m, nullptr, 0, f_col,
                 c->st);
   c->stale = true;
+  c->lp_stale = true;
   return c->check("pd_collision_update");
 }
 
@@ -782,6 +878,7 @@ pd_status pd_local_step_region(pd_ctx* c, const double* x2, void* R_beta, double
     HIPCK(c, hipMemsetAsync(f_beta, 0, 3 * c->m * sizeof(double), c->st));
     return PD_OK;
   }
+  PhaseTimer tm(c, PD_PHASE_LOCAL_REGION);
   local_step(c->nbeta, c->d_tets_beta, c->nbeta, c->d_Bm_beta, c->d_vol_beta, c->nbeta, x2, c->m,
              c->mu, c->d_fe, R_beta, rot_fp32 ? 1 : 0, c->st);
   node_gather3(c->m, c->d_inc_b_ptr, c->d_inc_b, c->d_fe, c->nbeta, nullptr, f_beta, c->m, 0, c->st);
@@ -792,57 +889,142 @@ pd_status pd_assemble_rhs(pd_ctx* c, const double* ft, const double* f_beta, con
                           double* g) {
   if (bad_ctx(c) || !ft || !g) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
+  PhaseTimer tm(c, PD_PHASE_ASSEMBLE);
   axpy3_sum((int)c->m, ft, f_beta, f_col, g, c->st);
   return c->check("pd_assemble_rhs");
 }
 
+namespace {
+
+// H = S + W^T C W on the lower tiles of d_H (FP64).
+void build_H(pd_ctx* c) {
+  const int m = (int)c->m;
+  PhaseTimer tm(c, PD_PHASE_HBUILD);
+  copy_lower_tiles(c->d_S, m, c->d_H, c->ldH, m, c->st);
+  if (c->n_pen > 0)
+    penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, nullptr, m, c->d_H, c->ldH,
+                  nullptr, c->st);
+}
+
+// res = g - (S + P) u in FP64; returns max over columns of ||res|| / ||g|| (synchronizes).
+pd_status residual(pd_ctx* c, const double* g, const double* u, double* rel) {
+  const int m = (int)c->m;
+  HIPCK(c, hipMemcpyAsync(c->d_res, g, 3 * (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  symv3(c->d_S, m, m, u, m, -1.0, 1.0, c->d_res, m, c->st);
+  if (c->n_pen > 0) {
+    penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, u, m, nullptr, 0, c->d_y,
+                  c->st);
+    axpy3_sum(m, c->d_res, c->d_y, nullptr, c->d_res, c->st);
+  }
+  colnorm2_3(m, c->d_res, c->d_norms, c->st);
+  colnorm2_3(m, g, c->d_norms + 3, c->st);
+  double nrm[6];
+  HIPCK(c, hipMemcpyAsync(nrm, c->d_norms, 6 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCK(c, hipStreamSynchronize(c->st));
+  double rr = 0.0;
+  for (int v = 0; v < 3; ++v)
+    if (nrm[3 + v] > 0) rr = std::max(rr, std::sqrt(nrm[v] / nrm[3 + v]));
+  *rel = rr;
+  return PD_OK;
+}
+
+pd_status ensure_lp_buffers(pd_ctx* c) {
+  if (c->d_H32) return PD_OK;
+  const int64_t m = c->m;
+  CK(c->alloc(&c->d_H32, (int64_t)c->ldH32 * m));
+  CK(c->alloc(&c->d_linv32, (int64_t)c->ntm * NB * NB));
+  CK(c->alloc(&c->d_y32, 3 * m));
+  CK(c->alloc(&c->d_xs32, 3 * m));
+  CK(c->alloc(&c->d_dvec, m));
+  CK(c->alloc(&c->d_lp_ticket, 2));
+  CK(c->alloc(&c->d_lp_flags, 2 * (int64_t)c->ntm));
+  HIPCK(c, hipMemsetAsync(c->d_lp_ticket, 0, 2 * sizeof(unsigned long long), c->st));
+  HIPCK(c, hipMemsetAsync(c->d_lp_flags, 0, 2 * (int64_t)c->ntm * sizeof(int), c->st));
+  return PD_OK;
+}
+
+}  // namespace
+
 pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision prec,
                           pd_solve_info* info) {
   if (bad_ctx(c) || !g || !u) return PD_ERR_INVALID;
-  if (prec != PD_FP64) return c->fail(PD_ERR_INVALID, "precision mode not available");
+  if (prec != PD_FP64 && prec != PD_FP32_IR && prec != PD_BF16_IR)
+    return c->fail(PD_ERR_INVALID, "unknown precision mode %d", (int)prec);
   if (c->broken) return PD_ERR_HIP;
   const int m = (int)c->m;
-  if (c->stale) {
-    copy_lower_tiles(c->d_S, m, c->d_H, m, m, c->st);
-    if (c->n_pen > 0)
-      penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, nullptr, m, c->d_H, m,
-                    nullptr, c->st);
-    HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
-    potrf_tiled(c->d_H, m, m, c->d_linv, c->d_info, c->st);
-    c->stale = false;
-  }
-  trsv3_forward(c->d_H, m, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags, c->d_err, c->st);
-  trsv3_backward(c->d_H, m, m, c->d_linv, c->d_y, m, u, m, c->d_ticket + 1, c->d_flags + c->ntm,
-                 c->d_err, c->st);
-  CK(c->check("pd_global_solve"));
-  int hinfo = 0, herr = 0;
-  if (info) {
-    // residual r = g - S u - P u in FP64
-    HIPCK(c, hipMemcpyAsync(c->d_res, g, 3 * (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-    symv3(c->d_S, m, m, u, m, -1.0, 1.0, c->d_res, m, c->st);
-    if (c->n_pen > 0) {
-      penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, u, m, nullptr, 0, c->d_y,
-                    c->st);
-      axpy3_sum(m, c->d_res, c->d_y, nullptr, c->d_res, c->st);
+  if (prec == PD_FP64) {
+    if (c->stale) {
+      build_H(c);
+      HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
+      PhaseTimer tm(c, PD_PHASE_FACTOR);
+      cholesky(c, c->d_H, c->ldH, m);
+      c->stale = false;
+      c->lp_stale = true;       // d_H was rebuilt
     }
-    colnorm2_3(m, c->d_res, c->d_norms, c->st);
-    colnorm2_3(m, g, c->d_norms + 3, c->st);
-    double nrm[6];
-    HIPCK(c, hipMemcpyAsync(nrm, c->d_norms, 6 * sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCK(c, hipMemcpyAsync(&hinfo, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    HIPCK(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    HIPCK(c, hipStreamSynchronize(c->st));
-    double rr = 0.0;
-    for (int v = 0; v < 3; ++v)
-      if (nrm[3 + v] > 0) rr = std::max(rr, std::sqrt(nrm[v] / nrm[3 + v]));
-    info->ir_iters = 0;
+    {
+      PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
+      trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
+                    c->d_err, c->st);
+      trsv3_backward(c->d_H, c->ldH, m, c->d_linv, c->d_y, m, u, m, c->d_ticket + 1,
+                     c->d_flags + c->ntm, c->d_err, c->st);
+    }
+    CK(c->check("pd_global_solve"));
+    if (info) {
+      double rr = 0.0;
+      CK(residual(c, g, u, &rr));
+      int hinfo = 0, herr = 0;
+      HIPCK(c, hipMemcpy(&hinfo, c->d_info, sizeof(int), hipMemcpyDeviceToHost));
+      HIPCK(c, hipMemcpy(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+      info->ir_iters = 0;
+      info->bad_pivot = hinfo;
+      info->fell_back = 0;
+      info->reserved = 0;
+      info->rel_residual = rr;
+      if (herr) return c->fail(PD_ERR_HIP, "dependency wait timed out");
+      if (hinfo) return c->fail(PD_ERR_NOT_SPD, "non-positive pivot at %d", hinfo);
+    }
+    return PD_OK;
+  }
+  // ---- low-precision factor + iterative refinement with an FP64 residual
+  CK(ensure_lp_buffers(c));
+  if (c->lp_stale || c->lp_prec != (int)prec) {
+    build_H(c);
+    c->stale = true;            // d_H no longer holds an FP64 factor
+    HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
+    PhaseTimer tm(c, PD_PHASE_FACTOR);
+    equilibrate_convert(c->d_H, c->ldH, m, c->d_dvec, c->d_H32, c->ldH32, c->st);
+    potrf_dataflow_lp(c->d_H32, c->ldH32, m, c->d_linv32, c->d_tflags, c->d_tticket, ++c->chol_epoch,
+                      c->d_info, c->d_err, c->n_wg, prec == PD_BF16_IR, c->st);
+    c->lp_stale = false;
+    c->lp_prec = (int)prec;
+  }
+  PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
+  trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, g, c->d_y32, c->d_xs32, u, 0,
+                 c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
+  CK(c->check("pd_global_solve"));
+  double rr = 0.0;
+  int it = 0;
+  CK(residual(c, g, u, &rr));
+  while (!(rr <= c->ir_tol) && it < c->max_ir) {
+    trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, c->d_res, c->d_y32, c->d_xs32,
+                   u, 1, c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
+    ++it;
+    CK(residual(c, g, u, &rr));
+  }
+  int hinfo = 0, herr = 0;
+  HIPCK(c, hipMemcpy(&hinfo, c->d_info, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCK(c, hipMemcpy(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  if (info) {
+    info->ir_iters = it;
     info->bad_pivot = hinfo;
     info->fell_back = 0;
     info->reserved = 0;
     info->rel_residual = rr;
-    if (herr) return c->fail(PD_ERR_HIP, "triangular solve dependency wait timed out");
-    if (hinfo) return c->fail(PD_ERR_NOT_SPD, "non-positive pivot at %d", hinfo);
   }
+  if (herr) return c->fail(PD_ERR_HIP, "dependency wait timed out");
+  if (hinfo) return c->fail(PD_ERR_NOT_SPD, "non-positive pivot at %d", hinfo);
+  if (!(rr <= c->ir_tol))
+    return c->fail(PD_ERR_IR_STALLED, "refinement reached %.3e after %d steps", rr, it);
   return PD_OK;
 }
 
@@ -850,10 +1032,35 @@ pd_status pd_inner_update(pd_ctx* c, const double* u2, double* x2, double* delta
   if (bad_ctx(c) || !u2 || !x2 || !delta2 || !ft) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
   const int m = (int)c->m;
+  PhaseTimer tm(c, PD_PHASE_INNER_UPDATE);
   inner_update(m, u2, x2, delta2, c->st);
   symv3(c->d_S, m, m, u2, m, -1.0, 1.0, ft, m, c->st);
   if (c->nbeta > 0) csr_spmv3(m, c->d_Abptr, c->d_Abcol, c->d_Abval, u2, m, 1.0, ft, m, ft, m, c->st);
   return c->check("pd_inner_update");
+}
+
+pd_status pd_set_timing(pd_ctx* c, int on) {
+  if (bad_ctx(c)) return PD_ERR_INVALID;
+  c->timing = on != 0;
+  return PD_OK;
+}
+
+pd_status pd_get_timings(pd_ctx* c, double* ms, int64_t* counts) {
+  if (bad_ctx(c) || !ms) return PD_ERR_INVALID;
+  HIPCK(c, hipStreamSynchronize(c->st));
+  for (int p = 0; p < PD_N_PHASES; ++p) {
+    ms[p] = 0.0;
+    if (counts) counts[p] = 0;
+  }
+  for (auto& pr : c->ev_pairs) {
+    float t = 0.f;
+    HIPCK(c, hipEventElapsedTime(&t, c->ev_pool[pr.second.first], c->ev_pool[pr.second.second]));
+    ms[pr.first] += t;
+    if (counts) counts[pr.first] += 1;
+  }
+  c->ev_pairs.clear();
+  c->ev_used = 0;
+  return PD_OK;
 }
 
 const char* pd_last_error(const pd_ctx* c) {

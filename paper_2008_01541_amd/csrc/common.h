@@ -17,6 +17,10 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // dense FP64
 void copy_lower_tiles(const double* S, int lds, double* H, int ldh, int n, hipStream_t st);
 void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStream_t st);
+// Single-launch dataflow Cholesky; flags: nt*nt ints (zero-initialised once,
+// epoch strictly increasing per call), ticket: one counter reset by the call.
+void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
+                    int epoch, int* info, int* err, int n_wg, hipStream_t st);
 void trtri_from_factor(const double* L, int ldl, int n, const double* linv_ws, double* M,
                        double* X, int ldx, hipStream_t st);
 void lauum_full(const double* X, int ldx, int n, double* Z, int ldz, hipStream_t st);
@@ -29,6 +33,16 @@ void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const
 // y = alpha * A v + beta * y for symmetric A (full storage), 3 right-hand sides.
 void symv3(const double* A, int lda, int n, const double* v, int ldv, double alpha,
            double beta, double* y, int ldy, hipStream_t st);
+
+// low precision (FP32 / BF16-operand) factor of the equilibrated system
+void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, int* flags, unsigned* ticket,
+                       int epoch, int* info, int* err, int n_wg, bool bf16, hipStream_t st);
+void equilibrate_convert(const double* H, int ld, int n, double* d, float* H32, int ld32,
+                         hipStream_t st);
+// x (+)= D L^-T L^-1 D r with L the FP32 factor of D H D (three right-hand sides).
+void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const double* d,
+                    const double* r, float* y, float* xs, double* x, int accumulate,
+                    unsigned long long* tickets, int* flags, int* err, hipStream_t st);
 
 // FEM / sparse
 void tet_geometry(const double* rest, int64_t n, const int32_t* tets, int64_t T,
@@ -50,7 +64,7 @@ void scatter_add_rows3(int64_t count, const int32_t* ids, const double* src, int
 void csr_spmv3(int64_t rows, const int32_t* ptr, const int32_t* col, const double* val,
                const double* v, int64_t ldv, double alpha, double* y, int64_t ldy,
                const double* base, int64_t ldbase, hipStream_t st);
-void dense_times_sparse_t(const double* Z, int w, int nr, const int32_t* rows,
+void dense_times_sparse_t(const double* Z, int ldz, int w, int nr, const int32_t* rows,
                           const int32_t* ptr, const int32_t* col, const double* val,
                           double* U, hipStream_t st);
 void sub_sparse_times_dense(double* Next, int ldn, int nr, const int32_t* rows,

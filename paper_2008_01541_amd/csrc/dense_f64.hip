@@ -3,6 +3,7 @@
 // three-right-hand-side triangular solves and the symmetric matrix-vector
 // product.  Tiles are NB x NB (NB = 64), column-major.  Products run on the
 // FP64 matrix cores (v_mfma_f64_16x16x4f64) with operands staged through LDS.
+#include <algorithm>
 #include <climits>
 #include "common.h"
 
@@ -10,6 +11,13 @@ namespace pdk {
 
 constexpr int KC = 16;           // K-chunk staged through LDS per step
 constexpr int LDS_LD = NB + 4;   // padded LDS row (doubles)
+
+__device__ inline double coherent_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void coherent_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 struct Acc {                     // one wave's 32 x 32 share of a 64 x 64 tile
   double4_t c[2][2];
@@ -96,31 +104,19 @@ __device__ void gemm_acc(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
 // ---------------------------------------------------------------------------
 // Cholesky building blocks
 
-// Factor diagonal tile k in place (lower) and write its inverse (64x64, lower,
-// identity-padded past the matrix edge) to linv_ws + k*NB*NB.  A non-positive
-// pivot stores its 1-based global index in *info (first one wins) and is
-// replaced by 1 so that the factorization stays finite.
-__global__ __launch_bounds__(256) void k_potrf_diag(double* A, int lda, int n, int k,
-                                                    double* linv_ws, int* info) {
-  __shared__ double T[NB][NB + 1];   // T[c][r] = tile(r, c)
-  __shared__ double X[NB][NB + 1];   // X[c][r] = inverse(r, c)
-  __shared__ double inv_d[NB];
+// Cholesky of a 64 x 64 tile held in LDS (T[c][r] = tile(r, c), lower part
+// valid, rows/cols >= mr padded with the identity) and the inverse of the
+// factor into X (X[c][r] = inverse(r, c), zero above the diagonal).  A
+// non-positive pivot stores its 1-based global index gbase + j + 1 in *info
+// (first one wins) and is replaced by 1 so that the factorization stays finite.
+__device__ void factor_tile_lds(double (*T)[LDS_LD], double (*X)[LDS_LD], double* inv_d, int mr,
+                                int gbase, int* info) {
   const int t = threadIdx.x;
-  const int r0 = k * NB;
-  const int mr = min(NB, n - r0);
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    double v;
-    if (r < mr && c < mr) v = (r >= c) ? A[(long)(r0 + r) + (long)(r0 + c) * lda] : 0.0;
-    else v = (r == c) ? 1.0 : 0.0;
-    T[c][r] = v;
-  }
-  __syncthreads();
   for (int j = 0; j < NB; ++j) {
     __syncthreads();                       // trailing update of step j-1 complete
     double d = T[j][j];
     if (!(d > 0.0)) {
-      if (t == 0 && j < mr) atomicCAS(info, 0, r0 + j + 1);
+      if (t == 0 && j < mr) atomicCAS(info, 0, gbase + j + 1);
       d = 1.0;
     }
     const double ljj = sqrt(d);
@@ -152,6 +148,29 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int lda, int n, i
     }
   }
   __syncthreads();
+}
+
+__device__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
+                                    int* info);
+
+// Factor diagonal tile k in place (lower) and write its inverse (64x64, lower,
+// identity-padded past the matrix edge) to linv_ws + k*NB*NB.
+__global__ __launch_bounds__(256) void k_potrf_diag(double* A, int lda, int n, int k,
+                                                    double* linv_ws, int* info) {
+  __shared__ double T[NB][LDS_LD];
+  __shared__ double X[NB][LDS_LD];
+  __shared__ double inv_d[NB];
+  const int t = threadIdx.x;
+  const int r0 = k * NB;
+  const int mr = min(NB, n - r0);
+  for (int e = t; e < NB * NB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    double v;
+    if (r < mr && c < mr) v = (r >= c) ? A[(long)(r0 + r) + (long)(r0 + c) * lda] : 0.0;
+    else v = (r == c) ? 1.0 : 0.0;
+    T[c][r] = v;
+  }
+  factor_tile_blocked(T, X, mr, r0, info);
   double* Li = linv_ws + (long)k * NB * NB;
   for (int e = t; e < NB * NB; e += 256) {
     const int r = e & 63, c = e >> 6;
@@ -215,6 +234,375 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* A, int lda, int n, 
       }
 }
 
+// ---------------------------------------------------------------------------
+// Single-launch tiled Cholesky.  Persistent workgroups claim lower tiles in
+// column-major order from a ticket counter; the workgroup that owns tile
+// (i, j) accumulates sum_{k<j} L_ik L_jk^T on the matrix cores as soon as each
+// pair of operand tiles is published (operands double-buffered through LDS
+// with the next chunk's loads in flight during the current products), then
+// either factors the diagonal tile (blocked, in LDS) and publishes L_jj and its
+// inverse, or waits for Linv_jj and forms L_ij = (A_ij - acc) Linv_jj^T.  Each
+// factor tile is also written transposed into the upper triangle, so the
+// backward substitution reads L^T with unit stride.  A task only waits on
+// tasks with a smaller ticket, all of which belong to running workgroups, so
+// the schedule cannot deadlock; waits are bounded and raise *err instead.
+constexpr long SPIN_LIMIT_DF = 1L << 24;
+constexpr int KCD = 32;                 // K chunk of the pipelined accumulation
+
+// Cross-workgroup publication protocol.  Tiles, tile inverses and solve
+// vectors are written with agent-coherent (write-through) stores; after every
+// thread's stores have completed (s_waitcnt vmcnt(0)) and a barrier, one
+// thread stores the ready flag.  Consumers poll flags with agent-coherent
+// loads.  Published data is immutable for the rest of the launch, its cache
+// lines are never touched before publication by other workgroups (tiles are
+// 128-byte aligned: leading dimensions are multiples of 16 doubles, and the
+// owner reads its input tile with coherent loads), so plain cached loads of
+// published data cannot see stale lines and no cache invalidation is needed.
+__device__ inline void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }   // vmcnt(0)
+
+__device__ inline bool df_wait(const int* f, int epoch, int* err) {
+  long spins = 0;
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > SPIN_LIMIT_DF) {
+      atomicExch(err, 1);
+      return false;
+    }
+  }
+  return true;
+}
+
+__device__ inline void publish_flag(int* f, int epoch) {
+  wait_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_reset_counter(unsigned* ctr) { *ctr = 0u; }
+
+// Blocked (16 x 16) Cholesky of the LDS tile T (T[c][r] = tile(r, c), lower,
+// identity-padded past mr) and the inverse of the factor into X.
+__device__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
+                                    int* info) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int kb = 0; kb < 4; ++kb) {
+    const int b0 = kb * 16;
+    if (w == 0) {                          // 16 x 16 diagonal block, lane r holds row r
+      const int r = lane & 15;
+      double a[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = T[b0 + c][b0 + r];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double d = __shfl(a[c], c, 64);
+        if (!(d > 0.0)) {
+          if (lane == 0 && b0 + c < mr) atomicCAS(info, 0, gbase + b0 + c + 1);
+          d = 1.0;
+        }
+        const double l = sqrt(d), il = 1.0 / l;
+        if (r == c) a[c] = l;
+        else if (r > c) a[c] *= il;
+#pragma unroll
+        for (int s2 = c + 1; s2 < 16; ++s2) {
+          const double xs = __shfl(a[c], s2, 64);
+          if (r >= s2) a[s2] -= a[c] * xs;
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c <= r) T[b0 + c][b0 + r] = a[c];
+      }
+    }
+    __syncthreads();
+    const int nrow = NB - b0 - 16;
+    if (t < nrow) {                        // panel rows below: x L_D^T = row
+      const int rr = b0 + 16 + t;
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double sacc = T[b0 + c][rr];
+#pragma unroll
+        for (int p = 0; p < c; ++p) sacc -= x[p] * T[b0 + p][b0 + c];
+        x[c] = sacc / T[b0 + c][b0 + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) T[b0 + c][rr] = x[c];
+    }
+    __syncthreads();
+    if (nrow > 0) {                        // trailing update of the lower part
+      for (int e = t; e < nrow * nrow; e += 256) {
+        const int r = b0 + 16 + e % nrow, c = b0 + 16 + e / nrow;
+        if (r >= c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int p = 0; p < 16; ++p) acc += T[b0 + p][r] * T[b0 + p][c];
+          T[c][r] -= acc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // inverse: diagonal 16-blocks (wave b, lane c computes column c of block b)
+  {
+    const int b0 = w * 16, c = lane & 15;
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double sacc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int p = 0; p < r; ++p) sacc -= T[b0 + p][b0 + r] * x[p];
+      x[r] = (r >= c) ? sacc / T[b0 + r][b0 + r] : 0.0;
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) X[b0 + c][b0 + r] = x[r];
+    }
+    // zero the blocks above the diagonal
+    for (int e = lane; e < 16 * 48; e += 64) {
+      const int r = e & 15, cb = 16 + (e >> 4);      // column index 16..63
+      const int col = cb, row = b0 + r;
+      if (col >= b0 + 16) X[col][row] = 0.0;
+    }
+  }
+  __syncthreads();
+  // off-diagonal 16-blocks, block row ib: X_ib,jb = -X_ib,ib sum_pb L_ib,pb X_pb,jb
+  for (int ib = 1; ib < 4; ++ib) {
+    const int rb = 16 * ib, cnt = 16 * rb;
+    double y[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = t + 256 * q;
+      y[q] = 0.0;
+      if (e < cnt) {
+        const int r = e & 15, c = e >> 4;           // c in [0, rb)
+        const int p0 = (c >> 4) * 16;
+        double acc = 0.0;
+        for (int p = p0; p < rb; ++p) acc += T[p][rb + r] * X[c][p];
+        y[q] = acc;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = t + 256 * q;
+      if (e < cnt) X[e >> 4][rb + (e & 15)] = y[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = t + 256 * q;
+      y[q] = 0.0;
+      if (e < cnt) {
+        const int r = e & 15, c = e >> 4;
+        double acc = 0.0;
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) acc += X[rb + qq][rb + r] * X[c][rb + qq];
+        y[q] = -acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = t + 256 * q;
+      if (e < cnt) X[e >> 4][rb + (e & 15)] = y[q];
+    }
+    __syncthreads();
+  }
+}
+
+// acc += sum_{k<j} L_ik L_jk^T with double-buffered operand chunks.
+__device__ bool df_accumulate(Acc& acc, double (*buf)[KCD][LDS_LD], const double* __restrict__ A,
+                              int lda, int r0, int mr, int c0, int mc, int i, int j, int nt,
+                              const int* flags, int epoch, int* err, int* s_ok) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int r = t & 63, kq = t >> 6;
+  double (*Ab[2])[LDS_LD] = {buf[0], buf[1]};
+  double (*Bb[2])[LDS_LD] = {buf[2], buf[3]};
+  const int nch = 2 * j;
+  double ra[8], rb[8];
+  auto wait_k = [&](int k) -> bool {
+    if (t == 0) {
+      if (!df_wait(&flags[i * nt + k], epoch, err) || !df_wait(&flags[j * nt + k], epoch, err))
+        *s_ok = 0;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+  };
+  auto prefetch = [&](int ch) {
+    const long kabs = (long)(ch >> 1) * NB + (ch & 1) * KCD;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const long col = (kabs + kq + 4 * q) * lda;
+#ifdef PD_COHERENT_OPERAND_LOADS
+      ra[q] = (r < mr) ? coherent_load(&A[(long)(r0 + r) + col]) : 0.0;
+      rb[q] = (r < mc) ? coherent_load(&A[(long)(c0 + r) + col]) : 0.0;
+#else
+      ra[q] = (r < mr) ? A[(long)(r0 + r) + col] : 0.0;
+      rb[q] = (r < mc) ? A[(long)(c0 + r) + col] : 0.0;
+#endif
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      Ab[b][kq + 4 * q][r] = ra[q];
+      Bb[b][kq + 4 * q][r] = rb[q];
+    }
+  };
+  if (nch == 0) return true;
+  if (!wait_k(0)) return false;
+  prefetch(0);
+  store(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const bool nxt = ch + 1 < nch;
+    if (nxt) {
+      if (((ch + 1) & 1) == 0 && !wait_k((ch + 1) >> 1)) return false;
+      prefetch(ch + 1);
+    }
+    const int b = ch & 1;
+#pragma unroll
+    for (int ks = 0; ks < KCD / 4; ++ks) {
+      const int k = ks * 4 + (lane >> 4);
+      const double a0 = Ab[b][k][wr * 32 + (lane & 15)];
+      const double a1 = Ab[b][k][wr * 32 + 16 + (lane & 15)];
+      const double b0 = Bb[b][k][wc * 32 + (lane & 15)];
+      const double b1 = Bb[b][k][wc * 32 + 16 + (lane & 15)];
+      acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
+      acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
+      acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
+      acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
+    }
+    if (nxt) store(b ^ 1);
+    __syncthreads();
+  }
+  return true;
+}
+
+__global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, int n, int nt,
+                                                           double* linv_ws, int* flags,
+                                                           unsigned* ticket, int epoch, int* info,
+                                                           int* err) {
+  // 4 x 32 x 68 doubles = 69,632 bytes; reused as two 64 x 68 tiles after the accumulation
+  __shared__ double smem[4][KCD][LDS_LD];
+  __shared__ int s_task, s_ok;
+  double (*buf0)[LDS_LD] = (double (*)[LDS_LD]) & smem[0][0][0];
+  double (*buf1)[LDS_LD] = (double (*)[LDS_LD]) & smem[2][0][0];
+  const int t = threadIdx.x;
+  const int lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int ntask = nt * (nt + 1) / 2;
+  for (;;) {
+    __syncthreads();
+    if (t == 0) {
+      s_task = (int)atomicAdd(ticket, 1u);
+      s_ok = 1;
+    }
+    __syncthreads();
+    const int q = s_task;
+    if (q >= ntask) return;
+    int j = 0, start = 0;
+    while (start + (nt - j) <= q) {
+      start += nt - j;
+      ++j;
+    }
+    const int i = j + (q - start);
+    const int r0 = i * NB, c0 = j * NB;
+    const int mr = min(NB, n - r0), mc = min(NB, n - c0);
+    Acc acc;
+    acc_zero(acc);
+    if (!df_accumulate(acc, smem, A, lda, r0, mr, c0, mc, i, j, nt, flags, epoch, err, &s_ok))
+      return;
+    __syncthreads();
+    // C = A_ij - acc  ->  buf0[c][r]; padding: identity on the diagonal tile, zero elsewhere
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          const int r = acc_row(mb), c = acc_col(nb, qq);
+          double v;
+          if (r < mr && c < mc)
+            v = coherent_load(&A[(long)(r0 + r) + (long)(c0 + c) * lda]) - acc.c[mb][nb][qq];
+          else v = (i == j && r == c) ? 1.0 : 0.0;
+          buf0[c][r] = v;
+        }
+    __syncthreads();
+    if (i == j) {
+      factor_tile_blocked(buf0, buf1, mr, r0, info);
+      double* Li = linv_ws + (long)j * NB * NB;
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        coherent_store(&Li[e], buf1[c][r]);
+        // lower: L; strictly upper: L^T (transposed copy for the backward solve)
+        if (r < mr && c < mr)
+          coherent_store(&A[(long)(r0 + r) + (long)(r0 + c) * lda], (r >= c) ? buf0[c][r] : buf0[r][c]);
+      }
+    } else {
+      if (t == 0 && !df_wait(&flags[j * nt + j], epoch, err)) s_ok = 0;
+      __syncthreads();
+      if (!s_ok) return;
+      const double* Li = linv_ws + (long)j * NB * NB;
+      for (int e = t; e < NB * NB; e += 256) buf1[e >> 6][e & 63] = Li[e];   // buf1[kk][c] = Linv(c, kk)
+      __syncthreads();
+      acc_zero(acc);
+#pragma unroll 4
+      for (int ks = 0; ks < NB / 4; ++ks) {
+        const int k = ks * 4 + (lane >> 4);
+        const double a0 = buf0[k][wr * 32 + (lane & 15)];
+        const double a1 = buf0[k][wr * 32 + 16 + (lane & 15)];
+        const double b0 = buf1[k][wc * 32 + (lane & 15)];
+        const double b1 = buf1[k][wc * 32 + 16 + (lane & 15)];
+        acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
+        acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
+        acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
+        acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) buf0[acc_col(nb, qq)][acc_row(mb)] = acc.c[mb][nb][qq];
+      __syncthreads();
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (r < mr) coherent_store(&A[(long)(r0 + r) + (long)(c0 + c) * lda], buf0[c][r]);
+        // transposed copy: U(c0 + r', r0 + c') = L(r0 + c', c0 + r') with r' = e & 63, c' = e >> 6
+        if (c < mr) coherent_store(&A[(long)(c0 + r) + (long)(r0 + c) * lda], buf0[r][c]);
+      }
+    }
+    publish_flag(&flags[i * nt + j], epoch);
+  }
+}
+
+void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
+                    int epoch, int* info, int* err, int n_wg, hipStream_t st) {
+  const int nt = (n + NB - 1) / NB;
+  const int ntask = nt * (nt + 1) / 2;
+  k_reset_counter<<<1, 1, 0, st>>>(ticket);
+  k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags, ticket,
+                                                          epoch, info, err);
+}
+
+// Upper triangle <- transpose of the strictly lower triangle (tiles (j, i), i > j,
+// and the strictly upper part of diagonal tiles).
+__global__ __launch_bounds__(256) void k_mirror_lower(double* A, int lda, int n) {
+  int i, j;
+  tri_index(blockIdx.x, i, j);
+  const int r0 = i * NB, c0 = j * NB;
+  const int mr = min(NB, n - r0), mc = min(NB, n - c0);
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int c = e & 63, r = e >> 6;        // write U(c0 + c, r0 + r) = L(r0 + r, c0 + c)
+    if (r < mr && c < mc && (i != j || r > c))
+      A[(long)(c0 + c) + (long)(r0 + r) * lda] = A[(long)(r0 + r) + (long)(c0 + c) * lda];
+  }
+}
+
 void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStream_t st) {
   const int nt = (n + NB - 1) / NB;
   for (int k = 0; k < nt; ++k) {
@@ -225,6 +613,7 @@ void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStrea
       k_syrk_update<<<R * (R + 1) / 2, 256, 0, st>>>(A, lda, n, k);
     }
   }
+  k_mirror_lower<<<nt * (nt + 1) / 2, 256, 0, st>>>(A, lda, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,7 +747,7 @@ constexpr long SPIN_LIMIT = 1L << 24;
 
 __device__ inline bool wait_flag(int* f, int epoch, int* err) {
   long spins = 0;
-  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     __builtin_amdgcn_s_sleep(1);
     if (++spins > SPIN_LIMIT) {
@@ -369,20 +758,13 @@ __device__ inline bool wait_flag(int* f, int epoch, int* err) {
   return true;
 }
 
-__device__ inline double coherent_load(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void coherent_store(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// L y = g.
+// L y = g.  Row block i: y_i = Linv_ii (g_i - sum_{p<i} L_ip y_p).
 __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L, int ld, int n,
                                                    int nt, const double* __restrict__ linv,
                                                    const double* __restrict__ g, int ldg,
@@ -392,6 +774,7 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L,
   __shared__ int s_row, s_epoch, s_ok;
   __shared__ double ys[3][NB];
   __shared__ double part[4][3][NB];
+  __shared__ double Ls[NB][NB + 1];          // Ls[c][r] = Linv_ii(r, c)
   const int t = threadIdx.x;
   if (t == 0) {
     const unsigned long long tk = atomicAdd(ticket, 1ull);
@@ -403,23 +786,37 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L,
   const int i = s_row, epoch = s_epoch;
   const int r0 = i * NB, mr = min(NB, n - r0);
   const int r = t & 63, cg = t >> 6;
+  {
+    const double* Li = linv + (long)i * NB * NB;
+    for (int e = t; e < NB * NB; e += 256) Ls[e >> 6][e & 63] = Li[e];
+  }
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  for (int p = 0; p < i; ++p) {
-    double lv[16];
+  double lv[16];
+  if (i > 0) {
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-      lv[q] = (r < mr) ? L[(long)(r0 + r) + (long)(p * NB + cg * 16 + q) * ld] : 0.0;
+      lv[q] = (r < mr) ? L[(long)(r0 + r) + (long)(cg * 16 + q) * ld] : 0.0;
+  }
+  for (int p = 0; p < i; ++p) {
     if (t == 0 && !wait_flag(&flags[p], epoch, err)) s_ok = 0;
     __syncthreads();
     if (!s_ok) return;
     if (t < 3 * NB) ys[t >> 6][t & 63] = coherent_load(&y[(long)(t >> 6) * ldy + p * NB + (t & 63)]);
     __syncthreads();
+    double cur[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cur[q] = lv[q];
+    if (p + 1 < i) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        lv[q] = (r < mr) ? L[(long)(r0 + r) + (long)((p + 1) * NB + cg * 16 + q) * ld] : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int c = cg * 16 + q;
-      a0 += lv[q] * ys[0][c];
-      a1 += lv[q] * ys[1][c];
-      a2 += lv[q] * ys[2][c];
+      a0 += cur[q] * ys[0][c];
+      a1 += cur[q] * ys[1][c];
+      a2 += cur[q] * ys[2][c];
     }
     __syncthreads();
   }
@@ -433,19 +830,22 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L,
     ys[v][rr] = b - (part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr]);
   }
   __syncthreads();
-  const double* Li = linv + (long)i * NB * NB;
   if (t < 3 * NB) {
     const int v = t >> 6, rr = t & 63;
-    double s = 0.0;
-    for (int c = 0; c <= rr; ++c) s += Li[rr + c * NB] * ys[v][c];
-    if (rr < mr) coherent_store(&y[(long)v * ldy + r0 + rr], s);
+    double s0 = 0.0, s1 = 0.0;
+    int c = 0;
+    for (; c + 1 <= rr; c += 2) {
+      s0 += Ls[c][rr] * ys[v][c];
+      s1 += Ls[c + 1][rr] * ys[v][c + 1];
+    }
+    if (c <= rr) s0 += Ls[c][rr] * ys[v][c];
+    if (rr < mr) coherent_store(&y[(long)v * ldy + r0 + rr], s0 + s1);
   }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) __hip_atomic_store(&flags[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  publish_flag(&flags[i], epoch);
 }
 
-// L^T x = y.
+// L^T x = y, reading L^T from the upper triangle (U(r, c) = L(c, r) for c > r):
+// x_i = Linv_ii^T (y_i - sum_{p>i} U_ip x_p).
 __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L, int ld, int n,
                                                    int nt, const double* __restrict__ linv,
                                                    const double* __restrict__ y, int ldy,
@@ -455,6 +855,7 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L,
   __shared__ int s_row, s_epoch, s_ok;
   __shared__ double xs[3][NB];
   __shared__ double part[4][3][NB];
+  __shared__ double Ls[NB][NB + 1];          // Ls[c][r] = Linv_ii(r, c)
   const int t = threadIdx.x;
   if (t == 0) {
     const unsigned long long tk = atomicAdd(ticket, 1ull);
@@ -465,18 +866,24 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L,
   __syncthreads();
   const int i = s_row, epoch = s_epoch;
   const int r0 = i * NB, mr = min(NB, n - r0);
-  const int c = t & 63, rg = t >> 6;     // lane walks down a column of L
-  double acc[16][3];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
-  for (int p = nt - 1; p > i; --p) {
-    const int pr0 = p * NB, pmr = min(NB, n - pr0);
-    double lv[16];
+  const int r = t & 63, cg = t >> 6;
+  {
+    const double* Li = linv + (long)i * NB * NB;
+    for (int e = t; e < NB * NB; e += 256) Ls[e >> 6][e & 63] = Li[e];
+  }
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  double lv[16];
+  auto load_tile = [&](int p) {
+    const int pr0 = p * NB;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int rr = rg + 4 * q;
-      lv[q] = (c < pmr && rr < mr) ? L[(long)(pr0 + c) + (long)(r0 + rr) * ld] : 0.0;
+      const int col = pr0 + cg * 16 + q;
+      lv[q] = (r < mr && col < n) ? L[(long)(r0 + r) + (long)col * ld] : 0.0;
     }
+  };
+  if (i < nt - 1) load_tile(nt - 1);
+  for (int p = nt - 1; p > i; --p) {
+    const int pr0 = p * NB, pmr = min(NB, n - pr0);
     if (t == 0 && !wait_flag(&flags[p], epoch, err)) s_ok = 0;
     __syncthreads();
     if (!s_ok) return;
@@ -485,43 +892,42 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L,
       xs[v][cc] = (cc < pmr) ? coherent_load(&x[(long)v * ldx + pr0 + cc]) : 0.0;
     }
     __syncthreads();
+    double cur[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cur[q] = lv[q];
+    if (p - 1 > i) load_tile(p - 1);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      acc[q][0] += lv[q] * xs[0][c];
-      acc[q][1] += lv[q] * xs[1][c];
-      acc[q][2] += lv[q] * xs[2][c];
+      const int c = cg * 16 + q;
+      a0 += cur[q] * xs[0][c];
+      a1 += cur[q] * xs[1][c];
+      a2 += cur[q] * xs[2][c];
     }
     __syncthreads();
   }
-  // reduce over the 64 lanes (c) of each wave
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const double s0 = wave_sum(acc[q][0]);
-    const double s1 = wave_sum(acc[q][1]);
-    const double s2 = wave_sum(acc[q][2]);
-    if (c == 0) {
-      part[0][0][rg + 4 * q] = s0;
-      part[0][1][rg + 4 * q] = s1;
-      part[0][2][rg + 4 * q] = s2;
-    }
-  }
+  part[cg][0][r] = a0;
+  part[cg][1][r] = a1;
+  part[cg][2][r] = a2;
   __syncthreads();
   if (t < 3 * NB) {
     const int v = t >> 6, rr = t & 63;
     const double b = (rr < mr) ? y[(long)v * ldy + r0 + rr] : 0.0;
-    xs[v][rr] = b - part[0][v][rr];
+    xs[v][rr] = b - (part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr]);
   }
   __syncthreads();
-  const double* Li = linv + (long)i * NB * NB;
   if (t < 3 * NB) {
     const int v = t >> 6, rr = t & 63;
-    double s = 0.0;
-    for (int cc = rr; cc < NB; ++cc) s += Li[cc + rr * NB] * xs[v][cc];
-    if (rr < mr) coherent_store(&x[(long)v * ldx + r0 + rr], s);
+    // (Linv^T b)_rr = sum_{c >= rr} Linv(c, rr) b_c = sum_c Ls[rr][c] b_c
+    double s0 = 0.0, s1 = 0.0;
+    int c = rr;
+    for (; c + 1 < NB; c += 2) {
+      s0 += Ls[rr][c] * xs[v][c];
+      s1 += Ls[rr][c + 1] * xs[v][c + 1];
+    }
+    if (c < NB) s0 += Ls[rr][c] * xs[v][c];
+    if (rr < mr) coherent_store(&x[(long)v * ldx + r0 + rr], s0 + s1);
   }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) __hip_atomic_store(&flags[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  publish_flag(&flags[i], epoch);
 }
 
 void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const double* g,

@@ -390,7 +390,7 @@ void csr_spmv3(int64_t rows, const int32_t* ptr, const int32_t* col, const doubl
 }
 
 // U[i + jr*w] = sum_{e in row rows[jr] of B} val[e] * Z[i + col[e]*w]   (U = Z B^T on the rows)
-__global__ void k_dense_times_sparse_t(const double* __restrict__ Z, int w, int nr,
+__global__ void k_dense_times_sparse_t(const double* __restrict__ Z, int ldz, int w, int nr,
                                        const int32_t* __restrict__ rows,
                                        const int32_t* __restrict__ ptr,
                                        const int32_t* __restrict__ col,
@@ -400,15 +400,16 @@ __global__ void k_dense_times_sparse_t(const double* __restrict__ Z, int w, int 
   if (i >= w || jr >= nr) return;
   const int rr = rows[jr];
   double s = 0.0;
-  for (int32_t e = ptr[rr]; e < ptr[rr + 1]; ++e) s += val[e] * Z[(int64_t)i + (int64_t)col[e] * w];
+  for (int32_t e = ptr[rr]; e < ptr[rr + 1]; ++e) s += val[e] * Z[(int64_t)i + (int64_t)col[e] * ldz];
   U[(int64_t)i + (int64_t)jr * w] = s;
 }
 
-void dense_times_sparse_t(const double* Z, int w, int nr, const int32_t* rows, const int32_t* ptr,
-                          const int32_t* col, const double* val, double* U, hipStream_t st) {
+void dense_times_sparse_t(const double* Z, int ldz, int w, int nr, const int32_t* rows,
+                          const int32_t* ptr, const int32_t* col, const double* val, double* U,
+                          hipStream_t st) {
   if (w > 0 && nr > 0) {
     dim3 g(grid1(w), nr);
-    k_dense_times_sparse_t<<<g, 256, 0, st>>>(Z, w, nr, rows, ptr, col, val, U);
+    k_dense_times_sparse_t<<<g, 256, 0, st>>>(Z, ldz, w, nr, rows, ptr, col, val, U);
   }
 }
 

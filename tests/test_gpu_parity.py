@@ -205,3 +205,40 @@ def test_invalid_mesh_rejected(torch_cuda):
         PDContext(sc.rest, flipped, sc.region, sc.dirichlet, sc.mu)
     with pytest.raises(PDError):
         PDContext(sc.rest, sc.tets, np.zeros(sc.n_nodes, bool), sc.dirichlet, sc.mu)
+
+
+@pytest.mark.parametrize("name", ["cube8", "g16x15x8"])
+@pytest.mark.parametrize("prec", [1, 2])
+def test_refined_solve(torch_cuda, name, prec):
+    """FP32 / BF16-operand factor + FP64-residual refinement: residual <= 1e-8
+    (recomputed here by the oracle in FP64) and error <= kappa * 1e-8."""
+    import scipy.linalg as sla
+    sc = SMALL_SCENES[name]()
+    om = oracle_model(sc)
+    ctx = gpu_context(sc)
+    m = ctx.m
+    rng = np.random.default_rng(31)
+    npen = min(20, m)
+    sel = rng.choice(m, size=npen, replace=False)
+    idx = np.full((npen, 8), -1, dtype=np.int32)
+    idx[:, 0] = sel
+    w = np.zeros((npen, 8)); w[:, 0] = 1.0
+    c = np.full(npen, 1e6)
+    t = rng.normal(size=(3, npen))
+    x2 = sc.rest[:, om.i2]
+    fcol = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), dev(x2), fcol)
+    g = rng.normal(size=(3, m))
+    u = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    info = ctx.global_solve(dev(g), u, prec=prec, want_info=True)
+    H = om.schur() + ocol.penalty_matrix(m, idx, w, c)
+    ug = host(u, (3, -1))
+    r = g - (H @ ug.T).T
+    relres = max(np.linalg.norm(r[v]) / np.linalg.norm(g[v]) for v in range(3))
+    assert info["status"] == 0, info
+    assert relres <= 1e-8 and info["rel_residual"] <= 1e-8
+    ev = np.linalg.eigvalsh(H)
+    kappa = ev[-1] / ev[0]
+    u_or = sla.cho_solve(sla.cho_factor(H, lower=True), g.T).T
+    assert np.linalg.norm(ug - u_or) <= kappa * 1e-8 * np.linalg.norm(u_or)
+    assert info["ir_iters"] >= 1
