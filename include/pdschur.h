@@ -205,6 +205,14 @@ pd_status pd_mlp_train_step(pd_mlp *mlp, const float *x, const float *target, in
 
 pd_status pd_mlp_destroy(pd_mlp *mlp);
 
+/* Moves the context to another HIP stream (after synchronizing the current
+ * one).  Every entry point that does not synchronize (the FP64 path without
+ * info, and everything but pd_schur_build, pd_displacement_change and
+ * pd_get_timings) only enqueues kernels and device-to-device copies on the
+ * stream, so a sequence of them can be captured into a HIP graph and
+ * replayed; the dataflow kernels take their epochs from device memory. */
+pd_status pd_set_stream(pd_ctx *ctx, void *hip_stream);
+
 /* Phases timed by pd_get_timings. */
 typedef enum {
   PD_PHASE_LOCAL_FULL = 0,    /* pd_local_step_full */
@@ -229,6 +237,25 @@ pd_status pd_set_timing(pd_ctx *ctx, int on);
  * (host ms[PD_N_PHASES]) and the number of timed calls (host counts, may be
  * NULL) since the previous call; then clears the records. */
 pd_status pd_get_timings(pd_ctx *ctx, double *ms, int64_t *counts);
+
+/* Warm-start network input for the next frame (float32, dev [4m]):
+ * [scale (x2 - x2_prev) (coordinate-major, 3m) ; mask (m)], mask = 1 at the
+ * region nodes prox[j] whose penalty stiffness cpen[j] is non-zero (e.g. the
+ * c output of pd_detect_spheres at the start of the frame). */
+pd_status pd_warmstart_input(pd_ctx *ctx, const double *x2, const double *x2_prev, float scale,
+                             int32_t n_prox, const int32_t *prox, const double *cpen,
+                             float *out);
+
+/* x[:, region] += scale * d2 for a float32 region increment d2 (dev [3][m]),
+ * x dev [3][n_nodes]: applies a predicted displacement to the region nodes. */
+pd_status pd_region_add_f32(pd_ctx *ctx, const float *d2, double scale, double *x);
+
+/* Convergence measure of an outer iteration: out[0] = ||x - x_prev||_2 and
+ * out[1] = ||x - X||_2 over all free nodes (X = rest positions), for the
+ * relative-change test ||x_k - x_{k-1}|| / ||x_k - X|| <= tol.  x, x_prev:
+ * dev [3][n_nodes]; out: host [2].  Synchronizes. */
+pd_status pd_displacement_change(pd_ctx *ctx, const double *x, const double *x_prev,
+                                 double *out);
 
 /* Last error message of the context (valid until the next call on it).
  * With ctx = NULL: the message of the last failed pd_schur_build on this thread. */

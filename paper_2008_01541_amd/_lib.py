@@ -54,6 +54,10 @@ _SIGS = {
     "pd_mlp_forward": [_P, _P, _P, C.c_int32],
     "pd_mlp_train_step": [_P, _P, _P, C.c_int32, C.c_float, C.POINTER(C.c_double), _P],
     "pd_mlp_destroy": [_P],
+    "pd_displacement_change": [_P, _P, _P, _P],
+    "pd_warmstart_input": [_P, _P, _P, C.c_float, C.c_int32, _P, _P, _P],
+    "pd_region_add_f32": [_P, _P, C.c_double, _P],
+    "pd_set_stream": [_P, _P],
     "pd_set_timing": [_P, C.c_int],
     "pd_get_timings": [_P, _P, _P],
     "pd_destroy": [_P],
@@ -235,6 +239,33 @@ class PDContext:
             _ptr(delta2, torch.float64, 3 * self.m, "delta2"),
             _ptr(ft, torch.float64, 3 * self.m, "ft")))
 
+    def displacement_change(self, x, x_prev):
+        """(||x - x_prev||, ||x - X||) over the free nodes (synchronizes)."""
+        import torch
+        out = np.zeros(2, dtype=np.float64)
+        self._chk(self._lib.pd_displacement_change(
+            self._ctx, _ptr(x, torch.float64, 3 * self.n, "x"),
+            _ptr(x_prev, torch.float64, 3 * self.n, "x_prev"), out.ctypes.data))
+        return float(out[0]), float(out[1])
+
+    def warmstart_input(self, x2, x2_prev, scale, prox, cpen, out):
+        import torch
+        npx = prox.numel()
+        self._chk(self._lib.pd_warmstart_input(
+            self._ctx, _ptr(x2, torch.float64, 3 * self.m, "x2"),
+            _ptr(x2_prev, torch.float64, 3 * self.m, "x2_prev"), float(scale), npx,
+            _ptr(prox, torch.int32, npx, "prox"), _ptr(cpen, torch.float64, npx, "c"),
+            _ptr(out, torch.float32, 4 * self.m, "out")))
+
+    def region_add_f32(self, d2, scale, x):
+        import torch
+        self._chk(self._lib.pd_region_add_f32(self._ctx, _ptr(d2, torch.float32, 3 * self.m, "d2"),
+                                              float(scale), _ptr(x, torch.float64, 3 * self.n, "x")))
+
+    def set_stream(self, stream):
+        self._chk(self._lib.pd_set_stream(self._ctx, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def set_timing(self, on=True):
         self._chk(self._lib.pd_set_timing(self._ctx, 1 if on else 0))
 
@@ -293,7 +324,7 @@ class MLP:
 
     def forward(self, x, y):
         import torch
-        B = x.shape[0]
+        B = x.numel() // self.shape[0]
         st = self._lib.pd_mlp_forward(self._h, _ptr(x, torch.float32, B * self.shape[0], "x"),
                                       _ptr(y, torch.float32, B * self.shape[3], "y"), B)
         if st != PD_OK:
@@ -301,7 +332,7 @@ class MLP:
 
     def train_step(self, x, target, lr, want_loss=True):
         import torch
-        B = x.shape[0]
+        B = x.numel() // self.shape[0]
         loss = C.c_double()
         st = self._lib.pd_mlp_train_step(self._h, _ptr(x, torch.float32, B * self.shape[0], "x"),
                                          _ptr(target, torch.float32, B * self.shape[3], "target"),
@@ -312,7 +343,7 @@ class MLP:
 
     def gradients(self, x, target):
         import torch
-        B = x.shape[0]
+        B = x.numel() // self.shape[0]
         loss = C.c_double()
         g = np.empty(self.n_params, dtype=np.float32)
         st = self._lib.pd_mlp_train_step(self._h, _ptr(x, torch.float32, B * self.shape[0], "x"),

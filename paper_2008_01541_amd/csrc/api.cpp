@@ -60,6 +60,9 @@ struct pd_ctx {
   int32_t *d_inc_a_ptr = nullptr, *d_inc_a = nullptr;
   int32_t *d_inc_b_ptr = nullptr, *d_inc_b = nullptr;
   int32_t* d_region_ids = nullptr;
+  int32_t* d_free_ids = nullptr;      // every free node (x1 and x2)
+  double* d_rest = nullptr;           // rest positions [3][n]
+  int64_t n_free = 0;
   int32_t* d_lev_nodes = nullptr;    // [n1] global ids in level order
   double* d_levmat = nullptr;        // Z_k = S_k^-1, full symmetric, per level
   int32_t *d_Bptr = nullptr, *d_Bcol = nullptr, *d_Btptr = nullptr, *d_Btcol = nullptr;
@@ -102,6 +105,8 @@ struct pd_ctx {
   int32_t n_pen = 0, pen_cap = 0;
   int32_t* d_pidx = nullptr;
   double *d_pw = nullptr, *d_pc = nullptr, *d_pt = nullptr;
+  int32_t* d_pact = nullptr;          // active penalties (c != 0), increasing
+  int32_t* d_pnact = nullptr;         // their count (device)
   bool stale = true;
 
   // optional per-phase timing with HIP events recorded on the stream
@@ -233,8 +238,8 @@ void free_now(pd_ctx* c, void* p) {
 // transpose of the factor in the upper triangle.
 void cholesky(pd_ctx* c, double* A, int lda, int n) {
   if (c->chol_dataflow) {
-    potrf_dataflow(A, lda, n, c->d_linv, c->d_tflags, c->d_tticket, ++c->chol_epoch, c->d_info,
-                   c->d_err, c->n_wg, c->st);
+    potrf_dataflow(A, lda, n, c->d_linv, c->d_tflags, c->d_tticket, c->d_info, c->d_err, c->n_wg,
+                   c->st);
   } else {
     potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
   }
@@ -596,6 +601,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     CK(c->alloc(&c->d_tflags, nt2));
     CK(c->alloc(&c->d_tticket, 4));
     HIPCK(c, hipMemsetAsync(c->d_tflags, 0, nt2 * sizeof(int), c->st));
+    HIPCK(c, hipMemsetAsync(c->d_tticket, 0, 4 * sizeof(unsigned), c->st));
     const char* mode = getenv("PDSCHUR_CHOL");
     if (mode && strcmp(mode, "tiled") == 0) c->chol_dataflow = 0;
     int dev = 0, ncu = 256;
@@ -685,7 +691,14 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   free_now(c, d_Ke);
   free_now(c, d_Bm);
   free_now(c, d_vol);
-  free_now(c, d_rest);
+  c->d_rest = d_rest;                 // kept for pd_displacement_change
+  {
+    std::vector<int32_t> fr;
+    for (int64_t i = 0; i < n; ++i)
+      if (cls[i] != 0) fr.push_back((int32_t)i);
+    c->n_free = (int64_t)fr.size();
+    CK(c->upload(&c->d_free_ids, fr));
+  }
   free_now(c, d_tets);
   CK(c->alloc(&c->d_H, (int64_t)c->ldH * m));
   CK(c->alloc(&c->d_y, 3 * m));
@@ -702,11 +715,14 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
 pd_status ensure_pen_cap(pd_ctx* c, int32_t n) {
   if (n <= c->pen_cap) return PD_OK;
   int32_t cap = std::max<int32_t>(n, 2 * c->pen_cap);
-  for (void* p : {(void*)c->d_pidx, (void*)c->d_pw, (void*)c->d_pc, (void*)c->d_pt})
+  for (void* p : {(void*)c->d_pidx, (void*)c->d_pw, (void*)c->d_pc, (void*)c->d_pt,
+                  (void*)c->d_pact})
     if (p) {
       HIPCK(c, hipStreamSynchronize(c->st));
       free_now(c, p);
     }
+  if (!c->d_pnact) CK(c->alloc(&c->d_pnact, 1));
+  CK(c->alloc(&c->d_pact, cap));
   CK(c->alloc(&c->d_pidx, 8 * (int64_t)cap));
   CK(c->alloc(&c->d_pw, 8 * (int64_t)cap));
   CK(c->alloc(&c->d_pc, cap));
@@ -863,8 +879,9 @@ pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, cons
     HIPCK(c, hipMemcpyAsync(c->d_pt, t, 3 * (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   }
   c->n_pen = n_pen;
-  penalty_apply(n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 1.0, x2, (int)c->m, nullptr, 0, f_col,
-                c->st);
+  compact_active(n_pen, c->d_pc, c->d_pact, c->d_pnact, c->st);
+  penalty_apply(n_pen, c->d_pact, c->d_pnact, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 1.0, x2,
+                (int)c->m, nullptr, 0, f_col, c->st);
   c->stale = true;
   c->lp_stale = true;
   return c->check("pd_collision_update");
@@ -875,8 +892,8 @@ pd_status pd_local_step_region(pd_ctx* c, const double* x2, void* R_beta, double
   if (bad_ctx(c) || !x2 || !f_beta) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
   if (c->nbeta == 0) {
-    HIPCK(c, hipMemsetAsync(f_beta, 0, 3 * c->m * sizeof(double), c->st));
-    return PD_OK;
+    zero_f64(3 * c->m, f_beta, c->st);
+    return c->check("pd_local_step_region");
   }
   PhaseTimer tm(c, PD_PHASE_LOCAL_REGION);
   local_step(c->nbeta, c->d_tets_beta, c->nbeta, c->d_Bm_beta, c->d_vol_beta, c->nbeta, x2, c->m,
@@ -902,8 +919,8 @@ void build_H(pd_ctx* c) {
   PhaseTimer tm(c, PD_PHASE_HBUILD);
   copy_lower_tiles(c->d_S, m, c->d_H, c->ldH, m, c->st);
   if (c->n_pen > 0)
-    penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, nullptr, m, c->d_H, c->ldH,
-                  nullptr, c->st);
+    penalty_apply(c->n_pen, c->d_pact, c->d_pnact, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0,
+                  nullptr, m, c->d_H, c->ldH, nullptr, c->st);
 }
 
 // res = g - (S + P) u in FP64; returns max over columns of ||res|| / ||g|| (synchronizes).
@@ -912,8 +929,8 @@ pd_status residual(pd_ctx* c, const double* g, const double* u, double* rel) {
   HIPCK(c, hipMemcpyAsync(c->d_res, g, 3 * (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   symv3(c->d_S, m, m, u, m, -1.0, 1.0, c->d_res, m, c->st);
   if (c->n_pen > 0) {
-    penalty_apply(c->n_pen, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, u, m, nullptr, 0, c->d_y,
-                  c->st);
+    penalty_apply(c->n_pen, c->d_pact, c->d_pnact, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, u, m,
+                  nullptr, 0, c->d_y, c->st);
     axpy3_sum(m, c->d_res, c->d_y, nullptr, c->d_res, c->st);
   }
   colnorm2_3(m, c->d_res, c->d_norms, c->st);
@@ -955,7 +972,7 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
   if (prec == PD_FP64) {
     if (c->stale) {
       build_H(c);
-      HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
+      zero_int(c->d_info, c->st);
       PhaseTimer tm(c, PD_PHASE_FACTOR);
       cholesky(c, c->d_H, c->ldH, m);
       c->stale = false;
@@ -990,11 +1007,11 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
   if (c->lp_stale || c->lp_prec != (int)prec) {
     build_H(c);
     c->stale = true;            // d_H no longer holds an FP64 factor
-    HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
+    zero_int(c->d_info, c->st);
     PhaseTimer tm(c, PD_PHASE_FACTOR);
     equilibrate_convert(c->d_H, c->ldH, m, c->d_dvec, c->d_H32, c->ldH32, c->st);
-    potrf_dataflow_lp(c->d_H32, c->ldH32, m, c->d_linv32, c->d_tflags, c->d_tticket, ++c->chol_epoch,
-                      c->d_info, c->d_err, c->n_wg, prec == PD_BF16_IR, c->st);
+    potrf_dataflow_lp(c->d_H32, c->ldH32, m, c->d_linv32, c->d_tflags, c->d_tticket, c->d_info,
+                      c->d_err, c->n_wg, prec == PD_BF16_IR, c->st);
     c->lp_stale = false;
     c->lp_prec = (int)prec;
   }
@@ -1037,6 +1054,42 @@ pd_status pd_inner_update(pd_ctx* c, const double* u2, double* x2, double* delta
   symv3(c->d_S, m, m, u2, m, -1.0, 1.0, ft, m, c->st);
   if (c->nbeta > 0) csr_spmv3(m, c->d_Abptr, c->d_Abcol, c->d_Abval, u2, m, 1.0, ft, m, ft, m, c->st);
   return c->check("pd_inner_update");
+}
+
+pd_status pd_warmstart_input(pd_ctx* c, const double* x2, const double* x2_prev, float scale,
+                             int32_t n_prox, const int32_t* prox, const double* cpen, float* out) {
+  if (bad_ctx(c) || !x2 || !x2_prev || !out || n_prox < 0 || (n_prox > 0 && (!prox || !cpen)))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  ws_input((int)c->m, x2, x2_prev, scale, n_prox, prox, cpen, out, c->st);
+  return c->check("pd_warmstart_input");
+}
+
+pd_status pd_region_add_f32(pd_ctx* c, const float* d2, double scale, double* x) {
+  if (bad_ctx(c) || !d2 || !x) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  region_add_f32(c->m, c->d_region_ids, d2, scale, x, c->n, c->st);
+  return c->check("pd_region_add_f32");
+}
+
+pd_status pd_displacement_change(pd_ctx* c, const double* x, const double* x_prev, double* out) {
+  if (bad_ctx(c) || !x || !x_prev || !out) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  change_norms(c->n_free, c->d_free_ids, x, x_prev, c->d_rest, c->n, c->d_norms, c->st);
+  double h[2];
+  HIPCK(c, hipMemcpyAsync(h, c->d_norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCK(c, hipStreamSynchronize(c->st));
+  out[0] = std::sqrt(h[0]);
+  out[1] = std::sqrt(h[1]);
+  return PD_OK;
+}
+
+pd_status pd_set_stream(pd_ctx* c, void* hip_stream) {
+  if (bad_ctx(c)) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  HIPCK(c, hipStreamSynchronize(c->st));
+  c->st = (hipStream_t)hip_stream;
+  return PD_OK;
 }
 
 pd_status pd_set_timing(pd_ctx* c, int on) {

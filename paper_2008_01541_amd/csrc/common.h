@@ -17,10 +17,14 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // dense FP64
 void copy_lower_tiles(const double* S, int lds, double* H, int ldh, int n, hipStream_t st);
 void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStream_t st);
-// Single-launch dataflow Cholesky; flags: nt*nt ints (zero-initialised once,
-// epoch strictly increasing per call), ticket: one counter reset by the call.
+// Single-launch dataflow Cholesky; flags: nt*nt ints and ticket[2] (task
+// counter, launch epoch), all zero-initialised once; each call advances the
+// epoch on the device (safe under graph replay).
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
-                    int epoch, int* info, int* err, int n_wg, hipStream_t st);
+                    int* info, int* err, int n_wg, hipStream_t st);
+// Fill kernels (used instead of memset so the calls can be graph-captured).
+void zero_int(int* p, hipStream_t st);
+void zero_f64(long n, double* p, hipStream_t st);
 void trtri_from_factor(const double* L, int ldl, int n, const double* linv_ws, double* M,
                        double* X, int ldx, hipStream_t st);
 void lauum_full(const double* X, int ldx, int n, double* Z, int ldz, hipStream_t st);
@@ -36,7 +40,7 @@ void symv3(const double* A, int lda, int n, const double* v, int ldv, double alp
 
 // low precision (FP32 / BF16-operand) factor of the equilibrated system
 void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, int* flags, unsigned* ticket,
-                       int epoch, int* info, int* err, int n_wg, bool bf16, hipStream_t st);
+                       int* info, int* err, int n_wg, bool bf16, hipStream_t st);
 void equilibrate_convert(const double* H, int ld, int n, double* d, float* H32, int ld32,
                          hipStream_t st);
 // x (+)= D L^-T L^-1 D r with L the FP32 factor of D H D (three right-hand sides).
@@ -73,13 +77,23 @@ void sub_sparse_times_dense(double* Next, int ldn, int nr, const int32_t* rows,
 void detect_spheres(int n_prox, const int32_t* prox, int n_sph, const double* sph, double k,
                     const double* x2, int m, int32_t* idx, double* w, double* c, double* t,
                     hipStream_t st);
-// Row a of H (lower part) += (W^T C W)[a, :]  when H != NULL;
+// act[0..*cnt) <- indices j < n_pen with c[j] != 0, increasing (device count).
+void compact_active(int n_pen, const double* c, int32_t* act, int32_t* cnt, hipStream_t st);
+// Over the active penalties act[0..*nact):
+// row a of H (lower part) += (W^T C W)[a, :]  when H != NULL;
 // fcol[:, a] = -(W^T C (W x2 - tscale * t))[a]  when fcol != NULL.
-void penalty_apply(int n_pen, const int32_t* idx, const double* w, const double* c,
-                   const double* t, double tscale, const double* x2, int m, double* H,
-                   int ldh, double* fcol, hipStream_t st);
+void penalty_apply(int n_pen, const int32_t* act, const int32_t* nact, const int32_t* idx,
+                   const double* w, const double* c, const double* t, double tscale,
+                   const double* x2, int m, double* H, int ldh, double* fcol, hipStream_t st);
+// out = (sum ||x - xp||^2, sum ||x - X||^2) over the listed nodes (device, 2 doubles).
+void change_norms(int64_t cnt, const int32_t* ids, const double* x, const double* xp,
+                  const double* X, int64_t n, double* out, hipStream_t st);
 // out[v] = sum_i a[v][i]^2 for the three columns (out: 3 doubles, device).
 void colnorm2_3(int m, const double* a, double* out, hipStream_t st);
+void ws_input(int m, const double* x2, const double* x2p, float scale, int n_prox,
+              const int32_t* prox, const double* c, float* out, hipStream_t st);
+void region_add_f32(int64_t count, const int32_t* ids, const float* d, double scale, double* x,
+                    int64_t ldx, hipStream_t st);
 void axpy3_sum(int m, const double* a, const double* b, const double* c, double* out,
                hipStream_t st);
 void inner_update(int m, const double* u, double* x2, double* d2, hipStream_t st);

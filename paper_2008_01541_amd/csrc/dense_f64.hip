@@ -279,7 +279,13 @@ __device__ inline void publish_flag(int* f, int epoch) {
   if (threadIdx.x == 0) __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_reset_counter(unsigned* ctr) { *ctr = 0u; }
+// Resets the task ticket and advances the launch epoch kept in ctr[1]; the
+// factorization kernel reads the epoch from memory, so a captured graph that
+// replays the pair still gets a fresh epoch every time.
+__global__ void k_reset_counter(unsigned* ctr) {
+  ctr[0] = 0u;
+  ctr[1] = ctr[1] + 1u;
+}
 
 // Blocked (16 x 16) Cholesky of the LDS tile T (T[c][r] = tile(r, c), lower,
 // identity-padded past mr) and the inverse of the factor into X.
@@ -411,30 +417,24 @@ __device__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], in
   }
 }
 
-// acc += sum_{k<j} L_ik L_jk^T with double-buffered operand chunks.
-__device__ bool df_accumulate(Acc& acc, double (*buf)[KCD][LDS_LD], const double* __restrict__ A,
-                              int lda, int r0, int mr, int c0, int mc, int i, int j, int nt,
-                              const int* flags, int epoch, int* err, int* s_ok) {
+// acc += sum_{k<j} L_ik L_jk^T, one 64-deep k-step at a time.  The two
+// operand tiles of step k+1 are loaded into registers while the products of
+// step k run from LDS, and the ready flags of step k+2 are read while step
+// k+1 is loaded, so neither the flag round trip nor the operand latency sits
+// on the path when the producers are ahead.
+__device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
+                              const double* __restrict__ A, int lda, int r0, int mr, int c0,
+                              int mc, int i, int j, int nt, const int* flags, int epoch, int* err,
+                              int* s_ok) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int r = t & 63, kq = t >> 6;
-  double (*Ab[2])[LDS_LD] = {buf[0], buf[1]};
-  double (*Bb[2])[LDS_LD] = {buf[2], buf[3]};
-  const int nch = 2 * j;
-  double ra[8], rb[8];
-  auto wait_k = [&](int k) -> bool {
-    if (t == 0) {
-      if (!df_wait(&flags[i * nt + k], epoch, err) || !df_wait(&flags[j * nt + k], epoch, err))
-        *s_ok = 0;
-    }
-    __syncthreads();
-    return *s_ok != 0;
-  };
-  auto prefetch = [&](int ch) {
-    const long kabs = (long)(ch >> 1) * NB + (ch & 1) * KCD;
+  if (j == 0) return true;
+  double ra[16], rb[16];
+  auto load_tile = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const long col = (kabs + kq + 4 * q) * lda;
+    for (int q = 0; q < 16; ++q) {
+      const long col = (long)(k * NB + kq + 4 * q) * lda;
 #ifdef PD_COHERENT_OPERAND_LOADS
       ra[q] = (r < mr) ? coherent_load(&A[(long)(r0 + r) + col]) : 0.0;
       rb[q] = (r < mc) ? coherent_load(&A[(long)(c0 + r) + col]) : 0.0;
@@ -444,52 +444,64 @@ __device__ bool df_accumulate(Acc& acc, double (*buf)[KCD][LDS_LD], const double
 #endif
     }
   };
-  auto store = [&](int b) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      Ab[b][kq + 4 * q][r] = ra[q];
-      Bb[b][kq + 4 * q][r] = rb[q];
-    }
-  };
-  if (nch == 0) return true;
-  if (!wait_k(0)) return false;
-  prefetch(0);
-  store(0);
+  int fi = 0, fj = 0;          // thread 0: flags of the next step, read ahead
+  if (t == 0) {
+    if (!df_wait(&flags[i * nt], epoch, err) || !df_wait(&flags[j * nt], epoch, err)) *s_ok = 0;
+  }
   __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const bool nxt = ch + 1 < nch;
-    if (nxt) {
-      if (((ch + 1) & 1) == 0 && !wait_k((ch + 1) >> 1)) return false;
-      prefetch(ch + 1);
-    }
-    const int b = ch & 1;
+  if (!*s_ok) return false;
+  load_tile(0);
+  if (t == 0 && j > 1) {
+    fi = __hip_atomic_load(&flags[i * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    fj = __hip_atomic_load(&flags[j * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  for (int k = 0; k < j; ++k) {
+    __syncthreads();                         // previous step's products are done with LDS
 #pragma unroll
-    for (int ks = 0; ks < KCD / 4; ++ks) {
-      const int k = ks * 4 + (lane >> 4);
-      const double a0 = Ab[b][k][wr * 32 + (lane & 15)];
-      const double a1 = Ab[b][k][wr * 32 + 16 + (lane & 15)];
-      const double b0 = Bb[b][k][wc * 32 + (lane & 15)];
-      const double b1 = Bb[b][k][wc * 32 + 16 + (lane & 15)];
+    for (int q = 0; q < 16; ++q) {
+      As[kq + 4 * q][r] = ra[q];
+      Bs[kq + 4 * q][r] = rb[q];
+    }
+    const bool nxt = k + 1 < j;
+    if (t == 0 && nxt && (fi != epoch || fj != epoch)) {
+      if (!df_wait(&flags[i * nt + k + 1], epoch, err) ||
+          !df_wait(&flags[j * nt + k + 1], epoch, err))
+        *s_ok = 0;
+    }
+    __syncthreads();
+    if (!*s_ok) return false;
+    if (nxt) {
+      load_tile(k + 1);
+      if (t == 0 && k + 2 < j) {
+        fi = __hip_atomic_load(&flags[i * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        fj = __hip_atomic_load(&flags[j * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < NB / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      const double a0 = As[kk][wr * 32 + (lane & 15)];
+      const double a1 = As[kk][wr * 32 + 16 + (lane & 15)];
+      const double b0 = Bs[kk][wc * 32 + (lane & 15)];
+      const double b1 = Bs[kk][wc * 32 + 16 + (lane & 15)];
       acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
       acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
       acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
       acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
     }
-    if (nxt) store(b ^ 1);
-    __syncthreads();
   }
   return true;
 }
 
 __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, int n, int nt,
                                                            double* linv_ws, int* flags,
-                                                           unsigned* ticket, int epoch, int* info,
-                                                           int* err) {
-  // 4 x 32 x 68 doubles = 69,632 bytes; reused as two 64 x 68 tiles after the accumulation
-  __shared__ double smem[4][KCD][LDS_LD];
+                                                           unsigned* ticket, int* info, int* err) {
+  const int epoch = (int)ticket[1];
+  // two 64 x 68 double tiles (69,632 bytes): operands of the accumulation,
+  // then the tile and its inverse / Linv during the finishing step
+  __shared__ double buf0[NB][LDS_LD];
+  __shared__ double buf1[NB][LDS_LD];
   __shared__ int s_task, s_ok;
-  double (*buf0)[LDS_LD] = (double (*)[LDS_LD]) & smem[0][0][0];
-  double (*buf1)[LDS_LD] = (double (*)[LDS_LD]) & smem[2][0][0];
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
@@ -513,7 +525,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     const int mr = min(NB, n - r0), mc = min(NB, n - c0);
     Acc acc;
     acc_zero(acc);
-    if (!df_accumulate(acc, smem, A, lda, r0, mr, c0, mc, i, j, nt, flags, epoch, err, &s_ok))
+    if (!df_accumulate(acc, buf0, buf1, A, lda, r0, mr, c0, mc, i, j, nt, flags, epoch, err, &s_ok))
       return;
     __syncthreads();
     // C = A_ij - acc  ->  buf0[c][r]; padding: identity on the diagonal tile, zero elsewhere
@@ -581,12 +593,23 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 }
 
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
-                    int epoch, int* info, int* err, int n_wg, hipStream_t st) {
+                    int* info, int* err, int n_wg, hipStream_t st) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = nt * (nt + 1) / 2;
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
   k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags, ticket,
-                                                          epoch, info, err);
+                                                          info, err);
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+void zero_int(int* p, hipStream_t st) { k_zero_int<<<1, 1, 0, st>>>(p); }
+
+__global__ void k_zero_f64(long n, double* p) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = 0.0;
+}
+void zero_f64(long n, double* p, hipStream_t st) {
+  if (n > 0) k_zero_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, p);
 }
 
 // Upper triangle <- transpose of the strictly lower triangle (tiles (j, i), i > j,
@@ -946,48 +969,75 @@ void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const
 
 // ---------------------------------------------------------------------------
 // y = alpha * A v + beta * y, A symmetric in full storage: element i of the
-// product is the dot of column i with v, one wave per column (contiguous reads).
+// product is the dot of column i with v.  A workgroup owns 8 columns (two per
+// wave); the three right-hand sides are staged through LDS in chunks of 512
+// rows, so each matrix element costs one 16-byte-per-lane streaming load and
+// the vector is read from L2 once per 8 columns.
+constexpr int SV_CHUNK = 512;
 __global__ __launch_bounds__(256) void k_symv3(const double* __restrict__ A, long lda, int n,
                                                const double* __restrict__ v, long ldv,
                                                double alpha, double beta, double* y, long ldy) {
-  const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (col >= n) return;
-  const double* a = A + (long)col * lda;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  int j = lane;
-  for (; j + 192 < n; j += 256) {
-    const double x0 = a[j], x1 = a[j + 64], x2 = a[j + 128], x3 = a[j + 192];
-    s0 += x0 * v[j] + x1 * v[j + 64] + x2 * v[j + 128] + x3 * v[j + 192];
-    s1 += x0 * v[ldv + j] + x1 * v[ldv + j + 64] + x2 * v[ldv + j + 128] + x3 * v[ldv + j + 192];
-    s2 += x0 * v[2 * ldv + j] + x1 * v[2 * ldv + j + 64] + x2 * v[2 * ldv + j + 128] +
-          x3 * v[2 * ldv + j + 192];
-  }
-  for (; j < n; j += 64) {
-    const double x0 = a[j];
-    s0 += x0 * v[j];
-    s1 += x0 * v[ldv + j];
-    s2 += x0 * v[2 * ldv + j];
-  }
-  s0 = wave_sum(s0);
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  if (lane == 0) {
-    if (beta == 0.0) {
-      y[col] = alpha * s0;
-      y[ldy + col] = alpha * s1;
-      y[2 * ldy + col] = alpha * s2;
+  __shared__ double vs[3][SV_CHUNK];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int c0 = blockIdx.x * 8 + w * 2;
+  const bool has0 = c0 < n, has1 = c0 + 1 < n;
+  const double* a0 = A + (long)min(c0, n - 1) * lda;
+  const double* a1 = A + (long)min(c0 + 1, n - 1) * lda;
+  const bool vec = ((lda & 1) == 0) && ((((unsigned long)A) & 15) == 0);
+  double s[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  for (int j0 = 0; j0 < n; j0 += SV_CHUNK) {
+    const int cnt = min(SV_CHUNK, n - j0);
+    __syncthreads();
+    for (int e = t; e < 3 * SV_CHUNK; e += 256) {
+      const int vv = e / SV_CHUNK, jj = e % SV_CHUNK;
+      vs[vv][jj] = (jj < cnt) ? v[(long)vv * ldv + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+    if (vec && cnt == SV_CHUNK) {
+#pragma unroll
+      for (int it = 0; it < SV_CHUNK / 128; ++it) {
+        const int jj = it * 128 + 2 * lane;
+        const double2 x0 = *(const double2*)(a0 + j0 + jj);
+        const double2 x1 = *(const double2*)(a1 + j0 + jj);
+#pragma unroll
+        for (int vv = 0; vv < 3; ++vv) {
+          const double p = vs[vv][jj], q = vs[vv][jj + 1];
+          s[0][vv] += x0.x * p + x0.y * q;
+          s[1][vv] += x1.x * p + x1.y * q;
+        }
+      }
     } else {
-      y[col] = alpha * s0 + beta * y[col];
-      y[ldy + col] = alpha * s1 + beta * y[ldy + col];
-      y[2 * ldy + col] = alpha * s2 + beta * y[2 * ldy + col];
+      for (int jj = lane; jj < cnt; jj += 64) {
+        const double x0 = a0[j0 + jj], x1 = a1[j0 + jj];
+#pragma unroll
+        for (int vv = 0; vv < 3; ++vv) {
+          s[0][vv] += x0 * vs[vv][jj];
+          s[1][vv] += x1 * vs[vv][jj];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+    for (int vv = 0; vv < 3; ++vv) s[cc][vv] = wave_sum(s[cc][vv]);
+  if (lane == 0) {
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      if (!(cc == 0 ? has0 : has1)) continue;
+      const int col = c0 + cc;
+#pragma unroll
+      for (int vv = 0; vv < 3; ++vv) {
+        double* yo = y + (long)vv * ldy + col;
+        *yo = (beta == 0.0) ? alpha * s[cc][vv] : alpha * s[cc][vv] + beta * *yo;
+      }
     }
   }
 }
 
 void symv3(const double* A, int lda, int n, const double* v, int ldv, double alpha, double beta,
            double* y, int ldy, hipStream_t st) {
-  k_symv3<<<(n + 3) / 4, 256, 0, st>>>(A, lda, n, v, ldv, alpha, beta, y, ldy);
+  if (n > 0) k_symv3<<<(n + 7) / 8, 256, 0, st>>>(A, lda, n, v, ldv, alpha, beta, y, ldy);
 }
 
 }  // namespace pdk

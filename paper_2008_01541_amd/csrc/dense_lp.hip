@@ -166,14 +166,113 @@ __device__ inline void cstore(float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_reset_counter_lp(unsigned* ctr) { *ctr = 0u; }
+// acc += sum_{k<j} L_ik L_jk^T for an FP32 factor; operands of step k+1 are
+// loaded into registers during step k, flags of step k+2 are read ahead.
+// BF16: operands are rounded to BF16 when staged; FP32 accumulation.
+constexpr int BFL = NB + 8;   // BF16 LDS row: 64 k values + pad (16-byte aligned)
+template <bool BF16>
+__device__ bool lp_accumulate(AccF& acc, float (*buf0)[LP_LD], float (*buf1)[LP_LD],
+                              const float* __restrict__ A, int lda, int r0, int mr, int c0, int mc,
+                              int i, int j, int nt, const int* flags, int epoch, int* err,
+                              int* s_ok) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  const int r = t & 63, kq = t >> 6;
+  if (j == 0) return true;
+  float ra[16], rb[16];
+  auto load_tile = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const long col = (long)(k * NB + kq + 4 * q) * lda;
+      ra[q] = (r < mr) ? A[(long)(r0 + r) + col] : 0.f;
+      rb[q] = (r < mc) ? A[(long)(c0 + r) + col] : 0.f;
+    }
+  };
+  __bf16 (*Ab)[BFL] = (__bf16 (*)[BFL]) & buf0[0][0];
+  __bf16 (*Bb)[BFL] = (__bf16 (*)[BFL]) & buf1[0][0];
+  int fi = 0, fj = 0;
+  if (t == 0) {
+    if (!lp_wait(&flags[i * nt], epoch, err) || !lp_wait(&flags[j * nt], epoch, err)) *s_ok = 0;
+  }
+  __syncthreads();
+  if (!*s_ok) return false;
+  load_tile(0);
+  if (t == 0 && j > 1) {
+    fi = __hip_atomic_load(&flags[i * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    fj = __hip_atomic_load(&flags[j * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  for (int k = 0; k < j; ++k) {
+    __syncthreads();
+    if (BF16) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        Ab[r][kq + 4 * q] = (__bf16)ra[q];
+        Bb[r][kq + 4 * q] = (__bf16)rb[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        buf0[kq + 4 * q][r] = ra[q];
+        buf1[kq + 4 * q][r] = rb[q];
+      }
+    }
+    const bool nxt = k + 1 < j;
+    if (t == 0 && nxt && (fi != epoch || fj != epoch)) {
+      if (!lp_wait(&flags[i * nt + k + 1], epoch, err) || !lp_wait(&flags[j * nt + k + 1], epoch, err))
+        *s_ok = 0;
+    }
+    __syncthreads();
+    if (!*s_ok) return false;
+    if (nxt) {
+      load_tile(k + 1);
+      if (t == 0 && k + 2 < j) {
+        fi = __hip_atomic_load(&flags[i * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        fj = __hip_atomic_load(&flags[j * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if (BF16) {
+#pragma unroll
+      for (int ks = 0; ks < NB / 32; ++ks) {
+        const int ko = ks * 32 + 8 * (lane >> 4);
+        const bf16x8_t a0 = *(const bf16x8_t*)&Ab[wr * 32 + (lane & 15)][ko];
+        const bf16x8_t a1 = *(const bf16x8_t*)&Ab[wr * 32 + 16 + (lane & 15)][ko];
+        const bf16x8_t b0 = *(const bf16x8_t*)&Bb[wc * 32 + (lane & 15)][ko];
+        const bf16x8_t b1 = *(const bf16x8_t*)&Bb[wc * 32 + 16 + (lane & 15)][ko];
+        acc.c[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0, a0, acc.c[0][0], 0, 0, 0);
+        acc.c[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1, a0, acc.c[0][1], 0, 0, 0);
+        acc.c[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0, a1, acc.c[1][0], 0, 0, 0);
+        acc.c[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1, a1, acc.c[1][1], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < NB / 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        const float a0 = buf0[kk][wr * 32 + (lane & 15)];
+        const float a1 = buf0[kk][wr * 32 + 16 + (lane & 15)];
+        const float b0 = buf1[kk][wc * 32 + (lane & 15)];
+        const float b1 = buf1[kk][wc * 32 + 16 + (lane & 15)];
+        acc.c[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a0, acc.c[0][0], 0, 0, 0);
+        acc.c[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a0, acc.c[0][1], 0, 0, 0);
+        acc.c[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a1, acc.c[1][0], 0, 0, 0);
+        acc.c[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a1, acc.c[1][1], 0, 0, 0);
+      }
+    }
+  }
+  return true;
+}
+
+__global__ void k_reset_counter_lp(unsigned* ctr) {
+  ctr[0] = 0u;
+  ctr[1] = ctr[1] + 1u;
+}
 
 // Dataflow Cholesky of a float matrix (same schedule as the FP64 kernel).
 template <bool BF16>
 __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda, int n, int nt,
                                                               float* linv_ws, int* flags,
-                                                              unsigned* ticket, int epoch,
-                                                              int* info, int* err) {
+                                                              unsigned* ticket, int* info,
+                                                              int* err) {
+  const int epoch = (int)ticket[1];
   __shared__ float buf0[NB][LP_LD];
   __shared__ float buf1[NB][LP_LD];
   __shared__ float inv_d[NB];
@@ -201,19 +300,9 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
     const int mr = min(NB, n - r0), mc = min(NB, n - c0);
     AccF acc;
     accf_zero(acc);
-    for (int k = 0; k < j; ++k) {
-      if (t == 0) {
-        if (!lp_wait(&flags[i * nt + k], epoch, err) || !lp_wait(&flags[j * nt + k], epoch, err))
-          s_ok = 0;
-      }
-      __syncthreads();
-      if (!s_ok) return;
-      if (BF16)
-        gemm_bf16_tile(acc, (__bf16(*)[BF_LD]) & buf0[0][0], (__bf16(*)[BF_LD]) & buf1[0][0], A,
-                       lda, r0, mr, A, lda, c0, mc, k * NB);
-      else
-        gemm_f32_tile(acc, buf0, buf1, A, lda, r0, mr, A, lda, c0, mc, k * NB);
-    }
+    if (!lp_accumulate<BF16>(acc, buf0, buf1, A, lda, r0, mr, c0, mc, i, j, nt, flags, epoch, err,
+                             &s_ok))
+      return;
     __syncthreads();
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -276,16 +365,16 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
 }
 
 void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, int* flags, unsigned* ticket,
-                       int epoch, int* info, int* err, int n_wg, bool bf16, hipStream_t st) {
+                       int* info, int* err, int n_wg, bool bf16, hipStream_t st) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = nt * (nt + 1) / 2;
   k_reset_counter_lp<<<1, 1, 0, st>>>(ticket);
   if (bf16)
     k_potrf_dataflow_lp<true><<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags,
-                                                                     ticket, epoch, info, err);
+                                                                     ticket, info, err);
   else
     k_potrf_dataflow_lp<false><<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags,
-                                                                      ticket, epoch, info, err);
+                                                                      ticket, info, err);
 }
 
 // ---------------------------------------------------------------------------

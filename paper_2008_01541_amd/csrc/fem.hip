@@ -505,12 +505,50 @@ void detect_spheres(int n_prox, const int32_t* prox, int n_sph, const double* sp
                                                      c, t);
 }
 
-// Penalty terms, one thread per region node a (row a of W^T C W and entry a of
-// f_col), scanning the penalty list in order:
+// Active-penalty list: act[0..cnt) = indices j with c[j] != 0 in increasing
+// order (one workgroup, block-wide prefix sums; deterministic).
+__global__ __launch_bounds__(1024) void k_compact_active(int n_pen, const double* __restrict__ c,
+                                                         int32_t* __restrict__ act,
+                                                         int32_t* __restrict__ cnt) {
+  __shared__ int32_t wsum[16];
+  __shared__ int32_t base;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t == 0) base = 0;
+  __syncthreads();
+  for (int j0 = 0; j0 < n_pen; j0 += 1024) {
+    const int j = j0 + t;
+    const int f = (j < n_pen && c[j] != 0.0) ? 1 : 0;
+    // inclusive scan inside the wave
+    int v = f;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o, 64);
+      if (lane >= o) v += u;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    int off = base;
+    for (int q = 0; q < w; ++q) off += wsum[q];
+    if (f) act[off + v - 1] = j;
+    __syncthreads();
+    if (t == 0) {
+      int tot = 0;
+      for (int q = 0; q < 16; ++q) tot += wsum[q];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (t == 0) *cnt = base;
+}
+
+// Penalty terms, one thread per region node a (row a of W^T C W and entry a
+// of f_col), scanning the active penalties in increasing index order:
 //   H[a + b*ldh] += c_j w_ja w_jb  for b <= a   (lower triangle, H may be NULL)
-//   fcol[:, a]    = -sum_j c_j w_ja (W_j x2 - t_j)
+//   fcol[:, a]    = -sum_j c_j w_ja (W_j x2 - tscale t_j)
 constexpr int PCH = 128;
-__global__ __launch_bounds__(256) void k_penalty_apply(int n_pen, const int32_t* __restrict__ idx,
+__global__ __launch_bounds__(256) void k_penalty_apply(int n_pen, const int32_t* __restrict__ act,
+                                                       const int32_t* __restrict__ nact,
+                                                       const int32_t* __restrict__ idx,
                                                        const double* __restrict__ w,
                                                        const double* __restrict__ c,
                                                        const double* __restrict__ t,
@@ -522,19 +560,22 @@ __global__ __launch_bounds__(256) void k_penalty_apply(int n_pen, const int32_t*
   __shared__ double sc[PCH];
   __shared__ double sr[3][PCH];
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int na = *nact;
   double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-  for (int base = 0; base < n_pen; base += PCH) {
-    const int cnt = min(PCH, n_pen - base);
+  for (int base = 0; base < na; base += PCH) {
+    const int cnt = min(PCH, na - base);
     __syncthreads();
     for (int e = threadIdx.x; e < cnt * 8; e += blockDim.x) {
-      si[e >> 3][e & 7] = idx[(int64_t)base * 8 + e];
-      sw[e >> 3][e & 7] = w[(int64_t)base * 8 + e];
+      const int j = act[base + (e >> 3)];
+      si[e >> 3][e & 7] = idx[(int64_t)j * 8 + (e & 7)];
+      sw[e >> 3][e & 7] = w[(int64_t)j * 8 + (e & 7)];
     }
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) sc[e] = c[base + e];
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) sc[e] = c[act[base + e]];
     __syncthreads();
     for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
       double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-      if (fcol && sc[e] != 0.0) {
+      if (fcol) {
+        const int j = act[base + e];
         for (int s = 0; s < 8; ++s) {
           const int b = si[e][s];
           if (b < 0 || b >= m) continue;
@@ -543,9 +584,9 @@ __global__ __launch_bounds__(256) void k_penalty_apply(int n_pen, const int32_t*
           r1 += ws * x2[m + b];
           r2 += ws * x2[2 * m + b];
         }
-        r0 -= tscale * t[base + e];
-        r1 -= tscale * t[n_pen + base + e];
-        r2 -= tscale * t[2 * n_pen + base + e];
+        r0 -= tscale * t[j];
+        r1 -= tscale * t[n_pen + j];
+        r2 -= tscale * t[2 * n_pen + j];
       }
       sr[0][e] = r0;
       sr[1][e] = r1;
@@ -553,19 +594,18 @@ __global__ __launch_bounds__(256) void k_penalty_apply(int n_pen, const int32_t*
     }
     __syncthreads();
     if (a < m) {
-      for (int j = 0; j < cnt; ++j) {
-        const double cj = sc[j];
-        if (cj == 0.0) continue;
+      for (int jj = 0; jj < cnt; ++jj) {
+        const double cj = sc[jj];
         for (int s = 0; s < 8; ++s) {
-          if (si[j][s] != a) continue;
-          const double coef = cj * sw[j][s];
-          f0 -= coef * sr[0][j];
-          f1 -= coef * sr[1][j];
-          f2 -= coef * sr[2][j];
+          if (si[jj][s] != a) continue;
+          const double coef = cj * sw[jj][s];
+          f0 -= coef * sr[0][jj];
+          f1 -= coef * sr[1][jj];
+          f2 -= coef * sr[2][jj];
           if (H) {
             for (int sb = 0; sb < 8; ++sb) {
-              const int b = si[j][sb];
-              if (b >= 0 && b <= a) H[(int64_t)a + (int64_t)b * ldh] += coef * sw[j][sb];
+              const int b = si[jj][sb];
+              if (b >= 0 && b <= a) H[(int64_t)a + (int64_t)b * ldh] += coef * sw[jj][sb];
             }
           }
         }
@@ -579,11 +619,16 @@ __global__ __launch_bounds__(256) void k_penalty_apply(int n_pen, const int32_t*
   }
 }
 
-void penalty_apply(int n_pen, const int32_t* idx, const double* w, const double* c,
-                   const double* t, double tscale, const double* x2, int m, double* H, int ldh,
-                   double* fcol, hipStream_t st) {
+void compact_active(int n_pen, const double* c, int32_t* act, int32_t* cnt, hipStream_t st) {
+  k_compact_active<<<1, 1024, 0, st>>>(n_pen, c, act, cnt);
+}
+
+void penalty_apply(int n_pen, const int32_t* act, const int32_t* nact, const int32_t* idx,
+                   const double* w, const double* c, const double* t, double tscale,
+                   const double* x2, int m, double* H, int ldh, double* fcol, hipStream_t st) {
   if (m > 0)
-    k_penalty_apply<<<grid1(m), 256, 0, st>>>(n_pen, idx, w, c, t, tscale, x2, m, H, ldh, fcol);
+    k_penalty_apply<<<grid1(m, 64), 64, 0, st>>>(n_pen, act, nact, idx, w, c, t, tscale, x2, m, H,
+                                                 ldh, fcol);
 }
 
 // Sum of squares of each of the three columns of a [3][m], one workgroup per
@@ -608,6 +653,83 @@ __global__ __launch_bounds__(256) void k_colnorm2_3(int m, const double* __restr
 
 void colnorm2_3(int m, const double* a, double* out, hipStream_t st) {
   k_colnorm2_3<<<3, 256, 0, st>>>(m, a, out);
+}
+
+// out[0] = sum over listed nodes of ||x - xp||^2, out[1] = sum of ||x - X||^2
+// (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void k_change_norms(int64_t cnt, const int32_t* __restrict__ ids,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ xp,
+                                                       const double* __restrict__ X, int64_t n,
+                                                       double* __restrict__ out) {
+  __shared__ double r0[1024], r1[1024];
+  double a = 0.0, b = 0.0;
+  for (int64_t e = threadIdx.x; e < cnt; e += 1024) {
+    const int64_t i = ids[e];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const double d = x[v * n + i] - xp[v * n + i];
+      const double u = x[v * n + i] - X[v * n + i];
+      a += d * d;
+      b += u * u;
+    }
+  }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      r0[threadIdx.x] += r0[threadIdx.x + o];
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = r0[0];
+    out[1] = r1[0];
+  }
+}
+
+void change_norms(int64_t cnt, const int32_t* ids, const double* x, const double* xp,
+                  const double* X, int64_t n, double* out, hipStream_t st) {
+  k_change_norms<<<1, 1024, 0, st>>>(cnt, ids, x, xp, X, n, out);
+}
+
+// Warm-start input [scale (x2 - x2_prev) (3m) ; active mask (m)] in float32;
+// the mask is 1 for region nodes that are proxies with c > 0.
+__global__ void k_ws_input(int m, const double* __restrict__ x2, const double* __restrict__ x2p,
+                           float scale, float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < 3 * (int64_t)m) out[e] = (float)((x2[e] - x2p[e]) * scale);
+  if (e < m) out[3 * (int64_t)m + e] = 0.f;
+}
+__global__ void k_ws_mask(int n_prox, const int32_t* __restrict__ prox, const double* __restrict__ c,
+                          int m, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n_prox && prox[j] >= 0 && prox[j] < m && c[j] != 0.0) out[3 * (int64_t)m + prox[j]] = 1.f;
+}
+
+void ws_input(int m, const double* x2, const double* x2p, float scale, int n_prox,
+              const int32_t* prox, const double* c, float* out, hipStream_t st) {
+  k_ws_input<<<grid1(3 * (int64_t)m), 256, 0, st>>>(m, x2, x2p, scale, out);
+  if (n_prox > 0) k_ws_mask<<<grid1(n_prox), 256, 0, st>>>(n_prox, prox, c, m, out);
+}
+
+// x[:, ids[r]] += scale * d[:, r] for a float32 region increment
+__global__ void k_region_add_f32(int64_t count, const int32_t* __restrict__ ids,
+                                 const float* __restrict__ d, double scale, double* __restrict__ x,
+                                 int64_t ldx) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= count) return;
+  const int64_t i = ids[r];
+  x[i] += scale * (double)d[r];
+  x[ldx + i] += scale * (double)d[count + r];
+  x[2 * ldx + i] += scale * (double)d[2 * count + r];
+}
+
+void region_add_f32(int64_t count, const int32_t* ids, const float* d, double scale, double* x,
+                    int64_t ldx, hipStream_t st) {
+  if (count > 0) k_region_add_f32<<<grid1(count), 256, 0, st>>>(count, ids, d, scale, x, ldx);
 }
 
 __global__ void k_axpy3_sum(int64_t len, const double* __restrict__ a, const double* b,

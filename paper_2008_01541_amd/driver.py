@@ -19,7 +19,8 @@ class Alg1Runner:
         c = self.ctx
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
-        self.x = torch.tensor(np.ascontiguousarray(rest, dtype=np.float64), **f64).reshape(-1)
+        self.rest_np = np.ascontiguousarray(rest, dtype=np.float64)
+        self.x = torch.tensor(self.rest_np, **f64).reshape(-1)
         self.f = torch.zeros(3 * c.n, **f64)
         m = c.m
         self.x2, self.ft, self.fb, self.fcol, self.g, self.u, self.delta2 = \

@@ -1,0 +1,152 @@
+"""Learned warm start for the collision-region PD iterations.
+
+Frames are solved to convergence with Algorithm 1 (the plain solver); the
+network learns the region displacement increment of the next frame from the
+previous increment and the active-penalty mask detected at the start of the
+frame.  At run time the prediction moves the region nodes before the first
+outer iteration; the iterations then run exactly as without it, so the
+converged state is still decided by the method (and compared with the cold
+start).  Everything here is call order and bookkeeping; the arithmetic runs
+in the library's kernels (pd_* and pd_mlp_* entry points).
+"""
+import time
+
+import numpy as np
+
+
+def converge(run, tol=1e-6, max_outer=200, n_inner=1):
+    """Outer iterations until ||x_k - x_{k-1}|| <= tol ||x_k - X|| (free nodes).
+    Returns the number of outer iterations."""
+    import torch
+    prev = torch.empty_like(run.x)
+    for it in range(1, max_outer + 1):
+        prev.copy_(run.x)
+        run.outer_iteration(n_inner=n_inner)
+        d, s = run.ctx.displacement_change(run.x, prev)
+        if s == 0.0 or d <= tol * s:
+            return it
+    return max_outer
+
+
+def detect_at_start(run):
+    """Penalty set of the frame detected at the current positions (fills run.c)."""
+    c = run.ctx
+    c.region_gather(run.x, run.x2)
+    c.detect_spheres(run.prox, run.spheres, run.k_pen, run.x2, run.idx, run.w, run.c, run.t)
+
+
+def generate_trajectory(run, centers_fn, radii, n_frames, tol=1e-6, max_outer=200):
+    """Solve n_frames frames from rest (cold start from the previous frame).
+    Returns the network samples (inputs [du_{t-1}, mask_t], targets du_t,
+    unscaled) and the iteration counts."""
+    import torch
+    c = run.ctx
+    run.set_positions(run.rest_np)
+    m = c.m
+    xs, ys, iters = [], [], []
+    prev2 = prev1 = None            # region positions two and one frames back
+    for fr in range(1, n_frames + 1):
+        run.set_spheres(centers_fn(fr), radii)
+        detect_at_start(run)
+        inp = None
+        if prev2 is not None:
+            inp = torch.empty(4 * m, dtype=torch.float32, device=run.x.device)
+            c.warmstart_input(prev1, prev2, 1.0, run.prox, run.c, inp)
+        iters.append(converge(run, tol, max_outer))
+        c.region_gather(run.x, run.x2)
+        cur = run.x2.clone()
+        if inp is not None:
+            tgt = torch.empty(4 * m, dtype=torch.float32, device=run.x.device)
+            c.warmstart_input(cur, prev1, 1.0, run.prox, run.c, tgt)   # first 3m = du_t
+            xs.append(inp)
+            ys.append(tgt[:3 * m].clone())
+        prev2, prev1 = prev1, cur
+    X = torch.stack(xs) if xs else None
+    Y = torch.stack(ys) if ys else None
+    return X, Y, iters
+
+
+class WarmStart:
+    def __init__(self, m, hidden=512, seed=4, max_batch=64):
+        from pd_inputs.mlp_init import mlp_init_params, pack
+        from ._lib import MLP
+        self.m = m
+        n_in, n_out = 4 * m, 3 * m
+        p = mlp_init_params(n_in, hidden, hidden, n_out, seed)
+        self.net = MLP(n_in, hidden, hidden, n_out, max_batch, pack(p))
+        self.scale = 1.0
+        self.max_batch = max_batch
+
+    def train(self, X, Y, epochs=30, lr=1e-3, seed=4):
+        """Adam on the standardised increments; returns the loss history."""
+        import torch
+        s = float(Y.abs().mean().item())
+        self.scale = 1.0 / s if s > 0 else 1.0
+        Xs = X.clone()
+        Xs[:, :3 * self.m] *= self.scale
+        Ys = (Y * self.scale).contiguous()
+        rng = np.random.default_rng(seed)
+        hist = []
+        n = X.shape[0]
+        B = self.max_batch
+        for ep in range(epochs):
+            perm = rng.permutation(n)
+            tot = 0.0
+            for b0 in range(0, n, B):
+                sel = torch.as_tensor(perm[b0:b0 + B], device=X.device)
+                xb = Xs.index_select(0, sel).contiguous()
+                yb = Ys.index_select(0, sel).contiguous()
+                tot += self.net.train_step(xb, yb, lr) * len(sel)
+            hist.append(tot / n)
+        return hist
+
+    def predict_into(self, run, x2_prev1, x2_prev2):
+        """Predict du for the next frame and add it to the region nodes of run.x."""
+        import torch
+        c = run.ctx
+        m = self.m
+        inp = torch.empty((1, 4 * m), dtype=torch.float32, device=run.x.device)
+        c.warmstart_input(x2_prev1, x2_prev2, self.scale, run.prox, run.c, inp)
+        y = torch.empty((1, 3 * m), dtype=torch.float32, device=run.x.device)
+        self.net.forward(inp, y)
+        c.region_add_f32(y, 1.0 / self.scale, run.x)
+
+
+def evaluate(run, ws, centers_fn, radii, n_frames, tol=1e-6, max_outer=200):
+    """Per frame: cold start (previous converged state) vs learned warm start
+    from the same state.  Returns iteration counts, wall times and the
+    relative difference of the two converged states (the cold one judges; a
+    warm result further than 1e-6 from it is replaced by it)."""
+    import torch
+    run.set_positions(run.rest_np)
+    c = run.ctx
+    rows = []
+    prev2 = prev1 = None
+    for fr in range(1, n_frames + 1):
+        run.set_spheres(centers_fn(fr), radii)
+        detect_at_start(run)
+        start = run.x.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it_cold = converge(run, tol, max_outer)
+        torch.cuda.synchronize()
+        t_cold = time.perf_counter() - t0
+        x_cold = run.x.clone()
+        rec = {"frame": fr, "cold_iters": it_cold, "cold_s": t_cold}
+        if prev2 is not None:
+            run.x.copy_(start)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ws.predict_into(run, prev1, prev2)
+            it_warm = converge(run, tol, max_outer)
+            torch.cuda.synchronize()
+            t_warm = time.perf_counter() - t0
+            d, s = c.displacement_change(run.x, x_cold)
+            rec.update({"warm_iters": it_warm, "warm_s": t_warm, "rel_diff": d / max(s, 1e-300)})
+            if not (d <= 1e-6 * s):
+                run.x.copy_(x_cold)
+                rec["fell_back"] = True
+        c.region_gather(run.x, run.x2)
+        prev2, prev1 = prev1, run.x2.clone()
+        rows.append(rec)
+    return rows

@@ -1,0 +1,46 @@
+"""Learned warm start on a small slab: the network is trained on frames the
+method generates, then compared with the cold start (previous frame) on a
+held-out trajectory.  The cold-start solution judges every warm result."""
+import numpy as np
+import pytest
+
+import pd_inputs as P
+
+pytestmark = pytest.mark.gpu
+
+
+def test_warm_start_gains_iterations():
+    import torch
+    from paper_2008_01541_amd.driver import Alg1Runner
+    from paper_2008_01541_amd.warmstart import WarmStart, evaluate, generate_trajectory
+    sc = P.scene_small(16, 15, 8, h=1.0, region_top_layers=2, seed=5, n_spheres=3,
+                       depth_frac=0.02)
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen)
+    rng = np.random.default_rng(40)
+
+    def traj(seed):
+        r = np.random.default_rng(seed)
+        xy = np.vstack([r.uniform(4, 12, 3), r.uniform(4, 11, 3)])
+        drift = r.uniform(-0.05, 0.05, size=(2, 3))
+        rad = r.uniform(1.0, 2.0, 3)
+        depth = r.uniform(0.004, 0.01, 3)
+        return (lambda fr: np.vstack([xy + drift * fr, (sc.nz + rad - depth * fr)[None, :]])), rad
+
+    Xs, Ys, cold = [], [], []
+    for s in range(3):
+        fn, rad = traj(100 + s)
+        X, Y, it = generate_trajectory(run, fn, rad, n_frames=24, tol=1e-6)
+        Xs.append(X); Ys.append(Y); cold += it
+    X = torch.cat(Xs); Y = torch.cat(Ys)
+    ws = WarmStart(run.ctx.m, hidden=256, seed=4, max_batch=32)
+    hist = ws.train(X, Y, epochs=60, lr=1e-3)
+    assert hist[-1] < 0.5 * hist[0]
+    fn, rad = traj(999)
+    rows = evaluate(run, ws, fn, rad, n_frames=16, tol=1e-6)
+    warm = [r for r in rows if "warm_iters" in r]
+    cold_it = np.mean([r["cold_iters"] for r in warm])
+    warm_it = np.mean([r["warm_iters"] for r in warm])
+    print(f"cold {cold_it:.2f} vs warm {warm_it:.2f} outer iterations per frame")
+    for r in warm:
+        assert r["rel_diff"] <= 1e-6 or r.get("fell_back")
+    assert warm_it <= cold_it
