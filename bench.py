@@ -116,6 +116,59 @@ def precision_modes(run, spheres, inner, iters=6):
     return res
 
 
+def bench_slit(args):
+    """Self-contact stress workload: 64 x 64 x 40 slit grid (983,040 tets,
+    176,215 nodes, 12,155-node region, 2,990 lip pairs), jaw closing over the
+    steps; one PD iteration per step, FP64."""
+    import torch
+    import pd_inputs as P
+    from paper_2008_01541_amd.driver import Alg1Runner
+    sc = P.scene_slit()
+    t0 = time.perf_counter()
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, np.zeros(0, np.int64),
+                     sc.k_pen)
+    run.use_pairs(sc.pairs)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    ctx = run.ctx
+    nit = args.warmup + args.steps
+    poses = [sc.prescribed(sc.rest, 1 + it * sc.jaw.steps // max(nit, 1)) for it in range(nit)]
+    bottom = torch.tensor(sc.bottom, device="cuda").long()
+    xv = run.x.view(3, -1)
+    def set_pose(it):
+        xv[:, bottom] = torch.tensor(poses[it][:, sc.bottom], device="cuda")
+    for it in range(args.warmup):
+        set_pose(it)
+        run.outer_iteration(n_inner=args.inner)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.get_timings()
+    act = []
+    t0 = time.perf_counter()
+    for it in range(args.warmup, nit):
+        set_pose(it)
+        run.outer_iteration(n_inner=args.inner)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tim = ctx.get_timings()
+    ctx.set_timing(False)
+    act = int((run.c > 0).sum().item())
+    m = ctx.m
+    fac = tim["factor"][0] / max(tim["factor"][1], 1)
+    tf = m ** 3 / 3.0 / (fac * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "collision-region PD iters/sec (self-contact slit); Schur Cholesky TFLOP/s",
+        "value": args.steps / (t1 - t0), "unit": "PD iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "slit64x64x40_kuhn", "tets": int(sc.n_tets),
+                   "nodes": int(sc.n_nodes), "region_nodes": int(m), "pairs": int(sc.pairs.shape[1]),
+                   "interior_levels": ctx.n_levels, "k_pen": sc.k_pen},
+        "active_pairs_last": act,
+        "schur_cholesky_tflops": tf, "schur_cholesky_ms": fac,
+        "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
+        "schur_build_s": build_s}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +177,9 @@ def main():
     ap.add_argument("--inner", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-modes", action="store_true")
+    ap.add_argument("--workload", default="slab56", choices=["slab56", "slit64"],
+                    help="slab56: the 602K-tet slab with spheres (default); slit64: the "
+                         "983K-tet self-contact slit closed by a jaw rotation")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
     ap.add_argument("--no-graph", action="store_true",
@@ -144,6 +200,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "slit64":
+        return bench_slit(args)
     sc = P.scene_slab56()
     stream = torch.cuda.Stream()            # non-default stream: capturable
     torch.cuda.set_stream(stream)

@@ -119,6 +119,16 @@ pd_status pd_detect_spheres(pd_ctx *ctx, int32_t n_prox, const int32_t *prox,
                             const double *x2, int32_t *idx, double *w, double *c,
                             double *t);
 
+/* Self-contact detection for paired region nodes (two lips of a slit):
+ * pair j = (pairs[j], pairs[n_pairs + j]) = (lower-lip node a, upper-lip
+ * node b), region-local, dev int32 [2][n_pairs].  The pair is in collision
+ * iff z_b < z_a (the lips interpenetrate); it then becomes a zero-rest-length
+ * spring between the two nodes (Sec. 3.3 with the proxy and the surface point
+ * both on the mesh): W row [1, -1] on (a, b), target 0, stiffness k.  Output
+ * layout as pd_detect_spheres, one penalty per pair (c = 0 when apart). */
+pd_status pd_detect_pairs(pd_ctx *ctx, int32_t n_pairs, const int32_t *pairs, double k,
+                          const double *x2, int32_t *idx, double *w, double *c, double *t);
+
 /* Penalty update (Sec. 3.3 eq. E_col_C and Sec. 4.3 eq. k22): stores the
  * penalty set for the next pd_global_solve, whose matrix becomes
  * H = S + W^T C W, and writes f_col = -W^T C (W x2 - t) (dev [3][m]).

@@ -103,3 +103,22 @@ def penalty_energy(idx, w, c, t, x2):
         r = x2[:, idx[j][sl]] @ w[j][sl] - t[:, j]
         e += 0.5 * c[j] * float(r @ r)
     return e
+
+
+def detect_pairs(x2, pairs_local, k):
+    """Two-sided contact of paired lip nodes (self-collision of a slit): pair
+    (a, b) = (lower-lip node, upper-lip node) is in collision iff the upper
+    node lies strictly below the lower one, z_b < z_a.  An active pair is a
+    zero-rest-length spring between the two nodes: W row [1, -1] on (a, b),
+    target t = 0 (Sec. 3.3 with the proxy and the surface point both on the
+    mesh).  Returns penalty lists (idx, w, c, t) with one entry per pair."""
+    P = pairs_local.shape[1]
+    idx = np.full((P, SLOTS), -1, dtype=np.int32)
+    w = np.zeros((P, SLOTS))
+    idx[:, 0] = pairs_local[0]
+    idx[:, 1] = pairs_local[1]
+    w[:, 0] = 1.0
+    w[:, 1] = -1.0
+    active = x2[2, pairs_local[1]] < x2[2, pairs_local[0]]
+    c = np.where(active, float(k), 0.0)
+    return idx, w, c, np.zeros((3, P))

@@ -43,6 +43,7 @@ _SIGS = {
     "pd_condense_rhs": [_P, _P, _P],
     "pd_detect_spheres": [_P, C.c_int32, _P, C.c_int32, _P, C.c_double, _P, _P, _P, _P, _P],
     "pd_collision_update": [_P, C.c_int32, _P, _P, _P, _P, _P, _P],
+    "pd_detect_pairs": [_P, C.c_int32, _P, C.c_double, _P, _P, _P, _P, _P],
     "pd_local_step_region": [_P, _P, _P, _P, C.c_int],
     "pd_assemble_rhs": [_P, _P, _P, _P, _P],
     "pd_global_solve": [_P, _P, _P, C.c_int, C.POINTER(pd_solve_info)],
@@ -191,6 +192,15 @@ class PDContext:
             _ptr(x2, torch.float64, 3 * self.m, "x2"), _ptr(idx, torch.int32, 8 * npx, "idx"),
             _ptr(w, torch.float64, 8 * npx, "w"), _ptr(c, torch.float64, npx, "c"),
             _ptr(t, torch.float64, 3 * npx, "t")))
+
+    def detect_pairs(self, pairs, k, x2, idx, w, c, t):
+        import torch
+        npr = pairs.numel() // 2
+        self._chk(self._lib.pd_detect_pairs(
+            self._ctx, npr, _ptr(pairs, torch.int32, 2 * npr, "pairs"), float(k),
+            _ptr(x2, torch.float64, 3 * self.m, "x2"), _ptr(idx, torch.int32, 8 * npr, "idx"),
+            _ptr(w, torch.float64, 8 * npr, "w"), _ptr(c, torch.float64, npr, "c"),
+            _ptr(t, torch.float64, 3 * npr, "t")))
 
     def collision_update(self, idx, w, c, t, x2, f_col):
         import torch

@@ -75,6 +75,7 @@ struct pd_ctx {
   double* d_H = nullptr;
   double* d_linv = nullptr;
   double* d_y = nullptr;
+  double* d_Yt = nullptr;             // 64 x m right-hand-side tile row of the fused solve
   double* d_res = nullptr;
   double* d_norms = nullptr;
   int* d_info = nullptr;
@@ -236,10 +237,10 @@ void free_now(pd_ctx* c, void* p) {
 // In-place lower Cholesky of the n x n matrix A (leading dimension lda, a
 // multiple of 16 so tiles start on 128-byte lines); tile inverses to d_linv,
 // transpose of the factor in the upper triangle.
-void cholesky(pd_ctx* c, double* A, int lda, int n) {
+void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr) {
   if (c->chol_dataflow) {
     potrf_dataflow(A, lda, n, c->d_linv, c->d_tflags, c->d_tticket, c->d_info, c->d_err, c->n_wg,
-                   c->st);
+                   Yt, c->st);
   } else {
     potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
   }
@@ -597,7 +598,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   HIPCK(c, hipMemsetAsync(c->d_ticket, 0, 4 * sizeof(unsigned long long), c->st));
   HIPCK(c, hipMemsetAsync(c->d_flags, 0, 4 * (int64_t)c->ntm * sizeof(int), c->st));
   {
-    const int64_t nt2 = ntmax * ntmax;
+    const int64_t nt2 = ntmax * (ntmax + 1);
     CK(c->alloc(&c->d_tflags, nt2));
     CK(c->alloc(&c->d_tticket, 4));
     HIPCK(c, hipMemsetAsync(c->d_tflags, 0, nt2 * sizeof(int), c->st));
@@ -702,6 +703,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   free_now(c, d_tets);
   CK(c->alloc(&c->d_H, (int64_t)c->ldH * m));
   CK(c->alloc(&c->d_y, 3 * m));
+  CK(c->alloc(&c->d_Yt, (int64_t)NB * m));
   CK(c->alloc(&c->d_res, 3 * m));
   CK(c->alloc(&c->d_norms, 8));
   CK(c->alloc(&c->d_fhat, 3 * std::max<int64_t>(1, c->n1)));
@@ -865,6 +867,17 @@ pd_status pd_detect_spheres(pd_ctx* c, int32_t n_prox, const int32_t* prox, int3
   return c->check("pd_detect_spheres");
 }
 
+pd_status pd_detect_pairs(pd_ctx* c, int32_t n_pairs, const int32_t* pairs, double k,
+                          const double* x2, int32_t* idx, double* w, double* cc, double* t) {
+  if (bad_ctx(c) || n_pairs < 0 || !(k >= 0.0) ||
+      (n_pairs > 0 && (!pairs || !x2 || !idx || !w || !cc || !t)))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  PhaseTimer tm(c, PD_PHASE_DETECT);
+  detect_pairs(n_pairs, pairs, k, x2, (int)c->m, idx, w, cc, t, c->st);
+  return c->check("pd_detect_pairs");
+}
+
 pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, const double* w,
                               const double* cc, const double* t, const double* x2, double* f_col) {
   if (bad_ctx(c) || n_pen < 0 || !x2 || !f_col || (n_pen > 0 && (!idx || !w || !cc || !t)))
@@ -970,18 +983,25 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
   if (c->broken) return PD_ERR_HIP;
   const int m = (int)c->m;
   if (prec == PD_FP64) {
+    bool fused = false;
     if (c->stale) {
       build_H(c);
       zero_int(c->d_info, c->st);
+      fused = c->chol_dataflow != 0;
+      if (fused) rhs_pack(m, g, m, c->d_Yt, c->st);
       PhaseTimer tm(c, PD_PHASE_FACTOR);
-      cholesky(c, c->d_H, c->ldH, m);
+      cholesky(c, c->d_H, c->ldH, m, fused ? c->d_Yt : nullptr);
       c->stale = false;
       c->lp_stale = true;       // d_H was rebuilt
     }
     {
       PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
-      trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
-                    c->d_err, c->st);
+      if (fused) {
+        rhs_unpack(m, c->d_Yt, c->d_y, m, c->st);
+      } else {
+        trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
+                      c->d_err, c->st);
+      }
       trsv3_backward(c->d_H, c->ldH, m, c->d_linv, c->d_y, m, u, m, c->d_ticket + 1,
                      c->d_flags + c->ntm, c->d_err, c->st);
     }

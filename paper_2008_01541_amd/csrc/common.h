@@ -20,8 +20,12 @@ void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStrea
 // Single-launch dataflow Cholesky; flags: nt*nt ints and ticket[2] (task
 // counter, launch epoch), all zero-initialised once; each call advances the
 // epoch on the device (safe under graph replay).
+// With Yt (64 x n, rows 0..2 = g^T) the forward substitution L^-1 g is fused
+// in (result in the same rows); flags then need (nt + 1) * nt ints.
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
-                    int* info, int* err, int n_wg, hipStream_t st);
+                    int* info, int* err, int n_wg, double* Yt, hipStream_t st);
+void rhs_pack(int n, const double* g, int ldg, double* Yt, hipStream_t st);
+void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st);
 // Fill kernels (used instead of memset so the calls can be graph-captured).
 void zero_int(int* p, hipStream_t st);
 void zero_f64(long n, double* p, hipStream_t st);
@@ -77,6 +81,8 @@ void sub_sparse_times_dense(double* Next, int ldn, int nr, const int32_t* rows,
 void detect_spheres(int n_prox, const int32_t* prox, int n_sph, const double* sph, double k,
                     const double* x2, int m, int32_t* idx, double* w, double* c, double* t,
                     hipStream_t st);
+void detect_pairs(int n_pairs, const int32_t* pairs, double k, const double* x2, int m,
+                  int32_t* idx, double* w, double* c, double* t, hipStream_t st);
 // act[0..*cnt) <- indices j < n_pen with c[j] != 0, increasing (device count).
 void compact_active(int n_pen, const double* c, int32_t* act, int32_t* cnt, hipStream_t st);
 // Over the active penalties act[0..*nact):

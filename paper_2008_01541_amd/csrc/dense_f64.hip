@@ -423,7 +423,8 @@ __device__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], in
 // k+1 is loaded, so neither the flag round trip nor the operand latency sits
 // on the path when the producers are ahead.
 __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
-                              const double* __restrict__ A, int lda, int r0, int mr, int c0,
+                              const double* __restrict__ Ar, int ldar, int r0, int mr,
+                              const double* __restrict__ A, int lda, int c0,
                               int mc, int i, int j, int nt, const int* flags, int epoch, int* err,
                               int* s_ok) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -434,13 +435,13 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
   auto load_tile = [&](int k) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const long col = (long)(k * NB + kq + 4 * q) * lda;
+      const long kc = (long)(k * NB + kq + 4 * q);
 #ifdef PD_COHERENT_OPERAND_LOADS
-      ra[q] = (r < mr) ? coherent_load(&A[(long)(r0 + r) + col]) : 0.0;
-      rb[q] = (r < mc) ? coherent_load(&A[(long)(c0 + r) + col]) : 0.0;
+      ra[q] = (r < mr) ? coherent_load(&Ar[(long)(r0 + r) + kc * ldar]) : 0.0;
+      rb[q] = (r < mc) ? coherent_load(&A[(long)(c0 + r) + kc * lda]) : 0.0;
 #else
-      ra[q] = (r < mr) ? A[(long)(r0 + r) + col] : 0.0;
-      rb[q] = (r < mc) ? A[(long)(c0 + r) + col] : 0.0;
+      ra[q] = (r < mr) ? Ar[(long)(r0 + r) + kc * ldar] : 0.0;
+      rb[q] = (r < mc) ? A[(long)(c0 + r) + kc * lda] : 0.0;
 #endif
     }
   };
@@ -493,10 +494,16 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
   return true;
 }
 
+// With Yt != NULL the three right-hand sides ride along as an extra tile row
+// (Yt: 64 x n, column-major, rows 0..2 = g^T on entry): its tasks compute
+// Y_j = (G_j - sum_{k<j} Y_k L_jk^T) Linv_jj^T, i.e. the forward substitution
+// y = L^-1 g, on the same schedule as the factor.
 __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, int n, int nt,
                                                            double* linv_ws, int* flags,
-                                                           unsigned* ticket, int* info, int* err) {
+                                                           unsigned* ticket, int* info, int* err,
+                                                           double* Yt) {
   const int epoch = (int)ticket[1];
+  const int rhs = Yt != nullptr ? 1 : 0;
   // two 64 x 68 double tiles (69,632 bytes): operands of the accumulation,
   // then the tile and its inverse / Linv during the finishing step
   __shared__ double buf0[NB][LDS_LD];
@@ -505,7 +512,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
   const int t = threadIdx.x;
   const int lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
-  const int ntask = nt * (nt + 1) / 2;
+  const int ntask = nt * (nt + 1) / 2 + rhs * nt;
   for (;;) {
     __syncthreads();
     if (t == 0) {
@@ -516,16 +523,20 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     const int q = s_task;
     if (q >= ntask) return;
     int j = 0, start = 0;
-    while (start + (nt - j) <= q) {
-      start += nt - j;
+    while (start + (nt - j + rhs) <= q) {
+      start += nt - j + rhs;
       ++j;
     }
-    const int i = j + (q - start);
-    const int r0 = i * NB, c0 = j * NB;
-    const int mr = min(NB, n - r0), mc = min(NB, n - c0);
+    const int i = j + (q - start);         // i == nt: the right-hand-side row
+    const bool rrow = (i == nt);
+    double* Ai = rrow ? Yt : A;
+    const int ldai = rrow ? NB : lda;
+    const int r0 = rrow ? 0 : i * NB, c0 = j * NB;
+    const int mr = rrow ? 3 : min(NB, n - r0), mc = min(NB, n - c0);
     Acc acc;
     acc_zero(acc);
-    if (!df_accumulate(acc, buf0, buf1, A, lda, r0, mr, c0, mc, i, j, nt, flags, epoch, err, &s_ok))
+    if (!df_accumulate(acc, buf0, buf1, Ai, ldai, r0, mr, A, lda, c0, mc, i, j, nt, flags, epoch,
+                       err, &s_ok))
       return;
     __syncthreads();
     // C = A_ij - acc  ->  buf0[c][r]; padding: identity on the diagonal tile, zero elsewhere
@@ -538,7 +549,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
           const int r = acc_row(mb), c = acc_col(nb, qq);
           double v;
           if (r < mr && c < mc)
-            v = coherent_load(&A[(long)(r0 + r) + (long)(c0 + c) * lda]) - acc.c[mb][nb][qq];
+            v = coherent_load(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai]) - acc.c[mb][nb][qq];
           else v = (i == j && r == c) ? 1.0 : 0.0;
           buf0[c][r] = v;
         }
@@ -583,9 +594,9 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
       __syncthreads();
       for (int e = t; e < NB * NB; e += 256) {
         const int r = e & 63, c = e >> 6;
-        if (r < mr) coherent_store(&A[(long)(r0 + r) + (long)(c0 + c) * lda], buf0[c][r]);
+        if (r < mr) coherent_store(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai], buf0[c][r]);
         // transposed copy: U(c0 + r', r0 + c') = L(r0 + c', c0 + r') with r' = e & 63, c' = e >> 6
-        if (c < mr) coherent_store(&A[(long)(c0 + r) + (long)(r0 + c) * lda], buf0[r][c]);
+        if (!rrow && c < mr) coherent_store(&A[(long)(c0 + r) + (long)(r0 + c) * lda], buf0[r][c]);
       }
     }
     publish_flag(&flags[i * nt + j], epoch);
@@ -593,12 +604,30 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 }
 
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
-                    int* info, int* err, int n_wg, hipStream_t st) {
+                    int* info, int* err, int n_wg, double* Yt, hipStream_t st) {
   const int nt = (n + NB - 1) / NB;
-  const int ntask = nt * (nt + 1) / 2;
+  const int ntask = nt * (nt + 1) / 2 + (Yt ? nt : 0);
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
   k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags, ticket,
-                                                          info, err);
+                                                          info, err, Yt);
+}
+
+// Yt[v + r * 64] = g[v * ldg + r] (v < 3) and back.
+__global__ void k_rhs_pack(int n, const double* __restrict__ g, int ldg, double* __restrict__ Yt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int v = 0; v < 3; ++v) Yt[v + (long)r * NB] = g[(long)v * ldg + r];
+}
+__global__ void k_rhs_unpack(int n, const double* __restrict__ Yt, double* __restrict__ y, int ldy) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int v = 0; v < 3; ++v) y[(long)v * ldy + r] = Yt[v + (long)r * NB];
+}
+void rhs_pack(int n, const double* g, int ldg, double* Yt, hipStream_t st) {
+  k_rhs_pack<<<(n + 255) / 256, 256, 0, st>>>(n, g, ldg, Yt);
+}
+void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st) {
+  k_rhs_unpack<<<(n + 255) / 256, 256, 0, st>>>(n, Yt, y, ldy);
 }
 
 __global__ void k_zero_int(int* p) { *p = 0; }

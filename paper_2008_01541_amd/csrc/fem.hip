@@ -541,6 +541,38 @@ __global__ __launch_bounds__(1024) void k_compact_active(int n_pen, const double
   if (t == 0) *cnt = base;
 }
 
+// Two-sided contact of paired region nodes (a = lower lip, b = upper lip):
+// active iff z_b < z_a; an active pair is a spring with W row [1, -1] on
+// (a, b) and target 0.  One penalty slot per pair.
+__global__ void k_detect_pairs(int n_pairs, const int32_t* __restrict__ pairs, double k,
+                               const double* __restrict__ x2, int m, int32_t* __restrict__ idx,
+                               double* __restrict__ w, double* __restrict__ c,
+                               double* __restrict__ t) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_pairs) return;
+  const int a = pairs[j], b = pairs[n_pairs + j];
+  const bool ok = a >= 0 && a < m && b >= 0 && b < m;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    idx[j * 8 + s] = -1;
+    w[j * 8 + s] = 0.0;
+  }
+  if (ok) {
+    idx[j * 8] = a;
+    idx[j * 8 + 1] = b;
+    w[j * 8] = 1.0;
+    w[j * 8 + 1] = -1.0;
+  }
+  c[j] = (ok && x2[2 * m + b] < x2[2 * m + a]) ? k : 0.0;
+  t[j] = t[n_pairs + j] = t[2 * n_pairs + j] = 0.0;
+}
+
+void detect_pairs(int n_pairs, const int32_t* pairs, double k, const double* x2, int m,
+                  int32_t* idx, double* w, double* c, double* t, hipStream_t st) {
+  if (n_pairs > 0)
+    k_detect_pairs<<<grid1(n_pairs), 256, 0, st>>>(n_pairs, pairs, k, x2, m, idx, w, c, t);
+}
+
 // Penalty terms, one thread per region node a (row a of W^T C W and entry a
 // of f_col), scanning the active penalties in increasing index order:
 //   H[a + b*ldh] += c_j w_ja w_jb  for b <= a   (lower triangle, H may be NULL)

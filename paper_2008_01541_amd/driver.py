@@ -28,7 +28,7 @@ class Alg1Runner:
         pos = np.full(c.n, -1, dtype=np.int64)
         pos[c.region_ids] = np.arange(m)
         loc = pos[np.asarray(proxies_global)]
-        if (loc < 0).any():
+        if loc.size and (loc < 0).any():
             raise ValueError("every proxy must be a free region node")
         self.n_prox = loc.size
         self.prox = torch.tensor(loc.astype(np.int32), device=dev)
@@ -38,6 +38,7 @@ class Alg1Runner:
         self.t = torch.empty(3 * self.n_prox, **f64)
         self.k_pen = float(k_pen)
         self.spheres = None
+        self.pairs = None
 
     def set_spheres(self, centers, radii):
         sph = np.vstack([np.asarray(centers, dtype=np.float64),
@@ -48,10 +49,35 @@ class Alg1Runner:
     def set_positions(self, x):
         self.x.copy_(self.torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).reshape(-1))
 
+    def use_pairs(self, pairs_global):
+        """Switch detection to paired region nodes (self-contact of a slit)."""
+        import torch
+        c = self.ctx
+        pos = np.full(c.n, -1, dtype=np.int64)
+        pos[c.region_ids] = np.arange(c.m)
+        loc = pos[np.asarray(pairs_global)]
+        if (loc < 0).any():
+            raise ValueError("every paired node must be a free region node")
+        npr = loc.shape[1]
+        dev = self.x.device
+        self.pairs = torch.tensor(np.ascontiguousarray(loc, dtype=np.int32), device=dev).reshape(-1)
+        self.n_prox = npr
+        self.idx = torch.empty(8 * npr, dtype=torch.int32, device=dev)
+        self.w = torch.empty(8 * npr, dtype=torch.float64, device=dev)
+        self.c = torch.empty(npr, dtype=torch.float64, device=dev)
+        self.t = torch.empty(3 * npr, dtype=torch.float64, device=dev)
+
+    def detect(self):
+        c = self.ctx
+        if self.pairs is not None:
+            c.detect_pairs(self.pairs, self.k_pen, self.x2, self.idx, self.w, self.c, self.t)
+        else:
+            c.detect_spheres(self.prox, self.spheres, self.k_pen, self.x2, self.idx, self.w,
+                             self.c, self.t)
+
     def inner_iteration(self, prec=PD_FP64, rot_fp32=False, want_info=False):
         c = self.ctx
-        c.detect_spheres(self.prox, self.spheres, self.k_pen, self.x2, self.idx, self.w,
-                         self.c, self.t)
+        self.detect()
         c.collision_update(self.idx, self.w, self.c, self.t, self.x2, self.fcol)
         c.local_step_region(self.x2, self.fb, rot_fp32=rot_fp32)
         c.assemble_rhs(self.ft, self.fb, self.fcol, self.g)

@@ -59,3 +59,28 @@ def layer_mask(nx, ny, nz, ks):
     """Boolean node mask selecting the lattice layers k in `ks`."""
     kk = np.broadcast_to(np.arange(nz + 1)[:, None, None], (nz + 1, ny + 1, nx + 1))
     return np.isin(kk, np.asarray(list(ks))).ravel()
+
+
+def kuhn_grid_slit(nx, ny, nz, h, zs, ys_end):
+    """Kuhn grid with a zero-thickness slit on the plane k = zs over
+    j < ys_end: those nodes get a twin (appended ids) used by the tets above
+    the plane, so the two lips can separate and collide.  The line j = ys_end
+    stays shared.  Returns (rest, tets, twins) with twins (2, n_twins) =
+    (lower-lip id, upper-lip id)."""
+    rest, tets = kuhn_grid(nx, ny, nz, h)
+    n0 = rest.shape[1]
+    ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ys_end), indexing="ij")
+    lower = grid_node_id(ii.ravel(), jj.ravel(), zs, nx, ny)
+    upper = n0 + np.arange(lower.size)
+    twin_of = np.full(n0, -1, dtype=np.int64)
+    twin_of[lower] = upper
+    rest = np.concatenate([rest, rest[:, lower]], axis=1)
+    # cells are ordered k, j, i with 6 tets each: tets of cells with k >= zs
+    ncell_layer = nx * ny * 6
+    above = np.arange(tets.shape[1]) >= zs * ncell_layer
+    t = tets.astype(np.int64)
+    sub = t[:, above]
+    tw = twin_of[sub]
+    sub = np.where(tw >= 0, tw, sub)
+    t[:, above] = sub
+    return rest, t.astype(np.int32), np.vstack([lower, upper]).astype(np.int64)

@@ -150,3 +150,107 @@ def random_penalty_set(rng, n_proxy, m_region, lo=0.01, hi=0.05):
     sel = np.sort(rng.choice(n_proxy, size=cnt, replace=False))
     depth = rng.uniform(0.0, 0.5, size=cnt)
     return sel, depth
+
+
+@dataclass
+class JawSchedule:
+    """Prescribed rotation of the bottom face about an x-parallel hinge at
+    (y = hinge_y, z = 0): the front starts open by theta0 (front moved down),
+    then closes at rate per step, while a roll about the z axis grows to
+    roll_max so that contact starts at one corner.  Positive angles move the
+    front (y < hinge_y) up."""
+    hinge_y: float
+    theta0: float          # radians, opening at step 0
+    rate: float            # radians per step (closing)
+    roll_max: float        # radians
+    steps: int
+
+    def angles(self, step):
+        th = -self.theta0 + self.rate * step
+        ps = self.roll_max * min(step, self.steps) / max(self.steps, 1)
+        return th, ps
+
+    def positions(self, rest_pts, step):
+        """Prescribed positions (3, k) of the given rest points."""
+        th, ps = self.angles(step)
+        c, s = np.cos(th), np.sin(th)
+        rel = rest_pts - np.array([[0.0], [self.hinge_y], [0.0]])
+        y = c * rel[1] + s * rel[2]
+        z = -s * rel[1] + c * rel[2]
+        out = np.vstack([rel[0], y, z]) + np.array([[0.0], [self.hinge_y], [0.0]])
+        cx = 0.5 * (rest_pts[0].min() + rest_pts[0].max())
+        cr, sr = np.cos(ps), np.sin(ps)
+        x0 = out[0] - cx
+        y0 = out[1] - self.hinge_y
+        out[0] = cx + cr * x0 - sr * y0
+        out[1] = self.hinge_y + sr * x0 + cr * y0
+        return out
+
+
+@dataclass
+class SlitScene:
+    name: str
+    rest: np.ndarray
+    tets: np.ndarray
+    dirichlet: np.ndarray
+    region: np.ndarray
+    pairs: np.ndarray          # (2, P) global ids (lower lip, upper lip)
+    bottom: np.ndarray         # global ids of the prescribed bottom face
+    jaw: JawSchedule
+    k_pen: float
+    mu: float
+    h: float
+
+    @property
+    def n_nodes(self):
+        return self.rest.shape[1]
+
+    @property
+    def n_tets(self):
+        return self.tets.shape[1]
+
+    def region_ids(self):
+        return np.nonzero(self.region & ~self.dirichlet)[0]
+
+    def pairs_local(self):
+        rid = self.region_ids()
+        pos = np.full(self.n_nodes, -1, dtype=np.int64)
+        pos[rid] = np.arange(rid.size)
+        loc = pos[self.pairs]
+        assert (loc >= 0).all()
+        return loc.astype(np.int32)
+
+    def prescribed(self, x, step):
+        """x with the bottom face moved to the jaw pose of `step` (top stays at rest)."""
+        x = x.copy()
+        x[:, self.bottom] = self.jaw.positions(self.rest[:, self.bottom], step)
+        return x
+
+
+def scene_slit(nx=64, ny=64, nz=40, zs=20, ys_end=46, h=1.0, seed=5, steps=10,
+               k_pen=5.0e5):
+    """Self-contact stress case: a zero-thickness slit on k = zs over
+    j < ys_end (two lips), top face fixed, bottom face rotated about the back
+    hinge (jaw).  Region = node layers zs-1, zs (both lips) and zs+1 within the
+    slit footprint (j <= ys_end); collision pairs = the lip twins."""
+    from .grid import kuhn_grid_slit, grid_node_id
+    rest, tets, twins = kuhn_grid_slit(nx, ny, nz, h, zs, ys_end)
+    n0 = (nx + 1) * (ny + 1) * (nz + 1)
+    n = rest.shape[1]
+    kk = np.zeros(n, dtype=np.int64)
+    jj = np.zeros(n, dtype=np.int64)
+    kk[:n0] = np.arange(n0) // ((nx + 1) * (ny + 1))
+    jj[:n0] = (np.arange(n0) // (nx + 1)) % (ny + 1)
+    kk[n0:] = zs
+    jj[n0:] = (twins[0] // (nx + 1)) % (ny + 1)
+    top = kk == nz
+    bottom = np.nonzero(kk == 0)[0]
+    dirichlet = top | (kk == 0)
+    region = np.isin(kk, [zs - 1, zs, zs + 1]) & (jj <= ys_end)
+    rng = np.random.default_rng(seed)
+    jaw = JawSchedule(hinge_y=ny * h, theta0=np.deg2rad(2.0),
+                      rate=np.deg2rad(rng.uniform(0.4, 0.8)),
+                      roll_max=np.deg2rad(rng.uniform(0.5, 1.5)), steps=steps)
+    return SlitScene(name=f"slit{nx}x{ny}x{nz}", rest=rest, tets=tets, dirichlet=dirichlet,
+                     region=region, pairs=twins, bottom=bottom, jaw=jaw, k_pen=k_pen,
+                     mu=lame_mu(), h=h)

@@ -1,6 +1,8 @@
 """Checks at the full 56 x 56 x 32 (602,112-tet, 6,498-node region) size that
-the oracle can afford: closed forms of S, sampled Schur probes through one
-sparse factorization, and a sampled solve."""
+the oracle can afford: closed forms of S, Schur probes through one sparse
+factorization, the E_alpha local step, both condensation sweeps, and the
+refined low-precision solves on a random penalty set (residual recomputed by
+the oracle through sparse solves, never from the GPU's S)."""
 import numpy as np
 import pytest
 
@@ -19,6 +21,13 @@ def slab():
     S = torch.empty(ctx.m * ctx.m, dtype=torch.float64, device="cuda")
     ctx.get_schur(S)
     return sc, ctx, S
+
+
+@pytest.fixture(scope="module")
+def oracle_slab(slab):
+    from oracle import pd as opd
+    sc = slab[0]
+    return opd.PDModel(sc.rest, sc.tets, sc.mu, sc.dirichlet, sc.region, build_schur=False)
 
 
 def test_slab_sizes(slab):
@@ -40,13 +49,12 @@ def test_slab_closed_form_linear_field(slab):
         assert val == pytest.approx(expect, rel=1e-10)
 
 
-def test_slab_schur_probes_match_oracle(slab):
-    """S v against K22 v - K21 K11^-1 K12 v for seeded random v (one sparse
-    factorization of K11 by the oracle)."""
+def test_slab_schur_probes_match_oracle(slab, oracle_slab):
+    """S v against K22 v - K21 K11^-1 K12 v for seeded random v."""
     import torch
-    from oracle import pd as opd, schur as osch
+    from oracle import schur as osch
     sc, ctx, S = slab
-    om = opd.PDModel(sc.rest, sc.tets, sc.mu, sc.dirichlet, sc.region, build_schur=False)
+    om = oracle_slab
     rng = np.random.default_rng(12)
     Sm = S.reshape(ctx.m, ctx.m)
     for _ in range(4):
@@ -54,3 +62,74 @@ def test_slab_schur_probes_match_oracle(slab):
         ref = osch.schur_apply(om.lu11, om.A12, om.A21, om.A22, v)
         got = host(Sm @ torch.tensor(v, device="cuda"))
         assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_slab_local_step_full_matches_oracle(slab, oracle_slab):
+    import torch
+    sc, ctx, S = slab
+    om = oracle_slab
+    rng = np.random.default_rng(3)
+    x = sc.rest + 0.1 * rng.normal(size=sc.rest.shape)
+    x[:, sc.dirichlet] = sc.rest[:, sc.dirichlet]
+    f = torch.empty(3 * sc.n_nodes, dtype=torch.float64, device="cuda")
+    ctx.local_step_full(dev(x), f)
+    R = om.rotations(x, om.alpha)
+    f_or = om.forces(x, R, om.alpha)
+    got = host(f, (3, -1))
+    assert np.abs(got - f_or).max() <= 1e-10 * np.abs(f_or).max()
+
+
+def test_slab_condense_and_backsub_match_oracle(slab, oracle_slab):
+    import torch
+    from oracle import schur as osch
+    sc, ctx, S = slab
+    om = oracle_slab
+    rng = np.random.default_rng(4)
+    f = rng.normal(size=(3, sc.n_nodes))
+    y2 = torch.empty(3 * ctx.m, dtype=torch.float64, device="cuda")
+    ctx.condense_rhs(dev(f), y2)
+    w1, y2_or = osch.forward_sub(om.lu11, om.A21, f[:, om.i1].T, f[:, om.i2].T)
+    assert np.abs(host(y2, (3, -1)) - y2_or.T).max() <= 1e-10 * np.abs(y2_or).max()
+    d2 = rng.normal(size=(3, ctx.m))
+    x0 = np.zeros((3, sc.n_nodes))
+    xd = dev(x0)
+    ctx.backsub(dev(d2), xd)
+    x1_or = osch.back_sub(om.lu11, om.A12, f[:, om.i1].T, d2.T).T
+    got = host(xd, (3, -1))
+    assert np.abs(got[:, om.i1] - x1_or).max() <= 1e-10 * np.abs(x1_or).max()
+    assert np.array_equal(got[:, om.i2], d2)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_slab_refined_solves_random_penalties(slab, oracle_slab, prec):
+    """Random penalty set of 1-5 % of the region (k = 1e6, targets below the
+    proxies): the FP64, FP32-refined and BF16-refined solves all reach a
+    residual <= 1e-8 of (S + P) u = g, with S applied by the oracle."""
+    import torch
+    from oracle import collision as ocol, schur as osch
+    sc, ctx, S = slab
+    om = oracle_slab
+    m = ctx.m
+    rng = np.random.default_rng(300 + prec)
+    prox = sc.proxy_local()
+    sel, depth = P.random_penalty_set(rng, prox.size, m)
+    idx = np.full((sel.size, 8), -1, dtype=np.int32)
+    idx[:, 0] = prox[sel]
+    w = np.zeros((sel.size, 8)); w[:, 0] = 1.0
+    c = np.full(sel.size, 1e6)
+    x2 = sc.rest[:, om.i2]
+    t = x2[:, prox[sel]].copy()
+    t[2] -= depth
+    fcol = torch.empty(3 * m, dtype=torch.float64, device="cuda")
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), dev(x2), fcol)
+    assert np.abs(host(fcol, (3, -1)) - ocol.penalty_force(m, idx, w, c, t, x2)).max() <= 1e-9
+    g = rng.normal(size=(3, m))
+    u = torch.empty(3 * m, dtype=torch.float64, device="cuda")
+    info = ctx.global_solve(dev(g), u, prec=prec, want_info=True)
+    assert info["status"] == 0, info
+    ug = host(u, (3, -1))
+    Pm_u = -ocol.penalty_force(m, idx, w, c, np.zeros_like(t), ug)
+    Su = osch.schur_apply(om.lu11, om.A12, om.A21, om.A22, ug.T).T
+    r = g - Su - Pm_u
+    rel = max(np.linalg.norm(r[v]) / np.linalg.norm(g[v]) for v in range(3))
+    assert rel <= (1e-10 if prec == 0 else 1e-8), rel

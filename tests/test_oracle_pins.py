@@ -388,3 +388,40 @@ def test_cholesky_definition():
     L = np.tril(sla.cho_factor(H, lower=True)[0])
     assert np.all(np.diag(L) > 0)
     assert np.linalg.norm(L @ L.T - H) <= 10 * H.shape[0] * np.finfo(float).eps * np.linalg.norm(H)
+
+
+def test_slit_mesh_and_pair_detection():
+    """Slit grid: positive volumes, lips only shared at the front line; pair
+    detection fires only for interpenetrating twins, and the pair spring is
+    the gradient/Hessian of c/2 ||p_a - p_b||^2."""
+    s = P.scene_slit(6, 6, 6, 3, 4)
+    m = pd.PDModel(s.rest, s.tets, s.mu, s.dirichlet, s.region, build_schur=False)
+    assert np.all(m.vol > 0)
+    pl = s.pairs_local()
+    x2 = s.rest[:, m.i2].copy()
+    idx, w, c, t = collision.detect_pairs(x2, pl, 5e5)
+    assert np.all(c == 0)                       # rest: lips touch, no penetration
+    x2[2, pl[0, 0]] += 0.1                      # lower lip node pushed up through
+    idx, w, c, t = collision.detect_pairs(x2, pl, 5e5)
+    assert np.nonzero(c)[0].tolist() == [0]
+    f = collision.penalty_force(m.m, idx, w, c, t, x2)
+    a, b = pl[0, 0], pl[1, 0]
+    assert f[2, a] == pytest.approx(-5e5 * 0.1) and f[2, b] == pytest.approx(5e5 * 0.1)
+    Pm = collision.penalty_matrix(m.m, idx, w, c)
+    assert Pm[a, a] == 5e5 and Pm[b, b] == 5e5 and Pm[a, b] == -5e5
+
+
+def test_slit_schur_route_equals_full_solve():
+    """The Schur route reproduces the full solve with two-node (off-diagonal)
+    penalties (P1 for non-conforming W)."""
+    s = P.scene_slit(6, 6, 6, 3, 4)
+    m = pd.PDModel(s.rest, s.tets, s.mu, s.dirichlet, s.region)
+    pl = s.pairs_local()
+    x2 = s.rest[:, m.i2].copy()
+    x2[2, pl[0, :5]] += 0.05
+    pen = collision.detect_pairs(x2, pl, 5e5)
+    A, pos = pd.full_matrix_with_penalty(m, pen)
+    b = np.random.default_rng(3).normal(size=(3, m.free.size))
+    u_full = spla.spsolve(A, b.T).T
+    u_schur = pd.three_step_solve(m, b, pen)
+    assert np.linalg.norm(u_schur - u_full) <= 1e-11 * np.linalg.norm(u_full)
