@@ -182,8 +182,8 @@ def main():
                          "983K-tet self-contact slit closed by a jaw rotation")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="time eager launches only (default: also replay a HIP graph of one iteration)")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time replays of a HIP graph of one iteration (experimental)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
@@ -235,7 +235,7 @@ def main():
     eager_value = args.steps / (t1 - t0)
     value = eager_value
     graph_value = None
-    if not args.no_graph:
+    if args.graph:
         # one outer iteration captured into a HIP graph; frames change by
         # copying the next sphere positions into the captured input buffer
         sph_buf = run.spheres.clone()

@@ -102,6 +102,9 @@ struct pd_ctx {
   // sweeps
   double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
   bool have_condense = false;
+  SweepDesc sweep{};                  // device descriptor of the levels (cooperative sweeps)
+  unsigned* d_bar = nullptr;
+  bool coop_sweeps = true;
   // penalties
   int32_t n_pen = 0, pen_cap = 0;
   int32_t* d_pidx = nullptr;
@@ -710,6 +713,37 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&c->d_v, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_xs, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_tmp, 3 * std::max<int64_t>(1, c->maxw)));
+  // descriptor of the levels for the single-launch sweeps
+  {
+    SweepDesc& d = c->sweep;
+    d.K = c->K;
+    d.n1 = c->n1;
+    d.m = c->m;
+    d.maxw = c->maxw;
+    d.levmat = c->d_levmat;
+    d.Bptr = c->d_Bptr; d.Bcol = c->d_Bcol; d.Bval = c->d_Bval;
+    d.Btptr = c->d_Btptr; d.Btcol = c->d_Btcol; d.Btval = c->d_Btval;
+    std::vector<long> lo(c->lev_off.begin(), c->lev_off.end());
+    std::vector<long> mo(c->lev_mat_off.begin(), c->lev_mat_off.end());
+    std::vector<int> lw(c->ldw.begin(), c->ldw.begin() + std::max(c->K, 0));
+    std::vector<long> bpo(c->B_ptr_off.begin(), c->B_ptr_off.end());
+    std::vector<long> bno(c->B_nnz_off.begin(), c->B_nnz_off.end());
+    std::vector<long> tpo(c->Bt_ptr_off.begin(), c->Bt_ptr_off.end());
+    std::vector<long> tno(c->Bt_nnz_off.begin(), c->Bt_nnz_off.end());
+    long *a, *b2, *e1, *e2, *e3, *e4;
+    int* f;
+    CK(c->upload(&a, lo)); CK(c->upload(&b2, mo)); CK(c->upload(&f, lw));
+    CK(c->upload(&e1, bpo)); CK(c->upload(&e2, bno)); CK(c->upload(&e3, tpo)); CK(c->upload(&e4, tno));
+    d.lev_off = a; d.mat_off = b2; d.ldw = f;
+    d.B_ptr_off = e1; d.B_nnz_off = e2; d.Bt_ptr_off = e3; d.Bt_nnz_off = e4;
+    CK(c->alloc(&c->d_bar, 4));
+    HIPCK(c, hipMemsetAsync(c->d_bar, 0, 4 * sizeof(unsigned), c->st));
+    const char* sw = getenv("PDSCHUR_SWEEP");
+    int dev = 0, coop = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+    c->coop_sweeps = coop != 0 && !(sw && strcmp(sw, "levels") == 0);
+  }
   HIPCK(c, hipStreamSynchronize(c->st));
   return PD_OK;
 }
@@ -811,6 +845,11 @@ pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
   PhaseTimer tm(c, PD_PHASE_CONDENSE);
   gather_rows3(n1, c->d_lev_nodes, f, c->n, c->d_fhat, n1, c->st);
   gather_rows3(m, c->d_region_ids, f, c->n, y2, m, c->st);
+  if (c->coop_sweeps) {
+    HIPCK(c, sweep_forward(c->sweep, c->d_fhat, c->d_v, y2, c->d_bar, c->d_err, c->st));
+    c->have_condense = true;
+    return c->check("pd_condense_rhs");
+  }
   for (int k = 0; k < c->K; ++k) {
     const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
     symv3(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_fhat + off, (int)n1, 1.0, 0.0,
@@ -836,8 +875,11 @@ pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
   if (!c->have_condense) return c->fail(PD_ERR_STATE, "pd_backsub needs a preceding pd_condense_rhs");
   const int64_t n1 = c->n1, m = c->m;
   PhaseTimer tm(c, PD_PHASE_BACKSUB);
-  if (n1 > 0) {
-    HIPCK(c, hipMemcpyAsync(c->d_xs, c->d_v, 3 * n1 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  if (n1 > 0 && c->coop_sweeps) {
+    HIPCK(c, sweep_backward(c->sweep, c->d_v, delta2, c->d_xs, c->d_tmp, c->d_bar, c->d_err, c->st));
+    scatter_add_rows3(n1, c->d_lev_nodes, c->d_xs, n1, x, c->n, c->st);
+  } else if (n1 > 0) {
+    copy_f64(3 * n1, c->d_v, c->d_xs, c->st);
     for (int k = c->K - 1; k >= 0; --k) {
       const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
       const int32_t* tp = c->d_Btptr + c->Bt_ptr_off[k];
@@ -885,11 +927,11 @@ pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, cons
   if (c->broken) return PD_ERR_HIP;
   CK(ensure_pen_cap(c, std::max<int32_t>(n_pen, 1)));
   PhaseTimer tm(c, PD_PHASE_COLLISION);
-  if (n_pen > 0) {
-    HIPCK(c, hipMemcpyAsync(c->d_pidx, idx, 8 * (size_t)n_pen * sizeof(int32_t), hipMemcpyDeviceToDevice, c->st));
-    HIPCK(c, hipMemcpyAsync(c->d_pw, w, 8 * (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-    HIPCK(c, hipMemcpyAsync(c->d_pc, cc, (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
-    HIPCK(c, hipMemcpyAsync(c->d_pt, t, 3 * (size_t)n_pen * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  if (n_pen > 0) {                    // copies by kernels (capturable like every other step)
+    copy_i32(8 * (long)n_pen, idx, c->d_pidx, c->st);
+    copy_f64(8 * (long)n_pen, w, c->d_pw, c->st);
+    copy_f64((long)n_pen, cc, c->d_pc, c->st);
+    copy_f64(3 * (long)n_pen, t, c->d_pt, c->st);
   }
   c->n_pen = n_pen;
   compact_active(n_pen, c->d_pc, c->d_pact, c->d_pnact, c->st);

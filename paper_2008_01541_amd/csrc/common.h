@@ -12,6 +12,20 @@ constexpr int NB = 64;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
+// Description of the interior levels for the cooperative sweeps; every
+// pointer is device memory (offset arrays uploaded once at build time).
+struct SweepDesc {
+  int K;
+  long n1, m, maxw;
+  const double* levmat;
+  const int32_t *Bptr, *Bcol, *Btptr, *Btcol;
+  const double *Bval, *Btval;
+  const long* lev_off;      // [K + 1]
+  const long* mat_off;      // [K]
+  const int* ldw;           // [K]
+  const long *B_ptr_off, *B_nnz_off, *Bt_ptr_off, *Bt_nnz_off;   // [K]
+};
+
 // ---- launchers (all asynchronous on `st`) --------------------------------
 
 // dense FP64
@@ -29,6 +43,8 @@ void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st);
 // Fill kernels (used instead of memset so the calls can be graph-captured).
 void zero_int(int* p, hipStream_t st);
 void zero_f64(long n, double* p, hipStream_t st);
+void copy_f64(long n, const double* src, double* dst, hipStream_t st);
+void copy_i32(long n, const int32_t* src, int32_t* dst, hipStream_t st);
 void trtri_from_factor(const double* L, int ldl, int n, const double* linv_ws, double* M,
                        double* X, int ldx, hipStream_t st);
 void lauum_full(const double* X, int ldx, int n, double* Z, int ldz, hipStream_t st);
@@ -51,6 +67,12 @@ void equilibrate_convert(const double* H, int ld, int n, double* d, float* H32, 
 void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const double* d,
                     const double* r, float* y, float* xs, double* x, int accumulate,
                     unsigned long long* tickets, int* flags, int* err, hipStream_t st);
+
+// cooperative condensation sweeps (bar: one zero-initialised counter)
+hipError_t sweep_forward(const SweepDesc& d, double* fhat, double* v, double* y2, unsigned* bar,
+                         int* err, hipStream_t st);
+hipError_t sweep_backward(const SweepDesc& d, const double* v, const double* delta2, double* xs,
+                          double* tmp, unsigned* bar, int* err, hipStream_t st);
 
 // FEM / sparse
 void tet_geometry(const double* rest, int64_t n, const int32_t* tets, int64_t T,

@@ -630,6 +630,21 @@ void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st) {
   k_rhs_unpack<<<(n + 255) / 256, 256, 0, st>>>(n, Yt, y, ldy);
 }
 
+__global__ void k_copy_f64(long n, const double* __restrict__ src, double* __restrict__ dst) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+__global__ void k_copy_i32(long n, const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = src[e];
+}
+void copy_f64(long n, const double* src, double* dst, hipStream_t st) {
+  if (n > 0) k_copy_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, src, dst);
+}
+void copy_i32(long n, const int32_t* src, int32_t* dst, hipStream_t st) {
+  if (n > 0) k_copy_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, src, dst);
+}
+
 __global__ void k_zero_int(int* p) { *p = 0; }
 void zero_int(int* p, hipStream_t st) { k_zero_int<<<1, 1, 0, st>>>(p); }
 
