@@ -594,9 +594,11 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
       __syncthreads();
       for (int e = t; e < NB * NB; e += 256) {
         const int r = e & 63, c = e >> 6;
-        if (r < mr) coherent_store(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai], buf0[c][r]);
+        // the right-hand-side row also runs over the last (ragged) column block
+        if (r < mr && c < mc) coherent_store(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai], buf0[c][r]);
         // transposed copy: U(c0 + r', r0 + c') = L(r0 + c', c0 + r') with r' = e & 63, c' = e >> 6
-        if (!rrow && c < mr) coherent_store(&A[(long)(c0 + r) + (long)(r0 + c) * lda], buf0[r][c]);
+        if (!rrow && c < mr && r < mc)
+          coherent_store(&A[(long)(c0 + r) + (long)(r0 + c) * lda], buf0[r][c]);
       }
     }
     publish_flag(&flags[i * nt + j], epoch);
