@@ -104,54 +104,189 @@ __device__ void gemm_acc(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
 // ---------------------------------------------------------------------------
 // Cholesky building blocks
 
-// Cholesky of a 64 x 64 tile held in LDS (T[c][r] = tile(r, c), lower part
-// valid, rows/cols >= mr padded with the identity) and the inverse of the
-// factor into X (X[c][r] = inverse(r, c), zero above the diagonal).  A
-// non-positive pivot stores its 1-based global index gbase + j + 1 in *info
-// (first one wins) and is replaced by 1 so that the factorization stays finite.
-__device__ void factor_tile_lds(double (*T)[LDS_LD], double (*X)[LDS_LD], double* inv_d, int mr,
-                                int gbase, int* info) {
-  const int t = threadIdx.x;
-  for (int j = 0; j < NB; ++j) {
-    __syncthreads();                       // trailing update of step j-1 complete
-    double d = T[j][j];
-    if (!(d > 0.0)) {
-      if (t == 0 && j < mr) atomicCAS(info, 0, gbase + j + 1);
-      d = 1.0;
-    }
-    const double ljj = sqrt(d);
-    const double il = 1.0 / ljj;
-    __syncthreads();
-    if (t == 0) { T[j][j] = ljj; inv_d[j] = il; }
-    if (t > j && t < NB) T[j][t] *= il;
-    __syncthreads();
-    const int r = t & 63;
-    for (int c = j + 1 + (t >> 6); c < NB; c += 4)
-      if (r >= c) T[c][r] -= T[j][r] * T[j][c];
-  }
-  __syncthreads();
-  // inverse of the lower factor, one column per lane of wave 0:
-  // x_c = 1/L_cc, x_i = -(sum_{p=c}^{i-1} L_ip x_p) / L_ii
-  if (t < NB) {
-    const int c = t;
-    for (int i = 0; i < c; ++i) X[c][i] = 0.0;
-    X[c][c] = inv_d[c];
-    for (int i = c + 1; i < NB; ++i) {
-      double s0 = 0.0, s1 = 0.0;
-      int p = c;
-      for (; p + 1 < i; p += 2) {
-        s0 += T[p][i] * X[c][p];
-        s1 += T[p + 1][i] * X[c][p + 1];
-      }
-      if (p < i) s0 += T[p][i] * X[c][p];
-      X[c][i] = -(s0 + s1) * inv_d[i];
-    }
-  }
-  __syncthreads();
+// DPP row broadcasts (row_newbcast: every lane of a row of 16 lanes reads lane
+// S of that row).  Written as volatile asm so that they stay in program order
+// and their results are consumed at once (the compiler otherwise hoists all of
+// them and spills); s_nop 1 covers the two wait states a DPP read needs after
+// a VALU write of its source.
+template <int S>
+__device__ __forceinline__ double row_bcast(double v) {
+  double o;
+  asm volatile("s_nop 1\n\tv_mov_b64_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
+               : "=v"(o)
+               : "v"(v), "i"(S));
+  return o;
+}
+// acc -= v(lane S of the row) * m
+template <int S>
+__device__ __forceinline__ void fnma_row_bcast(double& acc, double v, double m) {
+  asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(acc)
+               : "v"(v), "v"(m), "i"(S));
 }
 
-__device__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
-                                    int* info);
+// 1/sqrt(d): hardware estimate refined by two Newton steps y <- y (3 - d y^2) / 2.
+__device__ __forceinline__ double rsqrt_newton(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const double r = fma(-0.5 * d * y, y, 0.5);
+    y = fma(y, r, y);
+  }
+  return y;
+}
+
+// Right-looking elimination of one 16 x 16 block, one pivot per step C: lane
+// r (mod 16) holds row r of the block in a[]; the multipliers L(S, C) are
+// broadcast along each row of 16 lanes.
+template <int C, int S>
+__device__ __forceinline__ void chol16_update(double (&a)[16]) {
+  if constexpr (S < 16) {
+    fnma_row_bcast<S>(a[S], a[C], a[C]);
+    chol16_update<C, S + 1>(a);
+  }
+}
+template <int C>
+__device__ __forceinline__ void chol16_step(double (&a)[16], double (&il)[16], int r, int& bad) {
+  if constexpr (C < 16) {
+    double d = row_bcast<C>(a[C]);
+    const bool ok = d > 0.0;
+    bad = (!ok && bad == 0) ? C + 1 : bad;
+    d = ok ? d : 1.0;
+    const double y = rsqrt_newton(d);
+    il[C] = y;
+    a[C] = (r == C) ? d * y : ((r > C) ? a[C] * y : 0.0);
+    chol16_update<C, C + 1>(a);
+    chol16_step<C + 1>(a, il, r, bad);
+  }
+}
+// Column r of the inverse, x = L^-1 e_r, right-looking: once x[C] is final,
+// x[S] -= L(S, C) x[C] for S > C.
+template <int C, int S>
+__device__ __forceinline__ void inv16_update(const double (&a)[16], double (&x)[16]) {
+  if constexpr (S < 16) {
+    fnma_row_bcast<S>(x[S], a[C], x[C]);
+    inv16_update<C, S + 1>(a, x);
+  }
+}
+template <int C>
+__device__ __forceinline__ void inv16_step(const double (&a)[16], const double (&il)[16],
+                                           double (&x)[16]) {
+  if constexpr (C < 16) {
+    x[C] *= il[C];
+    inv16_update<C, C + 1>(a, x);
+    inv16_step<C + 1>(a, il, x);
+  }
+}
+
+// Cholesky factor and inverse of the 16 x 16 diagonal block at (b0, b0) of the
+// LDS tile T, by one wave (the four rows of 16 lanes work redundantly).  L
+// replaces the lower part of the block (zeros above), its inverse goes to the
+// same block of X (zeros above).  The first non-positive pivot j of the block
+// (inside the first mr rows) is reported in *info as gbase + b0 + j + 1 and
+// replaced by 1.
+__device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[LDS_LD], int b0,
+                                               int mr, int gbase, int* info) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  double a[16], il[16], x[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = T[b0 + c][b0 + r];
+  int bad = 0;          // first non-positive pivot of the block, 1-based; 0: none
+  chol16_step<0>(a, il, r, bad);
+  if (lane == 0 && bad > 0 && b0 + bad - 1 < mr) atomicCAS(info, 0, gbase + b0 + bad);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) x[c] = (c == r) ? 1.0 : 0.0;
+  inv16_step<0>(a, il, x);
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) T[b0 + c][b0 + r] = a[c];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) X[b0 + r][b0 + i] = x[i];
+  }
+}
+
+// C(m, n) += sum_k A(m, k) B(n, k) over one 16-deep block, m, n, k < 16, for
+// operands in LDS tiles (Ts[c][r] = tile(r, c)): A(m, k) = As[ak + k][am + m],
+// B(n, k) = Bs[bk + k][bn + n] (BT = false) or Bs[bn + n][bk + k] (BT = true).
+// Result: lane l, register q holds C(l % 16, l / 16 + 4 q).
+template <bool BT>
+__device__ inline void mma16(double4_t& acc, double (*As)[LDS_LD], int am, int ak,
+                             double (*Bs)[LDS_LD], int bn, int bk) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + (lane >> 4);
+    const double av = As[ak + k][am + (lane & 15)];
+    const double bv = BT ? Bs[bn + (lane & 15)][bk + k] : Bs[bk + k][bn + (lane & 15)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc, 0, 0, 0);
+  }
+}
+
+// Cholesky of a 64 x 64 tile held in LDS (T[c][r] = tile(r, c), lower part
+// valid, rows/cols >= mr padded with the identity) and the inverse of the
+// factor into X (X[c][r] = inverse(r, c), zero above the diagonal).  Right-
+// looking over 16-wide block columns: wave 0 factors and inverts the diagonal
+// block, the panel below becomes P Dinv^T and the trailing blocks are updated
+// on the matrix cores; the off-diagonal blocks of the inverse follow from
+// X_ij = -X_ii sum_{p=j}^{i-1} L_ip X_pj.  A non-positive pivot stores its
+// 1-based global index gbase + j + 1 in *info (first one wins) and is replaced
+// by 1 so that the factorization stays finite.  Only the lower triangle of T
+// is meaningful on return.
+__device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
+                                    int* info) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // zero the six strictly upper 16 x 16 blocks of X: X[16 jb + c][16 ib + r], ib < jb
+  for (int e = t; e < 6 * 256; e += 256) {
+    const int blk = e >> 8, r = e & 15, c = (e >> 4) & 15;
+    const int ib = blk < 3 ? 0 : (blk < 5 ? 1 : 2);
+    const int jb = blk < 3 ? blk + 1 : (blk < 5 ? blk - 1 : 3);
+    X[16 * jb + c][16 * ib + r] = 0.0;
+  }
+  if (w == 0) chol16_inverse(T, X, 0, mr, gbase, info);
+  __syncthreads();
+  for (int kb = 0; kb < 3; ++kb) {
+    const int b0 = 16 * kb;
+    // panel: block row ib = kb + 1 + w becomes P Dinv^T
+    if (kb + 1 + w <= 3) {
+      const int ib = kb + 1 + w;
+      double4_t acc = {0.0, 0.0, 0.0, 0.0};
+      mma16<false>(acc, T, 16 * ib, b0, X, b0, b0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) T[b0 + (lane >> 4) + 4 * q][16 * ib + (lane & 15)] = acc[q];
+    }
+    __syncthreads();
+    // trailing blocks (ib, jb), kb < jb <= ib <= 3; wave 0 takes the next
+    // diagonal block and goes straight on to factor it
+    const int R = 3 - kb, nblk = R * (R + 1) / 2;
+    for (int bi = (w == 0 ? 0 : w); bi < nblk; bi += (w == 0 ? nblk : 3)) {
+      int jb = kb + 1, rem = bi;
+      while (rem >= 4 - jb) { rem -= 4 - jb; ++jb; }
+      const int ib = jb + rem;
+      double4_t acc = {0.0, 0.0, 0.0, 0.0};
+      mma16<false>(acc, T, 16 * ib, b0, T, 16 * jb, b0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) T[16 * jb + (lane >> 4) + 4 * q][16 * ib + (lane & 15)] -= acc[q];
+    }
+    if (w == 0) chol16_inverse(T, X, b0 + 16, mr, gbase, info);
+    __syncthreads();
+  }
+  // off-diagonal blocks of the inverse, block row by block row
+  for (int i = 1; i < 4; ++i) {
+    if (w < i) {
+      const int j = w;
+      double4_t acc = {0.0, 0.0, 0.0, 0.0};
+      for (int p = j; p < i; ++p) mma16<true>(acc, T, 16 * i, 16 * p, X, 16 * j, 16 * p);
+      // stage Y = sum_p L_ip X_pj in the X_ij slot, then X_ij = -X_ii Y
+#pragma unroll
+      for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = acc[q];
+      double4_t acc2 = {0.0, 0.0, 0.0, 0.0};
+      mma16<true>(acc2, X, 16 * i, 16 * i, X, 16 * j, 16 * i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = -acc2[q];
+    }
+    __syncthreads();
+  }
+}
 
 // Factor diagonal tile k in place (lower) and write its inverse (64x64, lower,
 // identity-padded past the matrix edge) to linv_ws + k*NB*NB.
@@ -159,7 +294,6 @@ __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int lda, int n, i
                                                     double* linv_ws, int* info) {
   __shared__ double T[NB][LDS_LD];
   __shared__ double X[NB][LDS_LD];
-  __shared__ double inv_d[NB];
   const int t = threadIdx.x;
   const int r0 = k * NB;
   const int mr = min(NB, n - r0);
@@ -247,7 +381,6 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* A, int lda, int n, 
 // tasks with a smaller ticket, all of which belong to running workgroups, so
 // the schedule cannot deadlock; waits are bounded and raise *err instead.
 constexpr long SPIN_LIMIT_DF = 1L << 24;
-constexpr int KCD = 32;                 // K chunk of the pipelined accumulation
 
 // Cross-workgroup publication protocol.  Tiles, tile inverses and solve
 // vectors are written with agent-coherent (write-through) stores; after every
@@ -285,136 +418,6 @@ __device__ inline void publish_flag(int* f, int epoch) {
 __global__ void k_reset_counter(unsigned* ctr) {
   ctr[0] = 0u;
   ctr[1] = ctr[1] + 1u;
-}
-
-// Blocked (16 x 16) Cholesky of the LDS tile T (T[c][r] = tile(r, c), lower,
-// identity-padded past mr) and the inverse of the factor into X.
-__device__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
-                                    int* info) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  for (int kb = 0; kb < 4; ++kb) {
-    const int b0 = kb * 16;
-    if (w == 0) {                          // 16 x 16 diagonal block, lane r holds row r
-      const int r = lane & 15;
-      double a[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = T[b0 + c][b0 + r];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double d = __shfl(a[c], c, 64);
-        if (!(d > 0.0)) {
-          if (lane == 0 && b0 + c < mr) atomicCAS(info, 0, gbase + b0 + c + 1);
-          d = 1.0;
-        }
-        const double l = sqrt(d), il = 1.0 / l;
-        if (r == c) a[c] = l;
-        else if (r > c) a[c] *= il;
-#pragma unroll
-        for (int s2 = c + 1; s2 < 16; ++s2) {
-          const double xs = __shfl(a[c], s2, 64);
-          if (r >= s2) a[s2] -= a[c] * xs;
-        }
-      }
-      if (lane < 16) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-          if (c <= r) T[b0 + c][b0 + r] = a[c];
-      }
-    }
-    __syncthreads();
-    const int nrow = NB - b0 - 16;
-    if (t < nrow) {                        // panel rows below: x L_D^T = row
-      const int rr = b0 + 16 + t;
-      double x[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double sacc = T[b0 + c][rr];
-#pragma unroll
-        for (int p = 0; p < c; ++p) sacc -= x[p] * T[b0 + p][b0 + c];
-        x[c] = sacc / T[b0 + c][b0 + c];
-      }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) T[b0 + c][rr] = x[c];
-    }
-    __syncthreads();
-    if (nrow > 0) {                        // trailing update of the lower part
-      for (int e = t; e < nrow * nrow; e += 256) {
-        const int r = b0 + 16 + e % nrow, c = b0 + 16 + e / nrow;
-        if (r >= c) {
-          double acc = 0.0;
-#pragma unroll
-          for (int p = 0; p < 16; ++p) acc += T[b0 + p][r] * T[b0 + p][c];
-          T[c][r] -= acc;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // inverse: diagonal 16-blocks (wave b, lane c computes column c of block b)
-  {
-    const int b0 = w * 16, c = lane & 15;
-    double x[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double sacc = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int p = 0; p < r; ++p) sacc -= T[b0 + p][b0 + r] * x[p];
-      x[r] = (r >= c) ? sacc / T[b0 + r][b0 + r] : 0.0;
-    }
-    if (lane < 16) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) X[b0 + c][b0 + r] = x[r];
-    }
-    // zero the blocks above the diagonal
-    for (int e = lane; e < 16 * 48; e += 64) {
-      const int r = e & 15, cb = 16 + (e >> 4);      // column index 16..63
-      const int col = cb, row = b0 + r;
-      if (col >= b0 + 16) X[col][row] = 0.0;
-    }
-  }
-  __syncthreads();
-  // off-diagonal 16-blocks, block row ib: X_ib,jb = -X_ib,ib sum_pb L_ib,pb X_pb,jb
-  for (int ib = 1; ib < 4; ++ib) {
-    const int rb = 16 * ib, cnt = 16 * rb;
-    double y[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int e = t + 256 * q;
-      y[q] = 0.0;
-      if (e < cnt) {
-        const int r = e & 15, c = e >> 4;           // c in [0, rb)
-        const int p0 = (c >> 4) * 16;
-        double acc = 0.0;
-        for (int p = p0; p < rb; ++p) acc += T[p][rb + r] * X[c][p];
-        y[q] = acc;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int e = t + 256 * q;
-      if (e < cnt) X[e >> 4][rb + (e & 15)] = y[q];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int e = t + 256 * q;
-      y[q] = 0.0;
-      if (e < cnt) {
-        const int r = e & 15, c = e >> 4;
-        double acc = 0.0;
-#pragma unroll
-        for (int qq = 0; qq < 16; ++qq) acc += X[rb + qq][rb + r] * X[c][rb + qq];
-        y[q] = -acc;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int e = t + 256 * q;
-      if (e < cnt) X[e >> 4][rb + (e & 15)] = y[q];
-    }
-    __syncthreads();
-  }
 }
 
 // acc += sum_{k<j} L_ik L_jk^T, one 64-deep k-step at a time.  The two
@@ -533,13 +536,12 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     const int ldai = rrow ? NB : lda;
     const int r0 = rrow ? 0 : i * NB, c0 = j * NB;
     const int mr = rrow ? 3 : min(NB, n - r0), mc = min(NB, n - c0);
+    // the diagonal chain (diagonal and first sub-diagonal tiles) issues first
+    const bool critical = (i == j || i == j + 1) && !rrow;
+    if (critical) __builtin_amdgcn_s_setprio(2);
+    // acc <- -A_ij, read now so that the load is off the path after the last
+    // product; padding: identity on the diagonal tile, zero elsewhere
     Acc acc;
-    acc_zero(acc);
-    if (!df_accumulate(acc, buf0, buf1, Ai, ldai, r0, mr, A, lda, c0, mc, i, j, nt, flags, epoch,
-                       err, &s_ok))
-      return;
-    __syncthreads();
-    // C = A_ij - acc  ->  buf0[c][r]; padding: identity on the diagonal tile, zero elsewhere
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -547,22 +549,33 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
           const int r = acc_row(mb), c = acc_col(nb, qq);
-          double v;
-          if (r < mr && c < mc)
-            v = coherent_load(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai]) - acc.c[mb][nb][qq];
-          else v = (i == j && r == c) ? 1.0 : 0.0;
-          buf0[c][r] = v;
+          acc.c[mb][nb][qq] = (r < mr && c < mc)
+                                  ? -coherent_load(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai])
+                                  : ((i == j && r == c) ? -1.0 : 0.0);
         }
+    if (!df_accumulate(acc, buf0, buf1, Ai, ldai, r0, mr, A, lda, c0, mc, i, j, nt, flags, epoch,
+                       err, &s_ok))
+      return;
+    __syncthreads();
+    // C = A_ij - sum_k L_ik L_jk^T = -acc  ->  buf0[c][r]
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) buf0[acc_col(nb, qq)][acc_row(mb)] = -acc.c[mb][nb][qq];
     __syncthreads();
     if (i == j) {
       factor_tile_blocked(buf0, buf1, mr, r0, info);
+      // only the inverse is read inside this launch: publish it first, then
+      // write L (lower) and its transposed copy (strictly upper) for the solves
       double* Li = linv_ws + (long)j * NB * NB;
+      for (int e = t; e < NB * NB; e += 256) coherent_store(&Li[e], buf1[e >> 6][e & 63]);
+      publish_flag(&flags[i * nt + j], epoch);
       for (int e = t; e < NB * NB; e += 256) {
         const int r = e & 63, c = e >> 6;
-        coherent_store(&Li[e], buf1[c][r]);
-        // lower: L; strictly upper: L^T (transposed copy for the backward solve)
         if (r < mr && c < mr)
-          coherent_store(&A[(long)(r0 + r) + (long)(r0 + c) * lda], (r >= c) ? buf0[c][r] : buf0[r][c]);
+          A[(long)(r0 + r) + (long)(r0 + c) * lda] = (r >= c) ? buf0[c][r] : buf0[r][c];
       }
     } else {
       if (t == 0 && !df_wait(&flags[j * nt + j], epoch, err)) s_ok = 0;
@@ -596,12 +609,18 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
         const int r = e & 63, c = e >> 6;
         // the right-hand-side row also runs over the last (ragged) column block
         if (r < mr && c < mc) coherent_store(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai], buf0[c][r]);
-        // transposed copy: U(c0 + r', r0 + c') = L(r0 + c', c0 + r') with r' = e & 63, c' = e >> 6
-        if (!rrow && c < mr && r < mc)
-          coherent_store(&A[(long)(c0 + r) + (long)(r0 + c) * lda], buf0[r][c]);
+      }
+      publish_flag(&flags[i * nt + j], epoch);
+      // transposed copy, read only by the backward solve after this launch:
+      // U(c0 + r', r0 + c') = L(r0 + c', c0 + r') with r' = e & 63, c' = e >> 6
+      if (!rrow) {
+        for (int e = t; e < NB * NB; e += 256) {
+          const int r = e & 63, c = e >> 6;
+          if (c < mr && r < mc) A[(long)(c0 + r) + (long)(r0 + c) * lda] = buf0[r][c];
+        }
       }
     }
-    publish_flag(&flags[i * nt + j], epoch);
+    if (critical) __builtin_amdgcn_s_setprio(0);
   }
 }
 
