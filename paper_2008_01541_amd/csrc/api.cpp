@@ -102,9 +102,7 @@ struct pd_ctx {
   // sweeps
   double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
   bool have_condense = false;
-  SweepDesc sweep{};                  // device descriptor of the levels (cooperative sweeps)
-  unsigned* d_bar = nullptr;
-  bool coop_sweeps = true;
+  double* d_P = nullptr;              // chunk sums of one level's dense product (24 maxw)
   // penalties
   int32_t n_pen = 0, pen_cap = 0;
   int32_t* d_pidx = nullptr;
@@ -713,37 +711,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&c->d_v, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_xs, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_tmp, 3 * std::max<int64_t>(1, c->maxw)));
-  // descriptor of the levels for the single-launch sweeps
-  {
-    SweepDesc& d = c->sweep;
-    d.K = c->K;
-    d.n1 = c->n1;
-    d.m = c->m;
-    d.maxw = c->maxw;
-    d.levmat = c->d_levmat;
-    d.Bptr = c->d_Bptr; d.Bcol = c->d_Bcol; d.Bval = c->d_Bval;
-    d.Btptr = c->d_Btptr; d.Btcol = c->d_Btcol; d.Btval = c->d_Btval;
-    std::vector<long> lo(c->lev_off.begin(), c->lev_off.end());
-    std::vector<long> mo(c->lev_mat_off.begin(), c->lev_mat_off.end());
-    std::vector<int> lw(c->ldw.begin(), c->ldw.begin() + std::max(c->K, 0));
-    std::vector<long> bpo(c->B_ptr_off.begin(), c->B_ptr_off.end());
-    std::vector<long> bno(c->B_nnz_off.begin(), c->B_nnz_off.end());
-    std::vector<long> tpo(c->Bt_ptr_off.begin(), c->Bt_ptr_off.end());
-    std::vector<long> tno(c->Bt_nnz_off.begin(), c->Bt_nnz_off.end());
-    long *a, *b2, *e1, *e2, *e3, *e4;
-    int* f;
-    CK(c->upload(&a, lo)); CK(c->upload(&b2, mo)); CK(c->upload(&f, lw));
-    CK(c->upload(&e1, bpo)); CK(c->upload(&e2, bno)); CK(c->upload(&e3, tpo)); CK(c->upload(&e4, tno));
-    d.lev_off = a; d.mat_off = b2; d.ldw = f;
-    d.B_ptr_off = e1; d.B_nnz_off = e2; d.Bt_ptr_off = e3; d.Bt_nnz_off = e4;
-    CK(c->alloc(&c->d_bar, 4));
-    HIPCK(c, hipMemsetAsync(c->d_bar, 0, 4 * sizeof(unsigned), c->st));
-    const char* sw = getenv("PDSCHUR_SWEEP");
-    int dev = 0, coop = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
-    c->coop_sweeps = coop != 0 && !(sw && strcmp(sw, "levels") == 0);
-  }
+  CK(c->alloc(&c->d_P, 24 * std::max<int64_t>(1, c->maxw)));
   HIPCK(c, hipStreamSynchronize(c->st));
   return PD_OK;
 }
@@ -845,24 +813,19 @@ pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
   PhaseTimer tm(c, PD_PHASE_CONDENSE);
   gather_rows3(n1, c->d_lev_nodes, f, c->n, c->d_fhat, n1, c->st);
   gather_rows3(m, c->d_region_ids, f, c->n, y2, m, c->st);
-  if (c->coop_sweeps) {
-    HIPCK(c, sweep_forward(c->sweep, c->d_fhat, c->d_v, y2, c->d_bar, c->d_err, c->st));
-    c->have_condense = true;
-    return c->check("pd_condense_rhs");
-  }
   for (int k = 0; k < c->K; ++k) {
     const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
-    symv3(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_fhat + off, (int)n1, 1.0, 0.0,
-          c->d_v + off, (int)n1, c->st);
+    sweep_symv(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_fhat + off, n1, c->d_P,
+               c->st);
     const int32_t* bp = c->d_Bptr + c->B_ptr_off[k];
     const int32_t* bc = c->d_Bcol + c->B_nnz_off[k];
     const double* bv = c->d_Bval + c->B_nnz_off[k];
     if (k + 1 < c->K) {
       const int64_t off2 = c->lev_off[k + 1], w2 = c->lev_off[k + 2] - off2;
-      csr_spmv3(w2, bp, bc, bv, c->d_v + off, n1, -1.0, c->d_fhat + off2, n1, c->d_fhat + off2, n1,
-                c->st);
+      sweep_fwd_couple((int)w, c->d_P, c->d_v + off, n1, (int)w2, bp, bc, bv, c->d_fhat + off2, n1,
+                       c->st);
     } else {
-      csr_spmv3(m, bp, bc, bv, c->d_v + off, n1, -1.0, y2, m, y2, m, c->st);
+      sweep_fwd_couple((int)w, c->d_P, c->d_v + off, n1, (int)m, bp, bc, bv, y2, m, c->st);
     }
   }
   c->have_condense = true;
@@ -875,22 +838,28 @@ pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
   if (!c->have_condense) return c->fail(PD_ERR_STATE, "pd_backsub needs a preceding pd_condense_rhs");
   const int64_t n1 = c->n1, m = c->m;
   PhaseTimer tm(c, PD_PHASE_BACKSUB);
-  if (n1 > 0 && c->coop_sweeps) {
-    HIPCK(c, sweep_backward(c->sweep, c->d_v, delta2, c->d_xs, c->d_tmp, c->d_bar, c->d_err, c->st));
-    scatter_add_rows3(n1, c->d_lev_nodes, c->d_xs, n1, x, c->n, c->st);
-  } else if (n1 > 0) {
-    copy_f64(3 * n1, c->d_v, c->d_xs, c->st);
+  if (n1 > 0) {
+    // level k: tmp = B_k^T x_{k+1} (finishing xs_{k+1} = v_{k+1} - Z_{k+1} tmp_{k+1}), then
+    // the chunk sums of Z_k tmp; x_K = delta2
     for (int k = c->K - 1; k >= 0; --k) {
       const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
       const int32_t* tp = c->d_Btptr + c->Bt_ptr_off[k];
       const int32_t* tc = c->d_Btcol + c->Bt_nnz_off[k];
       const double* tv = c->d_Btval + c->Bt_nnz_off[k];
-      const double* xn = (k + 1 < c->K) ? c->d_xs + c->lev_off[k + 1] : delta2;
-      const int64_t ldxn = (k + 1 < c->K) ? n1 : m;
-      csr_spmv3(w, tp, tc, tv, xn, ldxn, 1.0, c->d_tmp, c->maxw, nullptr, 0, c->st);
-      symv3(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_tmp, (int)c->maxw, -1.0, 1.0,
-            c->d_xs + off, (int)n1, c->st);
+      if (k + 1 < c->K) {
+        const int64_t offn = c->lev_off[k + 1], wn = c->lev_off[k + 2] - offn;
+        sweep_bwd_couple((int)wn, c->d_P, c->d_v + offn, c->d_xs + offn, n1, nullptr, 0, (int)w,
+                         tp, tc, tv, c->d_tmp, c->maxw, c->st);
+      } else {
+        sweep_bwd_couple(0, nullptr, nullptr, nullptr, n1, delta2, m, (int)w, tp, tc, tv, c->d_tmp,
+                         c->maxw, c->st);
+      }
+      sweep_symv(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_tmp, c->maxw, c->d_P,
+                 c->st);
     }
+    const int64_t w0 = c->lev_off[1] - c->lev_off[0];
+    sweep_bwd_couple((int)w0, c->d_P, c->d_v, c->d_xs, n1, nullptr, 0, 0, nullptr, nullptr, nullptr,
+                     nullptr, 0, c->st);
     scatter_add_rows3(n1, c->d_lev_nodes, c->d_xs, n1, x, c->n, c->st);
   }
   scatter_add_rows3(m, c->d_region_ids, delta2, m, x, c->n, c->st);

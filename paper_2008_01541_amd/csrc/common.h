@@ -12,20 +12,6 @@ constexpr int NB = 64;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-// Description of the interior levels for the cooperative sweeps; every
-// pointer is device memory (offset arrays uploaded once at build time).
-struct SweepDesc {
-  int K;
-  long n1, m, maxw;
-  const double* levmat;
-  const int32_t *Bptr, *Bcol, *Btptr, *Btcol;
-  const double *Bval, *Btval;
-  const long* lev_off;      // [K + 1]
-  const long* mat_off;      // [K]
-  const int* ldw;           // [K]
-  const long *B_ptr_off, *B_nnz_off, *Bt_ptr_off, *Bt_nnz_off;   // [K]
-};
-
 // ---- launchers (all asynchronous on `st`) --------------------------------
 
 // dense FP64
@@ -68,11 +54,18 @@ void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const d
                     const double* r, float* y, float* xs, double* x, int accumulate,
                     unsigned long long* tickets, int* flags, int* err, hipStream_t st);
 
-// cooperative condensation sweeps (bar: one zero-initialised counter)
-hipError_t sweep_forward(const SweepDesc& d, double* fhat, double* v, double* y2, unsigned* bar,
-                         int* err, hipStream_t st);
-hipError_t sweep_backward(const SweepDesc& d, const double* v, const double* delta2, double* xs,
-                          double* tmp, unsigned* bar, int* err, hipStream_t st);
+// condensation sweeps, one interior level at a time.  sweep_split gives the
+// row chunks R of a level of width w; the chunk workspace P holds 3 R w doubles
+// (at most 24 w).
+void sweep_split(int64_t w, int* R, int* chunk);
+void sweep_symv(const double* Z, long ldz, int w, const double* x, long ldx, double* P,
+                hipStream_t st);
+void sweep_fwd_couple(int w, const double* P, double* v, long ldv, int rows, const int32_t* ptr,
+                      const int32_t* col, const double* val, double* xn, long ldn, hipStream_t st);
+void sweep_bwd_couple(int wn, const double* Q, const double* vn, double* xsn, long ldv,
+                      const double* delta2, long ldd, int rows, const int32_t* ptr,
+                      const int32_t* col, const double* val, double* tmp, long ldt,
+                      hipStream_t st);
 
 // FEM / sparse
 void tet_geometry(const double* rest, int64_t n, const int32_t* tets, int64_t T,

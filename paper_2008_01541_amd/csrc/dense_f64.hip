@@ -137,8 +137,10 @@ __device__ __forceinline__ double rsqrt_newton(double d) {
 }
 
 // Right-looking elimination of one 16 x 16 block, one pivot per step C: lane
-// r (mod 16) holds row r of the block in a[]; the multipliers L(S, C) are
-// broadcast along each row of 16 lanes.
+// r (mod 16) holds row r of the block in a[] and column r of the inverse in
+// x[] (initially the identity); the multipliers L(S, C) are broadcast along
+// each row of 16 lanes.  The pivot of step C + 1 is broadcast as soon as its
+// own update is done, so that its square root overlaps the rest of step C.
 template <int C, int S>
 __device__ __forceinline__ void chol16_update(double (&a)[16]) {
   if constexpr (S < 16) {
@@ -146,22 +148,6 @@ __device__ __forceinline__ void chol16_update(double (&a)[16]) {
     chol16_update<C, S + 1>(a);
   }
 }
-template <int C>
-__device__ __forceinline__ void chol16_step(double (&a)[16], double (&il)[16], int r, int& bad) {
-  if constexpr (C < 16) {
-    double d = row_bcast<C>(a[C]);
-    const bool ok = d > 0.0;
-    bad = (!ok && bad == 0) ? C + 1 : bad;
-    d = ok ? d : 1.0;
-    const double y = rsqrt_newton(d);
-    il[C] = y;
-    a[C] = (r == C) ? d * y : ((r > C) ? a[C] * y : 0.0);
-    chol16_update<C, C + 1>(a);
-    chol16_step<C + 1>(a, il, r, bad);
-  }
-}
-// Column r of the inverse, x = L^-1 e_r, right-looking: once x[C] is final,
-// x[S] -= L(S, C) x[C] for S > C.
 template <int C, int S>
 __device__ __forceinline__ void inv16_update(const double (&a)[16], double (&x)[16]) {
   if constexpr (S < 16) {
@@ -170,12 +156,25 @@ __device__ __forceinline__ void inv16_update(const double (&a)[16], double (&x)[
   }
 }
 template <int C>
-__device__ __forceinline__ void inv16_step(const double (&a)[16], const double (&il)[16],
-                                           double (&x)[16]) {
+__device__ __forceinline__ void chol16_step(double (&a)[16], double (&x)[16], double d, int r,
+                                            int& bad) {
   if constexpr (C < 16) {
-    x[C] *= il[C];
+    const bool ok = d > 0.0;
+    bad = (!ok && bad == 0) ? C + 1 : bad;
+    d = ok ? d : 1.0;
+    const double y = rsqrt_newton(d);
+    // column C of L: d y on the diagonal, a y below, 0 above (branch-free)
+    const double sc = (r > C) ? y : 0.0;
+    a[C] = fma(a[C], sc, (r == C) ? d * y : 0.0);
+    x[C] *= y;
+    double dn = 0.0;
+    if constexpr (C + 1 < 16) {
+      fnma_row_bcast<C + 1>(a[C + 1], a[C], a[C]);
+      dn = row_bcast<C + 1>(a[C + 1]);
+      chol16_update<C, C + 2>(a);
+    }
     inv16_update<C, C + 1>(a, x);
-    inv16_step<C + 1>(a, il, x);
+    chol16_step<C + 1>(a, x, dn, r, bad);
   }
 }
 
@@ -188,15 +187,15 @@ __device__ __forceinline__ void inv16_step(const double (&a)[16], const double (
 __device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[LDS_LD], int b0,
                                                int mr, int gbase, int* info) {
   const int lane = threadIdx.x & 63, r = lane & 15;
-  double a[16], il[16], x[16];
+  double a[16], x[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) a[c] = T[b0 + c][b0 + r];
+  for (int c = 0; c < 16; ++c) {
+    a[c] = T[b0 + c][b0 + r];
+    x[c] = (c == r) ? 1.0 : 0.0;
+  }
   int bad = 0;          // first non-positive pivot of the block, 1-based; 0: none
-  chol16_step<0>(a, il, r, bad);
+  chol16_step<0>(a, x, row_bcast<0>(a[0]), r, bad);
   if (lane == 0 && bad > 0 && b0 + bad - 1 < mr) atomicCAS(info, 0, gbase + b0 + bad);
-#pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = (c == r) ? 1.0 : 0.0;
-  inv16_step<0>(a, il, x);
   if (lane < 16) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) T[b0 + c][b0 + r] = a[c];

@@ -1,8 +1,15 @@
-// Condensation sweeps through the interior factor as single cooperative
-// launches.  The level chain is sequential (level k+1 needs all of level k),
-// so one persistent grid walks the levels with grid-wide barriers between the
-// dense symmetric products (Z_k times three columns) and the sparse coupling
-// updates, instead of two launches per level.
+// Condensation sweeps through the interior factor (one-way dissection in
+// breadth-first levels, Z_k = S_k^-1 dense and symmetric, B_k the sparse
+// coupling of level k to level k+1 or to the region).  The level chain is
+// sequential, so each level is two launches: a dense product with Z_k, and a
+// sparse coupling update that also finishes the dense product.
+//
+// Dense product: (Z_k x)[c] = Z_k[:, c] . x (Z_k symmetric, full storage,
+// column-major).  One wave owns 4 columns over one chunk of about 800 rows and
+// streams them with 16-byte loads, two row blocks in flight; the chunk
+// results (one partial sum per chunk, column and right-hand side) go to a
+// small workspace P[chunk][rhs][column], and the coupling launch adds them in
+// chunk order, so results do not depend on scheduling.
 #include <algorithm>
 #include "common.h"
 
@@ -10,221 +17,183 @@ namespace pdk {
 
 namespace {
 
-constexpr long SW_SPIN_LIMIT = 1L << 24;
+constexpr int SW_CW = 4;     // columns per wave
+constexpr int SW_U = 2;      // row blocks (128 rows each) in flight per wave
 
-__device__ inline double cld(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline void cst(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline double wsum(double v) {
+__device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// Grid barrier number b (0, 1, ...) on a counter that starts at zero.
-__device__ inline bool grid_barrier(unsigned* cnt, unsigned target, int* err) {
-  __builtin_amdgcn_s_waitcnt(0x0F70);     // own stores complete
-  __syncthreads();
-  __shared__ int ok;
-  if (threadIdx.x == 0) {
-    ok = 1;
-    atomicAdd(cnt, 1u);
-    long spins = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > SW_SPIN_LIMIT) {
-        atomicExch(err, 1);
-        ok = 0;
-        break;
-      }
+// P[(r * 3 + v) * w + c] = sum over rows j of chunk r of Z[j + c ldz] x[v ldx + j]
+__global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z, long ldz, int w,
+                                                    int R, int chunk, const double* __restrict__ x,
+                                                    long ldx, double* __restrict__ P) {
+  const int lane = threadIdx.x & 63;
+  const int u = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int ngroups = (w + SW_CW - 1) / SW_CW;
+  if (u >= ngroups * R) return;
+  const int g = u / R, r = u - g * R, c0 = g * SW_CW;
+  const int j0 = r * chunk, j1 = min(w, j0 + chunk);
+  double s[SW_CW][3];
+  const double* col[SW_CW];
+#pragma unroll
+  for (int cc = 0; cc < SW_CW; ++cc) {
+    s[cc][0] = s[cc][1] = s[cc][2] = 0.0;
+    col[cc] = Z + (long)min(c0 + cc, w - 1) * ldz;   // columns past w repeat the last one
+  }
+  const double* x0 = x;
+  const double* x1 = x + ldx;
+  const double* x2 = x + 2 * ldx;
+  int j = j0 + 2 * lane;                   // rows j, j + 1 (column starts are 16-byte aligned)
+  for (; j + 128 * (SW_U - 1) + 1 < j1; j += 128 * SW_U) {
+    double2 z[SW_U][SW_CW];
+    double xv[SW_U][3][2];
+#pragma unroll
+    for (int q = 0; q < SW_U; ++q) {
+      const int jj = j + 128 * q;
+#pragma unroll
+      for (int cc = 0; cc < SW_CW; ++cc) z[q][cc] = *(const double2*)(col[cc] + jj);
+      xv[q][0][0] = x0[jj]; xv[q][0][1] = x0[jj + 1];
+      xv[q][1][0] = x1[jj]; xv[q][1][1] = x1[jj + 1];
+      xv[q][2][0] = x2[jj]; xv[q][2][1] = x2[jj + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < SW_U; ++q)
+#pragma unroll
+      for (int cc = 0; cc < SW_CW; ++cc)
+#pragma unroll
+        for (int vv = 0; vv < 3; ++vv)
+          s[cc][vv] += z[q][cc].x * xv[q][vv][0] + z[q][cc].y * xv[q][vv][1];
+  }
+  for (; j < j1; j += 128) {
+    const bool two = j + 1 < j1;
+#pragma unroll
+    for (int cc = 0; cc < SW_CW; ++cc) {
+      const double za = col[cc][j], zb = two ? col[cc][j + 1] : 0.0;
+      s[cc][0] += za * x0[j] + (two ? zb * x0[j + 1] : 0.0);
+      s[cc][1] += za * x1[j] + (two ? zb * x1[j + 1] : 0.0);
+      s[cc][2] += za * x2[j] + (two ? zb * x2[j + 1] : 0.0);
     }
   }
-  __syncthreads();
-  return ok != 0;
-}
-
-// y[col] (=|+=) alpha * (Z[:, col] . v) for 8-column groups owned by this
-// workgroup (group g = blockIdx.x, blockIdx.x + gridDim.x, ...).  v is read
-// with coherent loads (it may have been written earlier in this launch).
-__device__ void level_symv(const double* __restrict__ Z, long ldz, int w, const double* v, long ldv,
-                           double alpha, bool accumulate, double* y, long ldy, double (*vs)[512]) {
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int ngroups = (w + 7) / 8;
-  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const int c0 = g * 8 + wv * 2;
-    const double* a0 = Z + (long)min(c0, w - 1) * ldz;
-    const double* a1 = Z + (long)min(c0 + 1, w - 1) * ldz;
-    double s[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    for (int j0 = 0; j0 < w; j0 += 512) {
-      const int cnt = min(512, w - j0);
-      __syncthreads();
-      for (int e = t; e < 3 * 512; e += 256) {
-        const int vv = e >> 9, jj = e & 511;
-        vs[vv][jj] = (jj < cnt) ? cld(&v[(long)vv * ldv + j0 + jj]) : 0.0;
-      }
-      __syncthreads();
-      if (cnt == 512 && ((ldz & 1) == 0)) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-          const int jj = it * 128 + 2 * lane;
-          const double2 x0 = *(const double2*)(a0 + j0 + jj);
-          const double2 x1 = *(const double2*)(a1 + j0 + jj);
+  for (int cc = 0; cc < SW_CW; ++cc)
 #pragma unroll
-          for (int vv = 0; vv < 3; ++vv) {
-            const double p = vs[vv][jj], q = vs[vv][jj + 1];
-            s[0][vv] += x0.x * p + x0.y * q;
-            s[1][vv] += x1.x * p + x1.y * q;
-          }
-        }
-      } else {
-        for (int jj = lane; jj < cnt; jj += 64) {
-          const double x0 = a0[j0 + jj], x1 = a1[j0 + jj];
+    for (int vv = 0; vv < 3; ++vv) s[cc][vv] = wave_sum(s[cc][vv]);
+  if (lane == 0) {
 #pragma unroll
-          for (int vv = 0; vv < 3; ++vv) {
-            s[0][vv] += x0 * vs[vv][jj];
-            s[1][vv] += x1 * vs[vv][jj];
-          }
-        }
-      }
-    }
+    for (int cc = 0; cc < SW_CW; ++cc)
+      if (c0 + cc < w)
 #pragma unroll
-    for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-      for (int vv = 0; vv < 3; ++vv) s[cc][vv] = wsum(s[cc][vv]);
-    if (lane == 0) {
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        const int col = c0 + cc;
-        if (col >= w) continue;
-#pragma unroll
-        for (int vv = 0; vv < 3; ++vv) {
-          double* yo = y + (long)vv * ldy + col;
-          cst(yo, accumulate ? cld(yo) + alpha * s[cc][vv] : alpha * s[cc][vv]);
-        }
-      }
-    }
+        for (int vv = 0; vv < 3; ++vv) P[(long)(r * 3 + vv) * w + c0 + cc] = s[cc][vv];
   }
 }
 
-// y[r] = base[r] + alpha * sum_e val[e] v[col[e]] for rows r of a CSR block,
-// rows spread over the whole grid; v and base read coherently.
-__device__ void level_spmv(int rows, const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                           const double* __restrict__ val, const double* v, long ldv, double alpha,
-                           double* y, long ldy, bool has_base) {
-  const long nthr = (long)gridDim.x * blockDim.x;
-  for (long r = (long)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += nthr) {
+__device__ inline double chunk_sum(const double* __restrict__ P, int R, int w, int vv, int c) {
+  double s = 0.0;
+  for (int r = 0; r < R; ++r) s += P[(long)(r * 3 + vv) * w + c];
+  return s;
+}
+
+// v[:, c] = Z_k x (chunk sums of P, c < w); xn[t] -= sum_e B(t, e) v[col(e)] (t < rows).
+__global__ void k_sweep_fwd_couple(int w, int R, const double* __restrict__ P, double* __restrict__ v,
+                                   long ldv, int rows, const int32_t* __restrict__ ptr,
+                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                   double* __restrict__ xn, long ldn) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < w) {
+#pragma unroll
+    for (int vv = 0; vv < 3; ++vv) v[(long)vv * ldv + t] = chunk_sum(P, R, w, vv, t);
+  }
+  if (t < rows) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+    for (int32_t e = ptr[t]; e < ptr[t + 1]; ++e) {
       const double a = val[e];
-      const long c = col[e];
-      s0 += a * cld(&v[c]);
-      s1 += a * cld(&v[ldv + c]);
-      s2 += a * cld(&v[2 * ldv + c]);
+      const int c = col[e];
+      s0 += a * chunk_sum(P, R, w, 0, c);
+      s1 += a * chunk_sum(P, R, w, 1, c);
+      s2 += a * chunk_sum(P, R, w, 2, c);
     }
-    const double b0 = has_base ? cld(&y[r]) : 0.0;
-    const double b1 = has_base ? cld(&y[ldy + r]) : 0.0;
-    const double b2 = has_base ? cld(&y[2 * ldy + r]) : 0.0;
-    cst(&y[r], b0 + alpha * s0);
-    cst(&y[ldy + r], b1 + alpha * s1);
-    cst(&y[2 * ldy + r], b2 + alpha * s2);
+    xn[t] -= s0;
+    xn[ldn + t] -= s1;
+    xn[2 * ldn + t] -= s2;
+  }
+}
+
+// Next level (k + 1) finished: xs_n = v_n - Z_n tmp_n from the chunk sums Q of
+// Z_n tmp_n (t < wn); then tmp[t] = sum_e B^T(t, e) x_n[col(e)] for t < rows,
+// with x_n = xs_n, or x_n = delta2 when Q is null (level k is the last one).
+__global__ void k_sweep_bwd_couple(int wn, int R, const double* __restrict__ Q,
+                                   const double* __restrict__ vn, double* __restrict__ xsn, long ldv,
+                                   const double* __restrict__ delta2, long ldd, int rows,
+                                   const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                   const double* __restrict__ val, double* __restrict__ tmp,
+                                   long ldt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (Q && t < wn) {
+#pragma unroll
+    for (int vv = 0; vv < 3; ++vv)
+      xsn[(long)vv * ldv + t] = vn[(long)vv * ldv + t] - chunk_sum(Q, R, wn, vv, t);
+  }
+  if (t < rows) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int32_t e = ptr[t]; e < ptr[t + 1]; ++e) {
+      const double a = val[e];
+      const int c = col[e];
+      if (Q) {
+        s0 += a * (vn[c] - chunk_sum(Q, R, wn, 0, c));
+        s1 += a * (vn[ldv + c] - chunk_sum(Q, R, wn, 1, c));
+        s2 += a * (vn[2 * ldv + c] - chunk_sum(Q, R, wn, 2, c));
+      } else {
+        s0 += a * delta2[c];
+        s1 += a * delta2[ldd + c];
+        s2 += a * delta2[2 * ldd + c];
+      }
+    }
+    tmp[t] = s0;
+    tmp[ldt + t] = s1;
+    tmp[2 * ldt + t] = s2;
   }
 }
 
 }  // namespace
 
-// Forward sweep: for k = 0..K-1: v_k = Z_k fhat_k;
-//   fhat_{k+1} -= B_k v_k  (k+1 < K)   or   y2 -= B_{K-1} v_{K-1}.
-// fhat and y2 hold the gathered forces on entry.
-__global__ __launch_bounds__(256) void k_sweep_forward(const SweepDesc d, double* fhat, double* v,
-                                                       double* y2, unsigned* bar, int* err) {
-  __shared__ double vs[3][512];
-  unsigned b = 0;
-  const unsigned G = gridDim.x;
-  for (int k = 0; k < d.K; ++k) {
-    const long off = d.lev_off[k];
-    const int w = (int)(d.lev_off[k + 1] - off);
-    level_symv(d.levmat + d.mat_off[k], d.ldw[k], w, fhat + off, d.n1, 1.0, false, v + off, d.n1, vs);
-    if (!grid_barrier(bar, G * ++b, err)) return;
-    const int32_t* bp = d.Bptr + d.B_ptr_off[k];
-    const int32_t* bc = d.Bcol + d.B_nnz_off[k];
-    const double* bv = d.Bval + d.B_nnz_off[k];
-    if (k + 1 < d.K) {
-      const long off2 = d.lev_off[k + 1];
-      const int w2 = (int)(d.lev_off[k + 2] - off2);
-      level_spmv(w2, bp, bc, bv, v + off, d.n1, -1.0, fhat + off2, d.n1, true);
-    } else {
-      level_spmv(d.m, bp, bc, bv, v + off, d.n1, -1.0, y2, d.m, true);
-    }
-    if (!grid_barrier(bar, G * ++b, err)) return;
-  }
+void sweep_split(int64_t w, int* R, int* chunk) {
+  const int r0 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (w + 400) / 800));
+  const int64_t ch = ((w + r0 - 1) / r0 + 127) / 128 * 128;
+  *chunk = (int)std::max<int64_t>(128, ch);
+  *R = (int)std::max<int64_t>(1, (w + *chunk - 1) / *chunk);
 }
 
-// Backward sweep: xs = v; for k = K-1..0: tmp = B_k^T x_{k+1} (x_K = delta2);
-//   xs_k -= Z_k tmp.
-__global__ __launch_bounds__(256) void k_sweep_backward(const SweepDesc d, const double* v,
-                                                        const double* delta2, double* xs,
-                                                        double* tmp, unsigned* bar, int* err) {
-  __shared__ double vs[3][512];
-  unsigned b = 0;
-  const unsigned G = gridDim.x;
-  {
-    const long nthr = (long)G * blockDim.x;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < 3L * d.n1; e += nthr)
-      cst(&xs[e], v[e]);
-  }
-  if (!grid_barrier(bar, G * ++b, err)) return;
-  for (int k = d.K - 1; k >= 0; --k) {
-    const long off = d.lev_off[k];
-    const int w = (int)(d.lev_off[k + 1] - off);
-    const int32_t* tp = d.Btptr + d.Bt_ptr_off[k];
-    const int32_t* tc = d.Btcol + d.Bt_nnz_off[k];
-    const double* tv = d.Btval + d.Bt_nnz_off[k];
-    const double* xn = (k + 1 < d.K) ? xs + d.lev_off[k + 1] : delta2;
-    const long ldxn = (k + 1 < d.K) ? d.n1 : d.m;
-    level_spmv(w, tp, tc, tv, xn, ldxn, 1.0, tmp, d.maxw, false);
-    if (!grid_barrier(bar, G * ++b, err)) return;
-    level_symv(d.levmat + d.mat_off[k], d.ldw[k], w, tmp, d.maxw, -1.0, true, xs + off, d.n1, vs);
-    if (!grid_barrier(bar, G * ++b, err)) return;
-  }
+void sweep_symv(const double* Z, long ldz, int w, const double* x, long ldx, double* P,
+                hipStream_t st) {
+  if (w <= 0) return;
+  int R, chunk;
+  sweep_split(w, &R, &chunk);
+  const int units = (w + SW_CW - 1) / SW_CW * R;
+  k_sweep_symv<<<(units + 3) / 4, 256, 0, st>>>(Z, ldz, w, R, chunk, x, ldx, P);
 }
 
-__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
-
-static int sweep_grid(const void* kernel) {
-  static int cached = 0;
-  if (cached) return cached;
-  int dev = 0, ncu = 256, per = 1;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess || per < 1) per = 1;
-  cached = ncu * std::min(per, 2);
-  return cached;
+void sweep_fwd_couple(int w, const double* P, double* v, long ldv, int rows, const int32_t* ptr,
+                      const int32_t* col, const double* val, double* xn, long ldn, hipStream_t st) {
+  const int n = std::max(w, rows);
+  if (n <= 0) return;
+  int R, chunk;
+  sweep_split(w, &R, &chunk);
+  k_sweep_fwd_couple<<<(n + 255) / 256, 256, 0, st>>>(w, R, P, v, ldv, rows, ptr, col, val, xn, ldn);
 }
 
-hipError_t sweep_forward(const SweepDesc& d, double* fhat, double* v, double* y2, unsigned* bar,
-                         int* err, hipStream_t st) {
-  if (d.K == 0) return hipSuccess;
-  k_zero_u32<<<1, 1, 0, st>>>(bar);
-  const int G = sweep_grid((const void*)k_sweep_forward);
-  SweepDesc dd = d;
-  void* args[] = {(void*)&dd, (void*)&fhat, (void*)&v, (void*)&y2, (void*)&bar, (void*)&err};
-  return hipLaunchCooperativeKernel((const void*)k_sweep_forward, dim3(G), dim3(256), args, 0, st);
-}
-
-hipError_t sweep_backward(const SweepDesc& d, const double* v, const double* delta2, double* xs,
-                          double* tmp, unsigned* bar, int* err, hipStream_t st) {
-  if (d.K == 0) return hipSuccess;
-  k_zero_u32<<<1, 1, 0, st>>>(bar);
-  const int G = sweep_grid((const void*)k_sweep_backward);
-  SweepDesc dd = d;
-  void* args[] = {(void*)&dd, (void*)&v, (void*)&delta2, (void*)&xs, (void*)&tmp, (void*)&bar,
-                  (void*)&err};
-  return hipLaunchCooperativeKernel((const void*)k_sweep_backward, dim3(G), dim3(256), args, 0, st);
+void sweep_bwd_couple(int wn, const double* Q, const double* vn, double* xsn, long ldv,
+                      const double* delta2, long ldd, int rows, const int32_t* ptr,
+                      const int32_t* col, const double* val, double* tmp, long ldt,
+                      hipStream_t st) {
+  const int n = std::max(Q ? wn : 0, rows);
+  if (n <= 0) return;
+  int R = 1, chunk;
+  if (Q) sweep_split(wn, &R, &chunk);
+  k_sweep_bwd_couple<<<(n + 255) / 256, 256, 0, st>>>(wn, R, Q, vn, xsn, ldv, delta2, ldd, rows,
+                                                      ptr, col, val, tmp, ldt);
 }
 
 }  // namespace pdk
