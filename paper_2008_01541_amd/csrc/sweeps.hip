@@ -90,70 +90,77 @@ __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z
   }
 }
 
-__device__ inline double chunk_sum(const double* __restrict__ P, int R, int w, int vv, int c) {
-  double s = 0.0;
-  for (int r = 0; r < R; ++r) s += P[(long)(r * 3 + vv) * w + c];
-  return s;
-}
-
-// v[:, c] = Z_k x (chunk sums of P, c < w); xn[t] -= sum_e B(t, e) v[col(e)] (t < rows).
+// One thread per (row, right-hand side): v[vv][c] = (Z_k x)[c] from the chunk
+// sums of P (c < w); xn[vv][t] -= sum_e B(t, e) v[vv][col(e)] (t < rows).  The
+// neighbour loop is unrolled so that its loads are in flight together.
 __global__ void k_sweep_fwd_couple(int w, int R, const double* __restrict__ P, double* __restrict__ v,
                                    long ldv, int rows, const int32_t* __restrict__ ptr,
                                    const int32_t* __restrict__ col, const double* __restrict__ val,
                                    double* __restrict__ xn, long ldn) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = max(w, rows);
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int vv = gt / n, t = gt - vv * n;
+  if (vv >= 3) return;
+  const double* Pv = P + (long)vv * w;
+  const long ldp = 3L * w;
   if (t < w) {
-#pragma unroll
-    for (int vv = 0; vv < 3; ++vv) v[(long)vv * ldv + t] = chunk_sum(P, R, w, vv, t);
+    double s = 0.0;
+    for (int r = 0; r < R; ++r) s += Pv[r * ldp + t];
+    v[(long)vv * ldv + t] = s;
   }
   if (t < rows) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t e = ptr[t]; e < ptr[t + 1]; ++e) {
-      const double a = val[e];
+    double acc = 0.0;
+    const int e1 = ptr[t + 1];
+#pragma unroll 4
+    for (int e = ptr[t]; e < e1; ++e) {
       const int c = col[e];
-      s0 += a * chunk_sum(P, R, w, 0, c);
-      s1 += a * chunk_sum(P, R, w, 1, c);
-      s2 += a * chunk_sum(P, R, w, 2, c);
+      double s = 0.0;
+      for (int r = 0; r < R; ++r) s += Pv[r * ldp + c];
+      acc += val[e] * s;
     }
-    xn[t] -= s0;
-    xn[ldn + t] -= s1;
-    xn[2 * ldn + t] -= s2;
+    xn[(long)vv * ldn + t] -= acc;
   }
 }
 
 // Next level (k + 1) finished: xs_n = v_n - Z_n tmp_n from the chunk sums Q of
 // Z_n tmp_n (t < wn); then tmp[t] = sum_e B^T(t, e) x_n[col(e)] for t < rows,
 // with x_n = xs_n, or x_n = delta2 when Q is null (level k is the last one).
+// One thread per (row, right-hand side).
 __global__ void k_sweep_bwd_couple(int wn, int R, const double* __restrict__ Q,
                                    const double* __restrict__ vn, double* __restrict__ xsn, long ldv,
                                    const double* __restrict__ delta2, long ldd, int rows,
                                    const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                    const double* __restrict__ val, double* __restrict__ tmp,
                                    long ldt) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = max(Q ? wn : 0, rows);
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+  const int vv = gt / n, t = gt - vv * n;
+  if (vv >= 3) return;
+  const long ldq = 3L * wn;
+  const double* Qv = Q ? Q + (long)vv * wn : nullptr;
+  const double* vnv = vn ? vn + (long)vv * ldv : nullptr;
   if (Q && t < wn) {
-#pragma unroll
-    for (int vv = 0; vv < 3; ++vv)
-      xsn[(long)vv * ldv + t] = vn[(long)vv * ldv + t] - chunk_sum(Q, R, wn, vv, t);
+    double s = 0.0;
+    for (int r = 0; r < R; ++r) s += Qv[r * ldq + t];
+    xsn[(long)vv * ldv + t] = vnv[t] - s;
   }
   if (t < rows) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int32_t e = ptr[t]; e < ptr[t + 1]; ++e) {
-      const double a = val[e];
-      const int c = col[e];
-      if (Q) {
-        s0 += a * (vn[c] - chunk_sum(Q, R, wn, 0, c));
-        s1 += a * (vn[ldv + c] - chunk_sum(Q, R, wn, 1, c));
-        s2 += a * (vn[2 * ldv + c] - chunk_sum(Q, R, wn, 2, c));
-      } else {
-        s0 += a * delta2[c];
-        s1 += a * delta2[ldd + c];
-        s2 += a * delta2[2 * ldd + c];
+    double acc = 0.0;
+    const int e1 = ptr[t + 1];
+    if (Q) {
+#pragma unroll 4
+      for (int e = ptr[t]; e < e1; ++e) {
+        const int c = col[e];
+        double s = 0.0;
+        for (int r = 0; r < R; ++r) s += Qv[r * ldq + c];
+        acc += val[e] * (vnv[c] - s);
       }
+    } else {
+      const double* d2 = delta2 + (long)vv * ldd;
+#pragma unroll 4
+      for (int e = ptr[t]; e < e1; ++e) acc += val[e] * d2[col[e]];
     }
-    tmp[t] = s0;
-    tmp[ldt + t] = s1;
-    tmp[2 * ldt + t] = s2;
+    tmp[(long)vv * ldt + t] = acc;
   }
 }
 
@@ -181,7 +188,8 @@ void sweep_fwd_couple(int w, const double* P, double* v, long ldv, int rows, con
   if (n <= 0) return;
   int R, chunk;
   sweep_split(w, &R, &chunk);
-  k_sweep_fwd_couple<<<(n + 255) / 256, 256, 0, st>>>(w, R, P, v, ldv, rows, ptr, col, val, xn, ldn);
+  k_sweep_fwd_couple<<<(3 * n + 255) / 256, 256, 0, st>>>(w, R, P, v, ldv, rows, ptr, col, val, xn,
+                                                         ldn);
 }
 
 void sweep_bwd_couple(int wn, const double* Q, const double* vn, double* xsn, long ldv,
@@ -192,8 +200,8 @@ void sweep_bwd_couple(int wn, const double* Q, const double* vn, double* xsn, lo
   if (n <= 0) return;
   int R = 1, chunk;
   if (Q) sweep_split(wn, &R, &chunk);
-  k_sweep_bwd_couple<<<(n + 255) / 256, 256, 0, st>>>(wn, R, Q, vn, xsn, ldv, delta2, ldd, rows,
-                                                      ptr, col, val, tmp, ldt);
+  k_sweep_bwd_couple<<<(3 * n + 255) / 256, 256, 0, st>>>(wn, R, Q, vn, xsn, ldv, delta2, ldd,
+                                                          rows, ptr, col, val, tmp, ldt);
 }
 
 }  // namespace pdk
