@@ -74,6 +74,7 @@ struct pd_ctx {
   double* d_S = nullptr;
   double* d_H = nullptr;
   double* d_linv = nullptr;
+  double* d_sbuf = nullptr;           // partial sums of the first sub-diagonal tiles (factor)
   double* d_y = nullptr;
   double* d_Yt = nullptr;             // 64 x m right-hand-side tile row of the fused solve
   double* d_res = nullptr;
@@ -240,8 +241,8 @@ void free_now(pd_ctx* c, void* p) {
 // transpose of the factor in the upper triangle.
 void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr) {
   if (c->chol_dataflow) {
-    potrf_dataflow(A, lda, n, c->d_linv, c->d_tflags, c->d_tticket, c->d_info, c->d_err, c->n_wg,
-                   Yt, c->st);
+    potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
+                   c->n_wg, Yt, c->st);
   } else {
     potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
   }
@@ -590,6 +591,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   c->ntm = (int)((m + NB - 1) / NB);
   const int64_t ntmax = (std::max<int64_t>(c->maxw, m) + NB - 1) / NB;
   CK(c->alloc(&c->d_linv, ntmax * NB * NB));
+  CK(c->alloc(&c->d_sbuf, ntmax * NB * NB));
   CK(c->alloc(&c->d_info, 1));
   CK(c->alloc(&c->d_err, 1));
   CK(c->alloc(&c->d_ticket, 4));
@@ -599,7 +601,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   HIPCK(c, hipMemsetAsync(c->d_ticket, 0, 4 * sizeof(unsigned long long), c->st));
   HIPCK(c, hipMemsetAsync(c->d_flags, 0, 4 * (int64_t)c->ntm * sizeof(int), c->st));
   {
-    const int64_t nt2 = ntmax * (ntmax + 1);
+    const int64_t nt2 = ntmax * (ntmax + 2);
     CK(c->alloc(&c->d_tflags, nt2));
     CK(c->alloc(&c->d_tticket, 4));
     HIPCK(c, hipMemsetAsync(c->d_tflags, 0, nt2 * sizeof(int), c->st));

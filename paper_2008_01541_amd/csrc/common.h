@@ -17,13 +17,14 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // dense FP64
 void copy_lower_tiles(const double* S, int lds, double* H, int ldh, int n, hipStream_t st);
 void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStream_t st);
-// Single-launch dataflow Cholesky; flags: nt*nt ints and ticket[2] (task
-// counter, launch epoch), all zero-initialised once; each call advances the
-// epoch on the device (safe under graph replay).
+// Single-launch dataflow Cholesky; flags: (nt + 2) * nt ints and ticket[2]
+// (task counter, launch epoch), all zero-initialised once; each call advances
+// the epoch on the device (safe under graph replay).  sbuf: nt * NB * NB
+// doubles of workspace (partial sums of the first sub-diagonal tiles).
 // With Yt (64 x n, rows 0..2 = g^T) the forward substitution L^-1 g is fused
-// in (result in the same rows); flags then need (nt + 1) * nt ints.
-void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
-                    int* info, int* err, int n_wg, double* Yt, hipStream_t st);
+// in (result in the same rows).
+void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
+                    unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st);
 void rhs_pack(int n, const double* g, int ldg, double* Yt, hipStream_t st);
 void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st);
 // Fill kernels (used instead of memset so the calls can be graph-captured).

@@ -419,7 +419,7 @@ __global__ void k_reset_counter(unsigned* ctr) {
   ctr[1] = ctr[1] + 1u;
 }
 
-// acc += sum_{k<j} L_ik L_jk^T, one 64-deep k-step at a time.  The two
+// acc += sum_{k<kend} L_ik L_jk^T, one 64-deep k-step at a time.  The two
 // operand tiles of step k+1 are loaded into registers while the products of
 // step k run from LDS, and the ready flags of step k+2 are read while step
 // k+1 is loaded, so neither the flag round trip nor the operand latency sits
@@ -427,12 +427,12 @@ __global__ void k_reset_counter(unsigned* ctr) {
 __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
                               const double* __restrict__ Ar, int ldar, int r0, int mr,
                               const double* __restrict__ A, int lda, int c0,
-                              int mc, int i, int j, int nt, const int* flags, int epoch, int* err,
-                              int* s_ok) {
+                              int mc, int i, int j, int kend, int nt, const int* flags, int epoch,
+                              int* err, int* s_ok) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int r = t & 63, kq = t >> 6;
-  if (j == 0) return true;
+  if (kend == 0) return true;
   double ra[16], rb[16];
   auto load_tile = [&](int k) {
 #pragma unroll
@@ -454,18 +454,18 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
   __syncthreads();
   if (!*s_ok) return false;
   load_tile(0);
-  if (t == 0 && j > 1) {
+  if (t == 0 && kend > 1) {
     fi = __hip_atomic_load(&flags[i * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     fj = __hip_atomic_load(&flags[j * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  for (int k = 0; k < j; ++k) {
+  for (int k = 0; k < kend; ++k) {
     __syncthreads();                         // previous step's products are done with LDS
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       As[kq + 4 * q][r] = ra[q];
       Bs[kq + 4 * q][r] = rb[q];
     }
-    const bool nxt = k + 1 < j;
+    const bool nxt = k + 1 < kend;
     if (t == 0 && nxt && (fi != epoch || fj != epoch)) {
       if (!df_wait(&flags[i * nt + k + 1], epoch, err) ||
           !df_wait(&flags[j * nt + k + 1], epoch, err))
@@ -475,7 +475,7 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
     if (!*s_ok) return false;
     if (nxt) {
       load_tile(k + 1);
-      if (t == 0 && k + 2 < j) {
+      if (t == 0 && k + 2 < kend) {
         fi = __hip_atomic_load(&flags[i * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         fj = __hip_atomic_load(&flags[j * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -496,24 +496,75 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
   return true;
 }
 
-// With Yt != NULL the three right-hand sides ride along as an extra tile row
-// (Yt: 64 x n, column-major, rows 0..2 = g^T on entry): its tasks compute
-// Y_j = (G_j - sum_{k<j} Y_k L_jk^T) Linv_jj^T, i.e. the forward substitution
-// y = L^-1 g, on the same schedule as the factor.
+// acc(r, c) += sum_kk As[kk][r] Bs[kk][c] over one 64-deep block in LDS (this
+// wave's 32 x 32 share, the layout of Acc).
+__device__ inline void lds_product(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll 4
+  for (int ks = 0; ks < NB / 4; ++ks) {
+    const int k = ks * 4 + (lane >> 4);
+    const double a0 = As[k][wr * 32 + (lane & 15)];
+    const double a1 = As[k][wr * 32 + 16 + (lane & 15)];
+    const double b0 = Bs[k][wc * 32 + (lane & 15)];
+    const double b1 = Bs[k][wc * 32 + 16 + (lane & 15)];
+    acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
+    acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
+    acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
+    acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
+  }
+}
+
+// T[c][r] = sign * acc(r, c)
+__device__ inline void acc_to_lds(const Acc& acc, double (*T)[LDS_LD], double sign) {
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) T[acc_col(nb, qq)][acc_row(mb)] = sign * acc.c[mb][nb][qq];
+}
+
+// T[e >> 6][e & 63] = src[e] for the 4096 elements of a 64 x 64 tile, with
+// all sixteen loads of a thread in flight before the LDS writes.
+__device__ inline void stage_tile(double (*T)[LDS_LD], const double* __restrict__ src) {
+  const int t = threadIdx.x;
+  double v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = src[t + 256 * q];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) T[(t >> 6) + 4 * q][t & 63] = v[q];
+}
+
+// Task kinds in column j (tickets in this order):
+//  * diagonal (j, j): accumulates k < j - 1, then finishes the sub-diagonal
+//    tile itself, L_{j,j-1} = (A_{j,j-1} - S_j) Linv_{j-1}^T with the partial
+//    sum S_j of the task below, adds its last product and factors the tile.
+//    The first sub-diagonal tile thus never takes a hand-off of its own on the
+//    chain diag(j-1) -> diag(j), the critical path of the factorization.
+//  * sub-diagonal (j + 1, j): S_{j+1} = sum_{k<j} L_{j+1,k} L_{j,k}^T into
+//    the workspace sbuf (published with its own flag, no Linv wait).
+//  * (i, j), i >= j + 2: accumulates k < j, waits for Linv_jj, forms
+//    L_ij = (A_ij - acc) Linv_jj^T.
+//  * with Yt != NULL the three right-hand sides ride along as an extra tile
+//    row (Yt: 64 x n, column-major, rows 0..2 = g^T on entry): its tasks
+//    compute Y_j = (G_j - sum_{k<j} Y_k L_jk^T) Linv_jj^T, i.e. the forward
+//    substitution y = L^-1 g, on the same schedule.
+// Flags: nt x nt for the tiles, nt more for the right-hand-side row, nt more
+// for the partial sums.
 __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, int n, int nt,
-                                                           double* linv_ws, int* flags,
-                                                           unsigned* ticket, int* info, int* err,
-                                                           double* Yt) {
+                                                           double* linv_ws, double* sbuf,
+                                                           int* flags, unsigned* ticket, int* info,
+                                                           int* err, double* Yt) {
   const int epoch = (int)ticket[1];
   const int rhs = Yt != nullptr ? 1 : 0;
+  int* sflags = flags + (nt + 1) * nt;
   // two 64 x 68 double tiles (69,632 bytes): operands of the accumulation,
   // then the tile and its inverse / Linv during the finishing step
   __shared__ double buf0[NB][LDS_LD];
   __shared__ double buf1[NB][LDS_LD];
   __shared__ int s_task, s_ok;
   const int t = threadIdx.x;
-  const int lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
   const int ntask = nt * (nt + 1) / 2 + rhs * nt;
   for (;;) {
     __syncthreads();
@@ -531,15 +582,16 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     }
     const int i = j + (q - start);         // i == nt: the right-hand-side row
     const bool rrow = (i == nt);
+    const bool diag = (i == j), sub = !rrow && i == j + 1;
     double* Ai = rrow ? Yt : A;
     const int ldai = rrow ? NB : lda;
     const int r0 = rrow ? 0 : i * NB, c0 = j * NB;
     const int mr = rrow ? 3 : min(NB, n - r0), mc = min(NB, n - c0);
-    // the diagonal chain (diagonal and first sub-diagonal tiles) issues first
-    const bool critical = (i == j || i == j + 1) && !rrow;
+    // the diagonal chain issues first
+    const bool critical = diag || sub;
     if (critical) __builtin_amdgcn_s_setprio(2);
-    // acc <- -A_ij, read now so that the load is off the path after the last
-    // product; padding: identity on the diagonal tile, zero elsewhere
+    // acc <- -A_ij (read now so that the load is off the path after the last
+    // product; padding: identity on the diagonal tile, zero elsewhere), or 0
     Acc acc;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -548,23 +600,79 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
           const int r = acc_row(mb), c = acc_col(nb, qq);
-          acc.c[mb][nb][qq] = (r < mr && c < mc)
-                                  ? -coherent_load(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai])
-                                  : ((i == j && r == c) ? -1.0 : 0.0);
+          acc.c[mb][nb][qq] = sub ? 0.0
+                            : (r < mr && c < mc)
+                                ? -coherent_load(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai])
+                                : ((diag && r == c) ? -1.0 : 0.0);
         }
-    if (!df_accumulate(acc, buf0, buf1, Ai, ldai, r0, mr, A, lda, c0, mc, i, j, nt, flags, epoch,
-                       err, &s_ok))
+    const int kend = diag ? max(j - 1, 0) : j;
+    if (!df_accumulate(acc, buf0, buf1, Ai, ldai, r0, mr, A, lda, c0, mc, i, j, kend, nt, flags,
+                       epoch, err, &s_ok))
       return;
+    if (sub) {
+      double* Sb = sbuf + (long)i * NB * NB;
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq)
+            coherent_store(&Sb[acc_row(mb) + NB * acc_col(nb, qq)], acc.c[mb][nb][qq]);
+      publish_flag(&sflags[i], epoch);
+      __builtin_amdgcn_s_setprio(0);
+      continue;
+    }
+    if (diag && j > 0) {
+      // tile (j, j - 1): rows of block j (mr of them), 64 columns
+      const int cs = (j - 1) * NB;
+      __syncthreads();                             // last products done with buf0
+      {
+        const int r = t & 63;
+        double v[16];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq)
+          v[qq] = (r < mr) ? coherent_load(&A[(long)(r0 + r) + (long)(cs + (t >> 6) + 4 * qq) * lda])
+                           : 0.0;
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][r] = v[qq];
+      }
+      if (t == 0 && (!df_wait(&sflags[j], epoch, err) ||
+                     !df_wait(&flags[(j - 1) * nt + (j - 1)], epoch, err)))
+        s_ok = 0;
+      __syncthreads();
+      if (!s_ok) return;
+      stage_tile(buf1, linv_ws + (long)(j - 1) * NB * NB);   // buf1[kk][c] = Linv(c, kk)
+      {
+        const double* Sb = sbuf + (long)j * NB * NB;
+        double v[16];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) v[qq] = Sb[t + 256 * qq];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][t & 63] -= v[qq];   // S(r, c)
+      }
+      __syncthreads();
+      Acc l;
+      acc_zero(l);
+      lds_product(l, buf0, buf1);                  // L = S Linv^T
+      __syncthreads();
+      acc_to_lds(l, buf0, 1.0);
+      __syncthreads();
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (r < mr) coherent_store(&A[(long)(r0 + r) + (long)(cs + c) * lda], buf0[c][r]);
+      }
+      lds_product(acc, buf0, buf0);                // acc += L L^T, while the stores drain
+      publish_flag(&flags[j * nt + (j - 1)], epoch);
+      // transposed copy: U(cs + r', r0 + c') = L(r0 + c', cs + r')
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (c < mr) A[(long)(cs + r) + (long)(r0 + c) * lda] = buf0[r][c];
+      }
+    }
     __syncthreads();
-    // C = A_ij - sum_k L_ik L_jk^T = -acc  ->  buf0[c][r]
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq) buf0[acc_col(nb, qq)][acc_row(mb)] = -acc.c[mb][nb][qq];
+    acc_to_lds(acc, buf0, -1.0);                   // C = A_ij - sum_k L_ik L_jk^T
     __syncthreads();
-    if (i == j) {
+    if (diag) {
       factor_tile_blocked(buf0, buf1, mr, r0, info);
       // only the inverse is read inside this launch: publish it first, then
       // write L (lower) and its transposed copy (strictly upper) for the solves
@@ -580,29 +688,12 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
       if (t == 0 && !df_wait(&flags[j * nt + j], epoch, err)) s_ok = 0;
       __syncthreads();
       if (!s_ok) return;
-      const double* Li = linv_ws + (long)j * NB * NB;
-      for (int e = t; e < NB * NB; e += 256) buf1[e >> 6][e & 63] = Li[e];   // buf1[kk][c] = Linv(c, kk)
+      stage_tile(buf1, linv_ws + (long)j * NB * NB);   // buf1[kk][c] = Linv(c, kk)
       __syncthreads();
       acc_zero(acc);
-#pragma unroll 4
-      for (int ks = 0; ks < NB / 4; ++ks) {
-        const int k = ks * 4 + (lane >> 4);
-        const double a0 = buf0[k][wr * 32 + (lane & 15)];
-        const double a1 = buf0[k][wr * 32 + 16 + (lane & 15)];
-        const double b0 = buf1[k][wc * 32 + (lane & 15)];
-        const double b1 = buf1[k][wc * 32 + 16 + (lane & 15)];
-        acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
-        acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
-        acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
-        acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
-      }
+      lds_product(acc, buf0, buf1);
       __syncthreads();
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-          for (int qq = 0; qq < 4; ++qq) buf0[acc_col(nb, qq)][acc_row(mb)] = acc.c[mb][nb][qq];
+      acc_to_lds(acc, buf0, 1.0);
       __syncthreads();
       for (int e = t; e < NB * NB; e += 256) {
         const int r = e & 63, c = e >> 6;
@@ -623,13 +714,13 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
   }
 }
 
-void potrf_dataflow(double* A, int lda, int n, double* linv_ws, int* flags, unsigned* ticket,
-                    int* info, int* err, int n_wg, double* Yt, hipStream_t st) {
+void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
+                    unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = nt * (nt + 1) / 2 + (Yt ? nt : 0);
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
-  k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags, ticket,
-                                                          info, err, Yt);
+  k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, sbuf, flags,
+                                                          ticket, info, err, Yt);
 }
 
 // Yt[v + r * 64] = g[v * ldg + r] (v < 3) and back.

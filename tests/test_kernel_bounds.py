@@ -1,5 +1,6 @@
 """Host-side model of the index ranges the dataflow factorization kernel
-touches (task mapping, ragged edge tiles, the fused right-hand-side row):
+touches (task mapping, ragged edge tiles, the fused right-hand-side row, the
+sub-diagonal tiles finished by the diagonal tasks and their partial sums):
 every load and store must stay inside the buffers the library allocates."""
 import numpy as np
 import pytest
@@ -32,7 +33,8 @@ def test_dataflow_indices_in_bounds(n, rhs):
     assert [task_of_ticket(q, nt, rhs) for q in range(ntask)] == dataflow_tasks(nt, rhs)
     a_size = lda * n
     yt_size = NB * n
-    flags_size = (nt + 1) * nt
+    flags_size = (nt + 2) * nt
+    sbuf_size = nt * NB * NB
     r = np.arange(NB)[:, None]
     c = np.arange(NB)[None, :]
     for (i, j) in dataflow_tasks(nt, rhs):
@@ -44,6 +46,23 @@ def test_dataflow_indices_in_bounds(n, rhs):
         ldai = NB if rrow else lda
         size_i = yt_size if rrow else a_size
         assert i * nt + j < flags_size
+        sub = (not rrow) and i == j + 1
+        if sub:
+            # partial sum of the sub-diagonal tile: sbuf slot i, flag after the tile flags
+            assert (nt + 1) * nt + i < flags_size
+            assert i * NB * NB + (NB - 1) + (NB - 1) * NB < sbuf_size
+        if i == j and j > 0:
+            # the diagonal task finishes tile (j, j - 1): rows < mr, all 64 columns,
+            # reads sbuf slot j, Linv of tile j - 1, and writes the transposed copy
+            cs = (j - 1) * NB
+            assert n - cs >= NB                       # column block j - 1 is never ragged
+            idx = (r0 + r) + (cs + c) * lda
+            assert idx[np.broadcast_to(r < mr, idx.shape)].max() < a_size
+            idxu = (cs + r) + (r0 + c) * lda          # U(cs + r', r0 + c'), c' < mr
+            assert idxu[np.broadcast_to(c < mr, idxu.shape)].max() < a_size
+            assert (nt + 1) * nt + j < flags_size
+            assert j * NB * NB + NB * NB - 1 < sbuf_size
+            assert (j - 1) * nt + (j - 1) < flags_size
         # C build / result store of the tile (bounded by mr, mc)
         sel = (r < mr) & (c < mc)
         idx = (r0 + r) + (c0 + c) * ldai
@@ -53,8 +72,10 @@ def test_dataflow_indices_in_bounds(n, rhs):
             idxu = (c0 + c.T) + (r0 + r.T) * lda      # U(c0 + r', r0 + c')
             selu = (r.T < mr) & (c.T < mc)
             assert idxu[selu].max() < a_size
-        # operand loads of the accumulation: rows < mr of Ai, rows < mc of A, k < j*NB
-        if j > 0:
-            kmax = j * NB - 1
+        # operand loads of the accumulation: rows < mr of Ai, rows < mc of A,
+        # k < kend*NB (the diagonal task stops one step early)
+        kend = max(j - 1, 0) if i == j else j
+        if kend > 0:
+            kmax = kend * NB - 1
             assert (r0 + mr - 1) + kmax * ldai < size_i
             assert (c0 + mc - 1) + kmax * lda < a_size
