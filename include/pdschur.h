@@ -169,6 +169,20 @@ pd_status pd_assemble_rhs(pd_ctx *ctx, const double *ft, const double *f_beta,
 pd_status pd_global_solve(pd_ctx *ctx, const double *g, double *u, pd_precision prec,
                           pd_solve_info *info);
 
+/* FP64 factorization of H = S + W^T C W ahead of the solve (Alg. 1 step 4.3,
+ * Sec. 4.4 Step 2), for callers that overlap it with other work: a following
+ * pd_global_solve(PD_FP64) then only runs the triangular solves (it would
+ * otherwise fuse the forward substitution into the factorization).  H only
+ * depends on the penalty set and S, not on the right-hand side, so the
+ * factorization may run on a second stream while pd_backsub, the full local
+ * step and pd_condense_rhs of the next iteration run on the first (see
+ * pd_use_stream).  n_workgroups > 0 caps the persistent workgroups of the
+ * factorization (default 2 per compute unit; fewer leave room for kernels of
+ * the other stream); <= 0 keeps the default.  A no-op when the factor is
+ * current.  Non-positive pivots are reported by a later pd_global_solve
+ * with info. */
+pd_status pd_factor(pd_ctx *ctx, int32_t n_workgroups);
+
 /* Inner update (Alg. 1 steps 4.6-4.7): x2 += u2, delta2 += u2 and
  * ft -= Sigma_alpha u2 with Sigma_alpha = S - A22^(beta).  All dev [3][m]. */
 pd_status pd_inner_update(pd_ctx *ctx, const double *u2, double *x2, double *delta2,
@@ -222,6 +236,16 @@ pd_status pd_mlp_destroy(pd_mlp *mlp);
  * stream, so a sequence of them can be captured into a HIP graph and
  * replayed; the dataflow kernels take their epochs from device memory. */
 pd_status pd_set_stream(pd_ctx *ctx, void *hip_stream);
+
+/* Moves the context to another HIP stream without synchronizing: later calls
+ * enqueue on hip_stream.  The caller orders work across streams (HIP events)
+ * and keeps calls that share context state apart: the factorization side
+ * (pd_detect_*, pd_collision_update, pd_local_step_region, pd_factor) and the
+ * sweep side (pd_backsub, pd_local_step_full, pd_condense_rhs, pd_region_gather)
+ * use disjoint context buffers and may run concurrently; pd_assemble_rhs,
+ * pd_global_solve and pd_inner_update read the results of both and must be
+ * ordered after them. */
+pd_status pd_use_stream(pd_ctx *ctx, void *hip_stream);
 
 /* Phases timed by pd_get_timings. */
 typedef enum {

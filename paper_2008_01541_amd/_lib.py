@@ -59,6 +59,8 @@ _SIGS = {
     "pd_warmstart_input": [_P, _P, _P, C.c_float, C.c_int32, _P, _P, _P],
     "pd_region_add_f32": [_P, _P, C.c_double, _P],
     "pd_set_stream": [_P, _P],
+    "pd_use_stream": [_P, _P],
+    "pd_factor": [_P, C.c_int32],
     "pd_set_timing": [_P, C.c_int],
     "pd_get_timings": [_P, _P, _P],
     "pd_destroy": [_P],
@@ -241,6 +243,10 @@ class PDContext:
         self._chk(st)
         return None
 
+    def factor(self, n_workgroups=0):
+        """FP64 factorization of H ahead of global_solve (pd_factor)."""
+        self._chk(self._lib.pd_factor(self._ctx, int(n_workgroups)))
+
     def inner_update(self, u2, x2, delta2, ft):
         import torch
         self._chk(self._lib.pd_inner_update(
@@ -274,6 +280,11 @@ class PDContext:
 
     def set_stream(self, stream):
         self._chk(self._lib.pd_set_stream(self._ctx, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+    def use_stream(self, stream):
+        """Enqueue later calls on stream without synchronizing (pd_use_stream)."""
+        self._chk(self._lib.pd_use_stream(self._ctx, C.c_void_p(stream.cuda_stream)))
         self.stream = stream
 
     def set_timing(self, on=True):

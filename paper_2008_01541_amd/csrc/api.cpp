@@ -56,7 +56,8 @@ struct pd_ctx {
   int32_t* d_tets_beta = nullptr;    // [4][nbeta] region-local ids
   double* d_Bm_beta = nullptr;
   double* d_vol_beta = nullptr;
-  double* d_fe = nullptr;            // [12][max(nalpha, nbeta)]
+  double* d_fe = nullptr;            // [12][nalpha]: element forces of the full local step
+  double* d_fe_b = nullptr;          // [12][nbeta]: element forces of the region local step
   int32_t *d_inc_a_ptr = nullptr, *d_inc_a = nullptr;
   int32_t *d_inc_b_ptr = nullptr, *d_inc_b = nullptr;
   int32_t* d_region_ids = nullptr;
@@ -239,10 +240,10 @@ void free_now(pd_ctx* c, void* p) {
 // In-place lower Cholesky of the n x n matrix A (leading dimension lda, a
 // multiple of 16 so tiles start on 128-byte lines); tile inverses to d_linv,
 // transpose of the factor in the upper triangle.
-void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr) {
+void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr, int n_wg = 0) {
   if (c->chol_dataflow) {
     potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
-                   c->n_wg, Yt, c->st);
+                   n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st);
   } else {
     potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
   }
@@ -688,7 +689,8 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     CK(c->upload(&c->d_inc_b_ptr, ptr));
     CK(c->upload(&c->d_inc_b, ent));
     CK(c->upload(&c->d_region_ids, c->region_ids));
-    CK(c->alloc(&c->d_fe, 12 * std::max<int64_t>(1, std::max(c->nalpha, c->nbeta))));
+    CK(c->alloc(&c->d_fe, 12 * std::max<int64_t>(1, c->nalpha)));
+    CK(c->alloc(&c->d_fe_b, 12 * std::max<int64_t>(1, c->nbeta)));
     HIPCK(c, hipStreamSynchronize(c->st));
     free_now(c, d_tbg);
   }
@@ -923,8 +925,9 @@ pd_status pd_local_step_region(pd_ctx* c, const double* x2, void* R_beta, double
   }
   PhaseTimer tm(c, PD_PHASE_LOCAL_REGION);
   local_step(c->nbeta, c->d_tets_beta, c->nbeta, c->d_Bm_beta, c->d_vol_beta, c->nbeta, x2, c->m,
-             c->mu, c->d_fe, R_beta, rot_fp32 ? 1 : 0, c->st);
-  node_gather3(c->m, c->d_inc_b_ptr, c->d_inc_b, c->d_fe, c->nbeta, nullptr, f_beta, c->m, 0, c->st);
+             c->mu, c->d_fe_b, R_beta, rot_fp32 ? 1 : 0, c->st);
+  node_gather3(c->m, c->d_inc_b_ptr, c->d_inc_b, c->d_fe_b, c->nbeta, nullptr, f_beta, c->m, 0,
+               c->st);
   return c->check("pd_local_step_region");
 }
 
@@ -1078,6 +1081,21 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
   return PD_OK;
 }
 
+pd_status pd_factor(pd_ctx* c, int32_t n_workgroups) {
+  if (bad_ctx(c)) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  if (!c->stale) return PD_OK;
+  build_H(c);
+  zero_int(c->d_info, c->st);
+  {
+    PhaseTimer tm(c, PD_PHASE_FACTOR);
+    cholesky(c, c->d_H, c->ldH, (int)c->m, nullptr, n_workgroups);
+  }
+  c->stale = false;
+  c->lp_stale = true;             // d_H was rebuilt
+  return c->check("pd_factor");
+}
+
 pd_status pd_inner_update(pd_ctx* c, const double* u2, double* x2, double* delta2, double* ft) {
   if (bad_ctx(c) || !u2 || !x2 || !delta2 || !ft) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
@@ -1125,6 +1143,13 @@ pd_status pd_set_stream(pd_ctx* c, void* hip_stream) {
   return PD_OK;
 }
 
+pd_status pd_use_stream(pd_ctx* c, void* hip_stream) {
+  if (bad_ctx(c)) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  c->st = (hipStream_t)hip_stream;
+  return PD_OK;
+}
+
 pd_status pd_set_timing(pd_ctx* c, int on) {
   if (bad_ctx(c)) return PD_ERR_INVALID;
   c->timing = on != 0;
@@ -1140,6 +1165,8 @@ pd_status pd_get_timings(pd_ctx* c, double* ms, int64_t* counts) {
   }
   for (auto& pr : c->ev_pairs) {
     float t = 0.f;
+    // the pair may have been recorded on another stream (pd_use_stream)
+    HIPCK(c, hipEventSynchronize(c->ev_pool[pr.second.second]));
     HIPCK(c, hipEventElapsedTime(&t, c->ev_pool[pr.second.first], c->ev_pool[pr.second.second]));
     ms[pr.first] += t;
     if (counts) counts[pr.first] += 1;

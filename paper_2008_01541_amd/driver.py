@@ -1,8 +1,10 @@
-"""Algorithm 1 of the paper driven through the C ABI, on one HIP stream.
+"""Algorithm 1 of the paper driven through the C ABI.
 
 Only buffers and call order live here; every step of an iteration is one of
 the library's entry points (the zero fill of the accumulated region
-correction at the start of an outer iteration is buffer initialisation)."""
+correction at the start of an outer iteration is buffer initialisation).
+outer_iteration runs one iteration on the context stream; run_pipelined
+overlaps consecutive iterations on two streams."""
 import numpy as np
 
 from ._lib import PDContext, PD_FP64
@@ -94,6 +96,55 @@ class Alg1Runner:
         infos = [self.inner_iteration(prec, rot_fp32, want_info) for _ in range(n_inner)]
         c.backsub(self.delta2, self.x)
         return infos
+
+    def run_pipelined(self, n_iters, spheres_of=None, n_workgroups=0, factor_stream=None):
+        """n_iters outer iterations with one inner iteration each, pipelined
+        over two streams.  The factorization side of iteration k (detection,
+        penalties, region local step, H = S + W^T C W and its Cholesky factor)
+        needs only the region positions after the inner update of iteration
+        k - 1, so it runs on a second stream while the back substitution of
+        k - 1, the full local step and the condensation of k run on the context
+        stream; the triangular solves and the inner update join both.  The
+        arithmetic is that of outer_iteration(n_inner=1) except that the
+        forward substitution is not fused into the factorization, and that the
+        region positions are carried over from the inner update instead of
+        being gathered from x after the back substitution (the same values:
+        delta2 holds the single update).  spheres_of(k) gives the obstacle
+        spheres of iteration k (None keeps the current ones)."""
+        torch = self.torch
+        c = self.ctx
+        s_main = c.stream
+        s_fac = factor_stream if factor_stream is not None else torch.cuda.Stream(device=self.x.device)
+        c.region_gather(self.x, self.x2)
+        ev_upd = torch.cuda.Event()
+        ev_upd.record(s_main)
+        for k in range(n_iters):
+            if spheres_of is not None:
+                self.spheres = spheres_of(k)
+            # factorization side of iteration k
+            s_fac.wait_event(ev_upd)
+            c.use_stream(s_fac)
+            self.detect()
+            c.collision_update(self.idx, self.w, self.c, self.t, self.x2, self.fcol)
+            c.local_step_region(self.x2, self.fb)
+            c.factor(n_workgroups)
+            ev_fac = torch.cuda.Event()
+            ev_fac.record(s_fac)
+            # sweep side: finish iteration k - 1, start iteration k
+            c.use_stream(s_main)
+            if k > 0:
+                c.backsub(self.delta2, self.x)
+            c.local_step_full(self.x, self.f)
+            c.condense_rhs(self.f, self.ft)
+            with torch.cuda.stream(s_main):
+                self.delta2.zero_()
+            s_main.wait_event(ev_fac)
+            c.assemble_rhs(self.ft, self.fb, self.fcol, self.g)
+            c.global_solve(self.g, self.u)
+            c.inner_update(self.u, self.x2, self.delta2, self.ft)
+            ev_upd = torch.cuda.Event()
+            ev_upd.record(s_main)
+        c.backsub(self.delta2, self.x)
 
     def positions(self):
         return self.x.reshape(3, -1).cpu().numpy()

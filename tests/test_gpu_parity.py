@@ -151,6 +151,33 @@ def test_alg1_iterations_match_oracle(torch_cuda, name, inner):
     assert worst <= 1e-9
 
 
+@pytest.mark.parametrize("name,n_wg", [("g9x7x6", 0), ("g16x15x8", 64)])
+def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg):
+    """Two-stream pipelined iterations (the factorization of iteration k
+    overlapping the back substitution of k - 1 and the condensation of k)
+    against the oracle's sequential Alg. 1 with one inner iteration."""
+    from paper_2008_01541_amd.driver import Alg1Runner
+    sc = SMALL_SCENES[name]()
+    om = oracle_model(sc)
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen)
+    frames = [1, 1, 2, 2, 3]
+    sph = {}
+    for f in sorted(set(frames)):
+        run.set_spheres(sc.spheres.centers(f), sc.spheres.radii)
+        sph[f] = run.spheres
+    torch_cuda.cuda.synchronize()
+    run.run_pipelined(len(frames), spheres_of=lambda k: sph[frames[k]], n_workgroups=n_wg)
+    x_or = sc.rest.copy()
+    for f in frames:
+        det = opd.sphere_detector(om, sc.proxy_local(), sc.spheres.centers(f), sc.spheres.radii,
+                                  sc.k_pen)
+        x_or = opd.alg1_outer_iteration(om, x_or, det, n_inner=1)
+    xg = run.positions()
+    disp = np.abs(x_or - sc.rest).max()
+    assert disp > 1e-6 * sc.h
+    assert np.abs(xg - x_or).max() / disp <= 1e-9
+
+
 def test_run_twice_bitwise_identical(torch_cuda):
     sc = SMALL_SCENES["g16x15x8"]()
     outs = []
