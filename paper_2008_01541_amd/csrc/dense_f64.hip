@@ -942,7 +942,26 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// L y = g.  Row block i: y_i = Linv_ii (g_i - sum_{p<i} L_ip y_p).
+// Two tile rows per workgroup ("super-row" s: tile rows TR s and TR s + 1), so
+// that one cross-workgroup hand-off covers 128 rows of the solve.  Thread
+// t works on row r = t & 63 of a tile and on the 16 columns cg = t >> 6 of it;
+// the four column groups are added through LDS.
+constexpr int TR = 2;
+
+// sums the four column-group partials of part (3 x 64 per group) into out[v][rr]
+// = base[v][rr] - sum; base may be null (then out = sum).
+__device__ inline void trsv_reduce(double (*part)[3][NB], const double* base, int ldb, int r0,
+                                   int mr, double (*out)[NB], bool negate) {
+  const int t = threadIdx.x;
+  if (t < 3 * NB) {
+    const int v = t >> 6, rr = t & 63;
+    const double sum = part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr];
+    const double b = (base && rr < mr) ? base[(long)v * ldb + r0 + rr] : 0.0;
+    out[v][rr] = negate ? b - sum : sum;
+  }
+}
+
+// L y = g.  Tile row i: y_i = Linv_ii (g_i - sum_{p<i} L_ip y_p).
 __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L, int ld, int n,
                                                    int nt, const double* __restrict__ linv,
                                                    const double* __restrict__ g, int ldg,
@@ -950,80 +969,116 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L,
                                                    unsigned long long* ticket, int* flags,
                                                    int* err) {
   __shared__ int s_row, s_epoch, s_ok;
-  __shared__ double ys[3][NB];
+  __shared__ double Ls[TR][NB][NB + 1];     // Ls[u][c][r] = Linv_{i_u}(r, c)
+  __shared__ double ys[3][TR * NB];         // y of a finished super-row / of this one
   __shared__ double part[4][3][NB];
-  __shared__ double Ls[NB][NB + 1];          // Ls[c][r] = Linv_ii(r, c)
+  __shared__ double zs[3][NB];
   const int t = threadIdx.x;
+  const int ns = (nt + TR - 1) / TR;
   if (t == 0) {
     const unsigned long long tk = atomicAdd(ticket, 1ull);
-    s_row = (int)(tk % (unsigned long long)nt);
-    s_epoch = (int)(tk / (unsigned long long)nt) + 1;
+    s_row = (int)(tk % (unsigned long long)ns);
+    s_epoch = (int)(tk / (unsigned long long)ns) + 1;
     s_ok = 1;
   }
   __syncthreads();
-  const int i = s_row, epoch = s_epoch;
-  const int r0 = i * NB, mr = min(NB, n - r0);
+  const int sr = s_row, epoch = s_epoch;
   const int r = t & 63, cg = t >> 6;
-  {
-    const double* Li = linv + (long)i * NB * NB;
-    for (int e = t; e < NB * NB; e += 256) Ls[e >> 6][e & 63] = Li[e];
-  }
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  double lv[16];
-  if (i > 0) {
+  const int i0 = TR * sr, nu = min(TR, nt - i0);
+  for (int u = 0; u < nu; ++u) {
+    const double* Li = linv + (long)(i0 + u) * NB * NB;
+    double v16[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      lv[q] = (r < mr) ? L[(long)(r0 + r) + (long)(cg * 16 + q) * ld] : 0.0;
+    for (int q = 0; q < 16; ++q) v16[q] = Li[t + 256 * q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Ls[u][(t >> 6) + 4 * q][t & 63] = v16[q];
   }
-  for (int p = 0; p < i; ++p) {
-    if (t == 0 && !wait_flag(&flags[p], epoch, err)) s_ok = 0;
+  double acc[TR][3];
+#pragma unroll
+  for (int u = 0; u < TR; ++u) acc[u][0] = acc[u][1] = acc[u][2] = 0.0;
+  for (int q = 0; q < sr; ++q) {
+    // the four operand tiles L_{i_u, TR q + u'} (16 columns each) load while the flag is awaited
+    double lv[TR][TR][16];
+#pragma unroll
+    for (int u = 0; u < TR; ++u) {
+      const int ru = (i0 + u) * NB + r;
+#pragma unroll
+      for (int w = 0; w < TR; ++w)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          lv[u][w][c] = (u < nu && ru < n) ? L[(long)ru + (long)((TR * q + w) * NB + cg * 16 + c) * ld]
+                                           : 0.0;
+    }
+    if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
     __syncthreads();
     if (!s_ok) return;
-    if (t < 3 * NB) ys[t >> 6][t & 63] = coherent_load(&y[(long)(t >> 6) * ldy + p * NB + (t & 63)]);
-    __syncthreads();
-    double cur[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cur[q] = lv[q];
-    if (p + 1 < i) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        lv[q] = (r < mr) ? L[(long)(r0 + r) + (long)((p + 1) * NB + cg * 16 + q) * ld] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = cg * 16 + q;
-      a0 += cur[q] * ys[0][c];
-      a1 += cur[q] * ys[1][c];
-      a2 += cur[q] * ys[2][c];
+    for (int e = t; e < 3 * TR * NB; e += 256) {
+      const int v = e / (TR * NB), cc = e - v * TR * NB;
+      ys[v][cc] = coherent_load(&y[(long)v * ldy + TR * q * NB + cc]);
     }
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TR; ++u)
+#pragma unroll
+      for (int w = 0; w < TR; ++w)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int col = w * NB + cg * 16 + c;
+          acc[u][0] += lv[u][w][c] * ys[0][col];
+          acc[u][1] += lv[u][w][c] * ys[1][col];
+          acc[u][2] += lv[u][w][c] * ys[2][col];
+        }
+    __syncthreads();
   }
-  part[cg][0][r] = a0;
-  part[cg][1][r] = a1;
-  part[cg][2][r] = a2;
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, rr = t & 63;
-    const double b = (rr < mr) ? g[(long)v * ldg + r0 + rr] : 0.0;
-    ys[v][rr] = b - (part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr]);
-  }
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, rr = t & 63;
-    double s0 = 0.0, s1 = 0.0;
-    int c = 0;
-    for (; c + 1 <= rr; c += 2) {
-      s0 += Ls[c][rr] * ys[v][c];
-      s1 += Ls[c + 1][rr] * ys[v][c + 1];
+  // finish the tile rows of this super-row in order
+  for (int u = 0; u < nu; ++u) {
+    const int i = i0 + u, r0 = i * NB, mr = min(NB, n - r0);
+    if (u > 0) {           // coupling to the rows finished above in this super-row
+      for (int w = 0; w < u; ++w)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int col = cg * 16 + c;
+          const double l = (r < mr) ? L[(long)(r0 + r) + (long)((i0 + w) * NB + col) * ld] : 0.0;
+          acc[u][0] += l * ys[0][w * NB + col];
+          acc[u][1] += l * ys[1][w * NB + col];
+          acc[u][2] += l * ys[2][w * NB + col];
+        }
     }
-    if (c <= rr) s0 += Ls[c][rr] * ys[v][c];
-    if (rr < mr) coherent_store(&y[(long)v * ldy + r0 + rr], s0 + s1);
+    part[cg][0][r] = acc[u][0];
+    part[cg][1][r] = acc[u][1];
+    part[cg][2][r] = acc[u][2];
+    __syncthreads();
+    trsv_reduce(part, g, ldg, r0, mr, zs, true);        // zs = g_i - sum
+    __syncthreads();
+    // y_i = Linv_ii zs: column group cg adds columns 16 cg .. 16 cg + 15
+    {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int col = cg * 16 + c;
+        const double l = Ls[u][col][r];
+        s0 += l * zs[0][col];
+        s1 += l * zs[1][col];
+        s2 += l * zs[2][col];
+      }
+      part[cg][0][r] = s0;
+      part[cg][1][r] = s1;
+      part[cg][2][r] = s2;
+    }
+    __syncthreads();
+    if (t < 3 * NB) {
+      const int v = t >> 6, rr = t & 63;
+      const double yv = part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr];
+      ys[v][u * NB + rr] = yv;
+      if (rr < mr) coherent_store(&y[(long)v * ldy + r0 + rr], yv);
+    }
+    __syncthreads();
   }
-  publish_flag(&flags[i], epoch);
+  publish_flag(&flags[sr], epoch);
 }
 
 // L^T x = y, reading L^T from the upper triangle (U(r, c) = L(c, r) for c > r):
-// x_i = Linv_ii^T (y_i - sum_{p>i} U_ip x_p).
+// x_i = Linv_ii^T (y_i - sum_{p>i} U_ip x_p).  Super-rows from the bottom.
 __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L, int ld, int n,
                                                    int nt, const double* __restrict__ linv,
                                                    const double* __restrict__ y, int ldy,
@@ -1031,95 +1086,129 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L,
                                                    unsigned long long* ticket, int* flags,
                                                    int* err) {
   __shared__ int s_row, s_epoch, s_ok;
-  __shared__ double xs[3][NB];
+  __shared__ double Ls[TR][NB][NB + 1];     // Ls[u][c][r] = Linv_{i_u}(r, c)
+  __shared__ double xs[3][TR * NB];
   __shared__ double part[4][3][NB];
-  __shared__ double Ls[NB][NB + 1];          // Ls[c][r] = Linv_ii(r, c)
+  __shared__ double zs[3][NB];
   const int t = threadIdx.x;
+  const int ns = (nt + TR - 1) / TR;
   if (t == 0) {
     const unsigned long long tk = atomicAdd(ticket, 1ull);
-    s_row = nt - 1 - (int)(tk % (unsigned long long)nt);
-    s_epoch = (int)(tk / (unsigned long long)nt) + 1;
+    s_row = ns - 1 - (int)(tk % (unsigned long long)ns);
+    s_epoch = (int)(tk / (unsigned long long)ns) + 1;
     s_ok = 1;
   }
   __syncthreads();
-  const int i = s_row, epoch = s_epoch;
-  const int r0 = i * NB, mr = min(NB, n - r0);
+  const int sr = s_row, epoch = s_epoch;
   const int r = t & 63, cg = t >> 6;
-  {
-    const double* Li = linv + (long)i * NB * NB;
-    for (int e = t; e < NB * NB; e += 256) Ls[e >> 6][e & 63] = Li[e];
-  }
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-  double lv[16];
-  auto load_tile = [&](int p) {
-    const int pr0 = p * NB;
+  const int i0 = TR * sr, nu = min(TR, nt - i0);
+  for (int u = 0; u < nu; ++u) {
+    const double* Li = linv + (long)(i0 + u) * NB * NB;
+    double v16[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = pr0 + cg * 16 + q;
-      lv[q] = (r < mr && col < n) ? L[(long)(r0 + r) + (long)col * ld] : 0.0;
+    for (int q = 0; q < 16; ++q) v16[q] = Li[t + 256 * q];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Ls[u][(t >> 6) + 4 * q][t & 63] = v16[q];
+  }
+  double acc[TR][3];
+#pragma unroll
+  for (int u = 0; u < TR; ++u) acc[u][0] = acc[u][1] = acc[u][2] = 0.0;
+  for (int q = ns - 1; q > sr; --q) {
+    double lv[TR][TR][16];
+#pragma unroll
+    for (int u = 0; u < TR; ++u) {
+      const int ru = (i0 + u) * NB + r;
+#pragma unroll
+      for (int w = 0; w < TR; ++w)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int col = (TR * q + w) * NB + cg * 16 + c;
+          lv[u][w][c] = (u < nu && ru < n && col < n) ? L[(long)ru + (long)col * ld] : 0.0;
+        }
     }
-  };
-  if (i < nt - 1) load_tile(nt - 1);
-  for (int p = nt - 1; p > i; --p) {
-    const int pr0 = p * NB, pmr = min(NB, n - pr0);
-    if (t == 0 && !wait_flag(&flags[p], epoch, err)) s_ok = 0;
+    if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
     __syncthreads();
     if (!s_ok) return;
+    const int qn = min(TR * NB, n - TR * q * NB);
+    for (int e = t; e < 3 * TR * NB; e += 256) {
+      const int v = e / (TR * NB), cc = e - v * TR * NB;
+      xs[v][cc] = (cc < qn) ? coherent_load(&x[(long)v * ldx + TR * q * NB + cc]) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TR; ++u)
+#pragma unroll
+      for (int w = 0; w < TR; ++w)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int col = w * NB + cg * 16 + c;
+          acc[u][0] += lv[u][w][c] * xs[0][col];
+          acc[u][1] += lv[u][w][c] * xs[1][col];
+          acc[u][2] += lv[u][w][c] * xs[2][col];
+        }
+    __syncthreads();
+  }
+  for (int u = nu - 1; u >= 0; --u) {
+    const int i = i0 + u, r0 = i * NB, mr = min(NB, n - r0);
+    if (u + 1 < nu) {      // coupling to the rows finished below in this super-row
+      for (int w = u + 1; w < nu; ++w) {
+        const int wn = min(NB, n - (i0 + w) * NB);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int col = cg * 16 + c;
+          const double l = (col < wn) ? L[(long)(r0 + r) + (long)((i0 + w) * NB + col) * ld] : 0.0;
+          acc[u][0] += l * xs[0][w * NB + col];
+          acc[u][1] += l * xs[1][w * NB + col];
+          acc[u][2] += l * xs[2][w * NB + col];
+        }
+      }
+    }
+    part[cg][0][r] = acc[u][0];
+    part[cg][1][r] = acc[u][1];
+    part[cg][2][r] = acc[u][2];
+    __syncthreads();
+    trsv_reduce(part, y, ldy, r0, mr, zs, true);        // zs = y_i - sum
+    __syncthreads();
+    // x_i = Linv_ii^T zs: (Linv^T z)(rr) = sum_c Linv(c, rr) z(c) = sum_c Ls[rr][c] z(c);
+    // thread (r, cg) adds c = 16 cg .. 16 cg + 15 for output row r
+    {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int col = cg * 16 + c;
+        const double l = Ls[u][r][col];
+        s0 += l * zs[0][col];
+        s1 += l * zs[1][col];
+        s2 += l * zs[2][col];
+      }
+      part[cg][0][r] = s0;
+      part[cg][1][r] = s1;
+      part[cg][2][r] = s2;
+    }
+    __syncthreads();
     if (t < 3 * NB) {
-      const int v = t >> 6, cc = t & 63;
-      xs[v][cc] = (cc < pmr) ? coherent_load(&x[(long)v * ldx + pr0 + cc]) : 0.0;
-    }
-    __syncthreads();
-    double cur[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cur[q] = lv[q];
-    if (p - 1 > i) load_tile(p - 1);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = cg * 16 + q;
-      a0 += cur[q] * xs[0][c];
-      a1 += cur[q] * xs[1][c];
-      a2 += cur[q] * xs[2][c];
+      const int v = t >> 6, rr = t & 63;
+      const double xv = part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr];
+      xs[v][u * NB + rr] = xv;
+      if (rr < mr) coherent_store(&x[(long)v * ldx + r0 + rr], xv);
     }
     __syncthreads();
   }
-  part[cg][0][r] = a0;
-  part[cg][1][r] = a1;
-  part[cg][2][r] = a2;
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, rr = t & 63;
-    const double b = (rr < mr) ? y[(long)v * ldy + r0 + rr] : 0.0;
-    xs[v][rr] = b - (part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr]);
-  }
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, rr = t & 63;
-    // (Linv^T b)_rr = sum_{c >= rr} Linv(c, rr) b_c = sum_c Ls[rr][c] b_c
-    double s0 = 0.0, s1 = 0.0;
-    int c = rr;
-    for (; c + 1 < NB; c += 2) {
-      s0 += Ls[rr][c] * xs[v][c];
-      s1 += Ls[rr][c + 1] * xs[v][c + 1];
-    }
-    if (c < NB) s0 += Ls[rr][c] * xs[v][c];
-    if (rr < mr) coherent_store(&x[(long)v * ldx + r0 + rr], s0 + s1);
-  }
-  publish_flag(&flags[i], epoch);
+  publish_flag(&flags[sr], epoch);
 }
 
 void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const double* g,
                    int ldg, double* y, int ldy, unsigned long long* ticket, int* flags,
                    int* err, hipStream_t st) {
-  const int nt = (n + NB - 1) / NB;
-  k_trsv3_fwd<<<nt, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err);
+  const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
+  k_trsv3_fwd<<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err);
 }
 
 void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
                     int ldy, double* x, int ldx, unsigned long long* ticket, int* flags,
                     int* err, hipStream_t st) {
-  const int nt = (n + NB - 1) / NB;
-  k_trsv3_bwd<<<nt, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, flags, err);
+  const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
+  k_trsv3_bwd<<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, flags, err);
 }
 
 // ---------------------------------------------------------------------------
