@@ -104,7 +104,7 @@ struct pd_ctx {
   // sweeps
   double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
   bool have_condense = false;
-  double* d_P = nullptr;              // chunk sums of one level's dense product (24 maxw)
+  double* d_P = nullptr;              // tile parts of one level's dense product
   // penalties
   int32_t n_pen = 0, pen_cap = 0;
   int32_t* d_pidx = nullptr;
@@ -715,7 +715,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&c->d_v, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_xs, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_tmp, 3 * std::max<int64_t>(1, c->maxw)));
-  CK(c->alloc(&c->d_P, 24 * std::max<int64_t>(1, c->maxw)));
+  CK(c->alloc(&c->d_P, sweep_workspace(c->maxw)));
   HIPCK(c, hipStreamSynchronize(c->st));
   return PD_OK;
 }
@@ -821,15 +821,16 @@ pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
     const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
     sweep_symv(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_fhat + off, n1, c->d_P,
                c->st);
+    sweep_assemble((int)w, c->d_P, nullptr, 0, c->d_v + off, n1, c->st);     // v_k = Z_k fhat_k
     const int32_t* bp = c->d_Bptr + c->B_ptr_off[k];
     const int32_t* bc = c->d_Bcol + c->B_nnz_off[k];
     const double* bv = c->d_Bval + c->B_nnz_off[k];
     if (k + 1 < c->K) {
       const int64_t off2 = c->lev_off[k + 1], w2 = c->lev_off[k + 2] - off2;
-      sweep_fwd_couple((int)w, c->d_P, c->d_v + off, n1, (int)w2, bp, bc, bv, c->d_fhat + off2, n1,
-                       c->st);
+      csr_spmv3(w2, bp, bc, bv, c->d_v + off, n1, -1.0, c->d_fhat + off2, n1, c->d_fhat + off2, n1,
+                c->st);
     } else {
-      sweep_fwd_couple((int)w, c->d_P, c->d_v + off, n1, (int)m, bp, bc, bv, y2, m, c->st);
+      csr_spmv3(m, bp, bc, bv, c->d_v + off, n1, -1.0, y2, m, y2, m, c->st);
     }
   }
   c->have_condense = true;
@@ -843,27 +844,19 @@ pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
   const int64_t n1 = c->n1, m = c->m;
   PhaseTimer tm(c, PD_PHASE_BACKSUB);
   if (n1 > 0) {
-    // level k: tmp = B_k^T x_{k+1} (finishing xs_{k+1} = v_{k+1} - Z_{k+1} tmp_{k+1}), then
-    // the chunk sums of Z_k tmp; x_K = delta2
+    // level k: tmp = B_k^T x_{k+1} (x_K = delta2), then xs_k = v_k - Z_k tmp
     for (int k = c->K - 1; k >= 0; --k) {
       const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
       const int32_t* tp = c->d_Btptr + c->Bt_ptr_off[k];
       const int32_t* tc = c->d_Btcol + c->Bt_nnz_off[k];
       const double* tv = c->d_Btval + c->Bt_nnz_off[k];
-      if (k + 1 < c->K) {
-        const int64_t offn = c->lev_off[k + 1], wn = c->lev_off[k + 2] - offn;
-        sweep_bwd_couple((int)wn, c->d_P, c->d_v + offn, c->d_xs + offn, n1, nullptr, 0, (int)w,
-                         tp, tc, tv, c->d_tmp, c->maxw, c->st);
-      } else {
-        sweep_bwd_couple(0, nullptr, nullptr, nullptr, n1, delta2, m, (int)w, tp, tc, tv, c->d_tmp,
-                         c->maxw, c->st);
-      }
+      const double* xn = (k + 1 < c->K) ? c->d_xs + c->lev_off[k + 1] : delta2;
+      const int64_t ldxn = (k + 1 < c->K) ? n1 : m;
+      csr_spmv3(w, tp, tc, tv, xn, ldxn, 1.0, c->d_tmp, c->maxw, nullptr, 0, c->st);
       sweep_symv(c->d_levmat + c->lev_mat_off[k], c->ldw[k], (int)w, c->d_tmp, c->maxw, c->d_P,
                  c->st);
+      sweep_assemble((int)w, c->d_P, c->d_v + off, n1, c->d_xs + off, n1, c->st);
     }
-    const int64_t w0 = c->lev_off[1] - c->lev_off[0];
-    sweep_bwd_couple((int)w0, c->d_P, c->d_v, c->d_xs, n1, nullptr, 0, 0, nullptr, nullptr, nullptr,
-                     nullptr, 0, c->st);
     scatter_add_rows3(n1, c->d_lev_nodes, c->d_xs, n1, x, c->n, c->st);
   }
   scatter_add_rows3(m, c->d_region_ids, delta2, m, x, c->n, c->st);

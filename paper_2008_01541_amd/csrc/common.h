@@ -55,18 +55,16 @@ void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const d
                     const double* r, float* y, float* xs, double* x, int accumulate,
                     unsigned long long* tickets, int* flags, int* err, hipStream_t st);
 
-// condensation sweeps, one interior level at a time.  sweep_split gives the
-// row chunks R of a level of width w; the chunk workspace P holds 3 R w doubles
-// (at most 24 w).
-void sweep_split(int64_t w, int* R, int* chunk);
+// condensation sweeps, one interior level at a time: sweep_symv writes the
+// tile parts of Z x for a level of width w (Z symmetric, only its lower tiles
+// read) into P (sweep_workspace(maxw) doubles); sweep_assemble forms
+// out = Z x, or out = base - Z x when base is non-null (all [3][*] with
+// leading dimensions ldx, ldb, ldo).
+int64_t sweep_workspace(int64_t maxw);
 void sweep_symv(const double* Z, long ldz, int w, const double* x, long ldx, double* P,
                 hipStream_t st);
-void sweep_fwd_couple(int w, const double* P, double* v, long ldv, int rows, const int32_t* ptr,
-                      const int32_t* col, const double* val, double* xn, long ldn, hipStream_t st);
-void sweep_bwd_couple(int wn, const double* Q, const double* vn, double* xsn, long ldv,
-                      const double* delta2, long ldd, int rows, const int32_t* ptr,
-                      const int32_t* col, const double* val, double* tmp, long ldt,
-                      hipStream_t st);
+void sweep_assemble(int w, const double* P, const double* base, long ldb, double* out, long ldo,
+                    hipStream_t st);
 
 // FEM / sparse
 void tet_geometry(const double* rest, int64_t n, const int32_t* tets, int64_t T,

@@ -1,15 +1,18 @@
 // Condensation sweeps through the interior factor (one-way dissection in
 // breadth-first levels, Z_k = S_k^-1 dense and symmetric, B_k the sparse
 // coupling of level k to level k+1 or to the region).  The level chain is
-// sequential, so each level is two launches: a dense product with Z_k, and a
-// sparse coupling update that also finishes the dense product.
+// sequential; each level is a dense product with Z_k, the assembly of its
+// result, and a sparse coupling update (csr_spmv3).
 //
-// Dense product: (Z_k x)[c] = Z_k[:, c] . x (Z_k symmetric, full storage,
-// column-major).  One wave owns 4 columns over one chunk of about 800 rows and
-// streams them with 16-byte loads, two row blocks in flight; the chunk
-// results (one partial sum per chunk, column and right-hand side) go to a
-// small workspace P[chunk][rhs][column], and the coupling launch adds them in
-// chunk order, so results do not depend on scheduling.
+// Dense product y = Z_k x with only the lower triangle read: Z_k is stored in
+// full (column-major), but the kernels walk the lower 64 x 64 tiles (I, J),
+// J <= I, once each, computing
+//   row part  Z_IJ x_J      (I > J), and
+//   col part  Z_IJ^T x_I,
+// each into the tile's slot of a workspace.  y_I is then the sum of the row
+// parts of tiles (I, J < I) and the col parts of tiles (I' >= I, I), taken
+// in that fixed order by the assembly kernel, so results do not depend on
+// scheduling.  HBM traffic is half the full matrix.
 #include <algorithm>
 #include "common.h"
 
@@ -17,191 +20,137 @@ namespace pdk {
 
 namespace {
 
-constexpr int SW_CW = 4;     // columns per wave
-constexpr int SW_U = 2;      // row blocks (128 rows each) in flight per wave
+constexpr int TS = 64;                 // tile size of the level products
+constexpr int SLOT = 3 * TS;           // doubles per part slot: [rhs][64]
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// P[(r * 3 + v) * w + c] = sum over rows j of chunk r of Z[j + c ldz] x[v ldx + j]
+// One wave per lower tile (I, J): the wave loads the whole 64 x 64 tile into
+// registers (lane = row, 64 coalesced column loads in flight), adds the row
+// part Z_IJ x_J in-lane, and forms the col part Z_IJ^T x_I sixteen columns at
+// a time through a wave-private LDS transpose (lane = (column, row group),
+// then two cross-lane additions).  Row parts go to slot t(I, J) of Prow
+// (off-diagonal tiles), col parts to slot t(I, J) of Pcol.
 __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z, long ldz, int w,
-                                                    int R, int chunk, const double* __restrict__ x,
-                                                    long ldx, double* __restrict__ P) {
-  const int lane = threadIdx.x & 63;
-  const int u = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int ngroups = (w + SW_CW - 1) / SW_CW;
-  if (u >= ngroups * R) return;
-  const int g = u / R, r = u - g * R, c0 = g * SW_CW;
-  const int j0 = r * chunk, j1 = min(w, j0 + chunk);
-  double s[SW_CW][3];
-  const double* col[SW_CW];
+                                                    int nb, const double* __restrict__ x, long ldx,
+                                                    double* __restrict__ Prow,
+                                                    double* __restrict__ Pcol) {
+  __shared__ double Ts[4][TS][17];         // per wave: 64 rows x 16 columns (+1 pad)
+  __shared__ double xs[4][2][3][TS];       // per wave: x_J, x_I
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int tt = blockIdx.x * 4 + wv;
+  const int ntiles = nb * (nb + 1) / 2;
+  if (tt >= ntiles) return;
+  int I = (int)((sqrt(8.0 * (double)tt + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= tt) ++I;
+  while (I * (I + 1) / 2 > tt) --I;
+  I = __builtin_amdgcn_readfirstlane(I);
+  const int J = tt - I * (I + 1) / 2;
+  const int i0 = I * TS, j0 = J * TS;
+  const int nr = min(TS, w - i0), nc = min(TS, w - j0);
+  // buffer loads: one 32-bit lane offset (the row) for all 64 columns, the
+  // column offset in a scalar register; lanes past the last row get an offset
+  // beyond the buffer's range and read zero
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(Z + (long)j0 * ldz), 0, (int)(nc * ldz * (long)sizeof(double)), 0x00020000);
+  const int voff = lane < nr ? (i0 + lane) * (int)sizeof(double) : 0x7ffffff0;
+  double z[TS];
 #pragma unroll
-  for (int cc = 0; cc < SW_CW; ++cc) {
-    s[cc][0] = s[cc][1] = s[cc][2] = 0.0;
-    col[cc] = Z + (long)min(c0 + cc, w - 1) * ldz;   // columns past w repeat the last one
+  for (int c = 0; c < TS; ++c)
+    z[c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                          rs, voff, c * (int)(ldz * sizeof(double)), 0));
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    xs[wv][0][v][lane] = lane < nc ? x[(long)v * ldx + j0 + lane] : 0.0;
+    xs[wv][1][v][lane] = lane < nr ? x[(long)v * ldx + i0 + lane] : 0.0;
   }
-  const double* x0 = x;
-  const double* x1 = x + ldx;
-  const double* x2 = x + 2 * ldx;
-  int j = j0 + 2 * lane;                   // rows j, j + 1 (column starts are 16-byte aligned)
-  for (; j + 128 * (SW_U - 1) + 1 < j1; j += 128 * SW_U) {
-    double2 z[SW_U][SW_CW];
-    double xv[SW_U][3][2];
+  if (nc < TS) {
 #pragma unroll
-    for (int q = 0; q < SW_U; ++q) {
-      const int jj = j + 128 * q;
+    for (int c = 0; c < TS; ++c)
+      if (c >= nc) z[c] = 0.0;
+  }
+  // row part, lane = row
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int cc = 0; cc < SW_CW; ++cc) z[q][cc] = *(const double2*)(col[cc] + jj);
-      xv[q][0][0] = x0[jj]; xv[q][0][1] = x0[jj + 1];
-      xv[q][1][0] = x1[jj]; xv[q][1][1] = x1[jj + 1];
-      xv[q][2][0] = x2[jj]; xv[q][2][1] = x2[jj + 1];
+  for (int c = 0; c < TS; ++c) {
+    s0 += z[c] * xs[wv][0][0][c];
+    s1 += z[c] * xs[wv][0][1][c];
+    s2 += z[c] * xs[wv][0][2][c];
+  }
+  if (I > J) {
+    double* pr = Prow + (long)tt * SLOT;
+    pr[lane] = s0;
+    pr[TS + lane] = s1;
+    pr[2 * TS + lane] = s2;
+  }
+  // col part, sixteen columns at a time: lane = (cc = lane & 15, rg = lane >> 4)
+  const int cc = lane & 15, rg = lane >> 4;
+  double* pc = Pcol + (long)tt * SLOT;
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) Ts[wv][lane][c] = z[16 * sb + c];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = 16 * rg + q;
+      const double zz = Ts[wv][r][cc];
+      a0 += zz * xs[wv][1][0][r];
+      a1 += zz * xs[wv][1][1][r];
+      a2 += zz * xs[wv][1][2][r];
     }
-#pragma unroll
-    for (int q = 0; q < SW_U; ++q)
-#pragma unroll
-      for (int cc = 0; cc < SW_CW; ++cc)
-#pragma unroll
-        for (int vv = 0; vv < 3; ++vv)
-          s[cc][vv] += z[q][cc].x * xv[q][vv][0] + z[q][cc].y * xv[q][vv][1];
-  }
-  for (; j < j1; j += 128) {
-    const bool two = j + 1 < j1;
-#pragma unroll
-    for (int cc = 0; cc < SW_CW; ++cc) {
-      const double za = col[cc][j], zb = two ? col[cc][j + 1] : 0.0;
-      s[cc][0] += za * x0[j] + (two ? zb * x0[j + 1] : 0.0);
-      s[cc][1] += za * x1[j] + (two ? zb * x1[j + 1] : 0.0);
-      s[cc][2] += za * x2[j] + (two ? zb * x2[j + 1] : 0.0);
+    a0 += __shfl_xor(a0, 16, 64);
+    a1 += __shfl_xor(a1, 16, 64);
+    a2 += __shfl_xor(a2, 16, 64);
+    a0 += __shfl_xor(a0, 32, 64);
+    a1 += __shfl_xor(a1, 32, 64);
+    a2 += __shfl_xor(a2, 32, 64);
+    if (lane < 16) {
+      pc[16 * sb + lane] = a0;
+      pc[TS + 16 * sb + lane] = a1;
+      pc[2 * TS + 16 * sb + lane] = a2;
     }
-  }
-#pragma unroll
-  for (int cc = 0; cc < SW_CW; ++cc)
-#pragma unroll
-    for (int vv = 0; vv < 3; ++vv) s[cc][vv] = wave_sum(s[cc][vv]);
-  if (lane == 0) {
-#pragma unroll
-    for (int cc = 0; cc < SW_CW; ++cc)
-      if (c0 + cc < w)
-#pragma unroll
-        for (int vv = 0; vv < 3; ++vv) P[(long)(r * 3 + vv) * w + c0 + cc] = s[cc][vv];
   }
 }
 
-// One thread per (row, right-hand side): v[vv][c] = (Z_k x)[c] from the chunk
-// sums of P (c < w); xn[vv][t] -= sum_e B(t, e) v[vv][col(e)] (t < rows).  The
-// neighbour loop is unrolled so that its loads are in flight together.
-__global__ void k_sweep_fwd_couple(int w, int R, const double* __restrict__ P, double* __restrict__ v,
-                                   long ldv, int rows, const int32_t* __restrict__ ptr,
-                                   const int32_t* __restrict__ col, const double* __restrict__ val,
-                                   double* __restrict__ xn, long ldn) {
-  const int n = max(w, rows);
+// out[v][g] = s or base[v][g] - s, s = (Z x)[v][g]: row parts of tiles (I, J < I),
+// then col parts of tiles (I' >= I, I), in that order.
+__global__ void k_sweep_assemble(int w, int nb, const double* __restrict__ Prow,
+                                 const double* __restrict__ Pcol, const double* __restrict__ base,
+                                 long ldb, double* __restrict__ out, long ldo) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int vv = gt / n, t = gt - vv * n;
-  if (vv >= 3) return;
-  const double* Pv = P + (long)vv * w;
-  const long ldp = 3L * w;
-  if (t < w) {
-    double s = 0.0;
-    for (int r = 0; r < R; ++r) s += Pv[r * ldp + t];
-    v[(long)vv * ldv + t] = s;
-  }
-  if (t < rows) {
-    double acc = 0.0;
-    const int e1 = ptr[t + 1];
+  const int v = gt / w, g = gt - v * w;
+  if (v >= 3) return;
+  const int I = g / TS, r = g - I * TS;
+  double s = 0.0;
+  const double* row = Prow + (long)(I * (I + 1) / 2) * SLOT + v * TS + r;
 #pragma unroll 4
-    for (int e = ptr[t]; e < e1; ++e) {
-      const int c = col[e];
-      double s = 0.0;
-      for (int r = 0; r < R; ++r) s += Pv[r * ldp + c];
-      acc += val[e] * s;
-    }
-    xn[(long)vv * ldn + t] -= acc;
-  }
-}
-
-// Next level (k + 1) finished: xs_n = v_n - Z_n tmp_n from the chunk sums Q of
-// Z_n tmp_n (t < wn); then tmp[t] = sum_e B^T(t, e) x_n[col(e)] for t < rows,
-// with x_n = xs_n, or x_n = delta2 when Q is null (level k is the last one).
-// One thread per (row, right-hand side).
-__global__ void k_sweep_bwd_couple(int wn, int R, const double* __restrict__ Q,
-                                   const double* __restrict__ vn, double* __restrict__ xsn, long ldv,
-                                   const double* __restrict__ delta2, long ldd, int rows,
-                                   const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                   const double* __restrict__ val, double* __restrict__ tmp,
-                                   long ldt) {
-  const int n = max(Q ? wn : 0, rows);
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int vv = gt / n, t = gt - vv * n;
-  if (vv >= 3) return;
-  const long ldq = 3L * wn;
-  const double* Qv = Q ? Q + (long)vv * wn : nullptr;
-  const double* vnv = vn ? vn + (long)vv * ldv : nullptr;
-  if (Q && t < wn) {
-    double s = 0.0;
-    for (int r = 0; r < R; ++r) s += Qv[r * ldq + t];
-    xsn[(long)vv * ldv + t] = vnv[t] - s;
-  }
-  if (t < rows) {
-    double acc = 0.0;
-    const int e1 = ptr[t + 1];
-    if (Q) {
+  for (int J = 0; J < I; ++J) s += row[(long)J * SLOT];
+  const double* col = Pcol + v * TS + r;
 #pragma unroll 4
-      for (int e = ptr[t]; e < e1; ++e) {
-        const int c = col[e];
-        double s = 0.0;
-        for (int r = 0; r < R; ++r) s += Qv[r * ldq + c];
-        acc += val[e] * (vnv[c] - s);
-      }
-    } else {
-      const double* d2 = delta2 + (long)vv * ldd;
-#pragma unroll 4
-      for (int e = ptr[t]; e < e1; ++e) acc += val[e] * d2[col[e]];
-    }
-    tmp[(long)vv * ldt + t] = acc;
-  }
+  for (int Ip = I; Ip < nb; ++Ip) s += col[(long)(Ip * (Ip + 1) / 2 + I) * SLOT];
+  out[(long)v * ldo + g] = base ? base[(long)v * ldb + g] - s : s;
 }
 
 }  // namespace
 
-void sweep_split(int64_t w, int* R, int* chunk) {
-  const int r0 = (int)std::min<int64_t>(8, std::max<int64_t>(1, (w + 400) / 800));
-  const int64_t ch = ((w + r0 - 1) / r0 + 127) / 128 * 128;
-  *chunk = (int)std::max<int64_t>(128, ch);
-  *R = (int)std::max<int64_t>(1, (w + *chunk - 1) / *chunk);
+int64_t sweep_workspace(int64_t maxw) {
+  const int64_t nb = (maxw + TS - 1) / TS;
+  return std::max<int64_t>(1, nb * (nb + 1) / 2) * 2 * SLOT;
 }
 
 void sweep_symv(const double* Z, long ldz, int w, const double* x, long ldx, double* P,
                 hipStream_t st) {
   if (w <= 0) return;
-  int R, chunk;
-  sweep_split(w, &R, &chunk);
-  const int units = (w + SW_CW - 1) / SW_CW * R;
-  k_sweep_symv<<<(units + 3) / 4, 256, 0, st>>>(Z, ldz, w, R, chunk, x, ldx, P);
+  const int nb = (w + TS - 1) / TS, ntiles = nb * (nb + 1) / 2;
+  k_sweep_symv<<<(ntiles + 3) / 4, 256, 0, st>>>(Z, ldz, w, nb, x, ldx, P, P + (long)ntiles * SLOT);
 }
 
-void sweep_fwd_couple(int w, const double* P, double* v, long ldv, int rows, const int32_t* ptr,
-                      const int32_t* col, const double* val, double* xn, long ldn, hipStream_t st) {
-  const int n = std::max(w, rows);
-  if (n <= 0) return;
-  int R, chunk;
-  sweep_split(w, &R, &chunk);
-  k_sweep_fwd_couple<<<(3 * n + 255) / 256, 256, 0, st>>>(w, R, P, v, ldv, rows, ptr, col, val, xn,
-                                                         ldn);
-}
-
-void sweep_bwd_couple(int wn, const double* Q, const double* vn, double* xsn, long ldv,
-                      const double* delta2, long ldd, int rows, const int32_t* ptr,
-                      const int32_t* col, const double* val, double* tmp, long ldt,
-                      hipStream_t st) {
-  const int n = std::max(Q ? wn : 0, rows);
-  if (n <= 0) return;
-  int R = 1, chunk;
-  if (Q) sweep_split(wn, &R, &chunk);
-  k_sweep_bwd_couple<<<(3 * n + 255) / 256, 256, 0, st>>>(wn, R, Q, vn, xsn, ldv, delta2, ldd,
-                                                          rows, ptr, col, val, tmp, ldt);
+void sweep_assemble(int w, const double* P, const double* base, long ldb, double* out, long ldo,
+                    hipStream_t st) {
+  if (w <= 0) return;
+  const int nb = (w + TS - 1) / TS, ntiles = nb * (nb + 1) / 2;
+  k_sweep_assemble<<<(3 * w + 255) / 256, 256, 0, st>>>(w, nb, P, P + (long)ntiles * SLOT, base,
+                                                        ldb, out, ldo);
 }
 
 }  // namespace pdk
