@@ -112,23 +112,32 @@ __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z
   }
 }
 
-// out[v][g] = s or base[v][g] - s, s = (Z x)[v][g]: row parts of tiles (I, J < I),
-// then col parts of tiles (I' >= I, I), in that order.
+// out[v][g] = s or base[v][g] - s, s = (Z x)[v][g].  Output row g of block I
+// has nb terms k = 0 .. nb - 1: the row part of tile (I, k) for k < I and the
+// col part of tile (k, I) for k >= I.  Four lanes share an output, lane q
+// adding terms k = q, q + 4, ...; the four partial sums are combined as
+// (s0 + s1) + (s2 + s3), so the result does not depend on scheduling.
 __global__ void k_sweep_assemble(int w, int nb, const double* __restrict__ Prow,
                                  const double* __restrict__ Pcol, const double* __restrict__ base,
                                  long ldb, double* __restrict__ out, long ldo) {
   const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = gt / w, g = gt - v * w;
-  if (v >= 3) return;
-  const int I = g / TS, r = g - I * TS;
+  const int q = gt & 3, o = gt >> 2;
+  const int v = o / w, g = o - v * w;
+  const bool live = v < 3;
   double s = 0.0;
-  const double* row = Prow + (long)(I * (I + 1) / 2) * SLOT + v * TS + r;
+  if (live) {
+    const int I = g / TS, r = g - I * TS;
+    const double* row = Prow + (long)(I * (I + 1) / 2) * SLOT + v * TS + r;
+    const double* col = Pcol + v * TS + r;
 #pragma unroll 4
-  for (int J = 0; J < I; ++J) s += row[(long)J * SLOT];
-  const double* col = Pcol + v * TS + r;
-#pragma unroll 4
-  for (int Ip = I; Ip < nb; ++Ip) s += col[(long)(Ip * (Ip + 1) / 2 + I) * SLOT];
-  out[(long)v * ldo + g] = base ? base[(long)v * ldb + g] - s : s;
+    for (int k = q; k < nb; k += 4)
+      s += (k < I) ? row[(long)k * SLOT] : col[(long)(k * (k + 1) / 2 + I) * SLOT];
+  }
+  const double s1 = __shfl_xor(s, 1, 64);
+  const double pair = (q & 1) ? s1 + s : s + s1;           // (s0 + s1) or (s2 + s3)
+  const double other = __shfl_xor(pair, 2, 64);
+  const double tot = (q & 2) ? other + pair : pair + other;
+  if (live && q == 0) out[(long)v * ldo + g] = base ? base[(long)v * ldb + g] - tot : tot;
 }
 
 }  // namespace
@@ -149,8 +158,8 @@ void sweep_assemble(int w, const double* P, const double* base, long ldb, double
                     hipStream_t st) {
   if (w <= 0) return;
   const int nb = (w + TS - 1) / TS, ntiles = nb * (nb + 1) / 2;
-  k_sweep_assemble<<<(3 * w + 255) / 256, 256, 0, st>>>(w, nb, P, P + (long)ntiles * SLOT, base,
-                                                        ldb, out, ldo);
+  k_sweep_assemble<<<(12 * w + 255) / 256, 256, 0, st>>>(w, nb, P, P + (long)ntiles * SLOT, base,
+                                                         ldb, out, ldo);
 }
 
 }  // namespace pdk
