@@ -23,6 +23,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+# HBM bytes per launch of the Schur factorization, from the rocprofv3 counter
+# runs summarised in this file (FETCH_SIZE and WRITE_SIZE, each scaled by the
+# same counter on a plain copy of known size); valid only while the kernel
+# source it names is unchanged (its sha256 is recorded there).
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "schur_factor_slab56_counters.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2008_01541_amd", "csrc", "dense_f64.hip")
+
+
+def measured_traffic():
+    """(bytes per launch, note) if the counter summary matches the current kernel source."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    h = re.search(r"dense_f64\.hip sha256:\s*([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != src:
+        return None
+    return int(m.group(1))
 
 
 def cpu_baseline(sc, frame):
@@ -318,7 +340,8 @@ def main():
         "schur_build_s": build_s,
         "roofline": {"bound": "mfma", "kernel": "schur_cholesky_fp64 (n^3/3 flop per factorization)",
                      "achieved": chol_tflops, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": chol_tflops / FP64_MFMA_PEAK_TFLOPS, "traffic": None},
+                     "frac": chol_tflops / FP64_MFMA_PEAK_TFLOPS,
+                     "traffic": measured_traffic(), "traffic_unit": "bytes per launch"},
     }
     if not args.no_precision_modes:
         out["precision_modes"] = precision_modes(run, sph[frames[-1]], args.inner)

@@ -170,18 +170,29 @@ pd_status pd_global_solve(pd_ctx *ctx, const double *g, double *u, pd_precision 
                           pd_solve_info *info);
 
 /* FP64 factorization of H = S + W^T C W ahead of the solve (Alg. 1 step 4.3,
- * Sec. 4.4 Step 2), for callers that overlap it with other work: a following
- * pd_global_solve(PD_FP64) then only runs the triangular solves (it would
- * otherwise fuse the forward substitution into the factorization).  H only
+ * Sec. 4.4 Step 2), for callers that overlap it with other work: H only
  * depends on the penalty set and S, not on the right-hand side, so the
  * factorization may run on a second stream while pd_backsub, the full local
  * step and pd_condense_rhs of the next iteration run on the first (see
  * pd_use_stream).  n_workgroups > 0 caps the persistent workgroups of the
  * factorization (default 2 per compute unit; fewer leave room for kernels of
- * the other stream); <= 0 keeps the default.  A no-op when the factor is
- * current.  Non-positive pivots are reported by a later pd_global_solve
- * with info. */
-pd_status pd_factor(pd_ctx *ctx, int32_t n_workgroups);
+ * the other stream); <= 0 keeps the default.
+ * supply_rhs = 0: a following pd_global_solve(PD_FP64) runs both triangular
+ * solves.  supply_rhs != 0: the forward substitution is fused into the
+ * factorization for a right-hand side handed over while it runs with
+ * pd_supply_rhs, which must be enqueued on another stream before anything
+ * waits for the factorization (otherwise its waits time out and the
+ * factorization reports PD_ERR_HIP); the following pd_global_solve then only
+ * runs the backward substitution, for that right-hand side (its g argument
+ * is not read).  A no-op when the factor is current.  Non-positive pivots
+ * are reported by a later pd_global_solve with info. */
+pd_status pd_factor(pd_ctx *ctx, int32_t n_workgroups, int32_t supply_rhs);
+
+/* Hands the right-hand side g (dev [3][m]) to a factorization started with
+ * pd_factor(..., supply_rhs != 0); a no-op otherwise.  Enqueued on the
+ * context's current stream (pd_use_stream), which must not wait for the
+ * factorization before this call. */
+pd_status pd_supply_rhs(pd_ctx *ctx, const double *g);
 
 /* Inner update (Alg. 1 steps 4.6-4.7): x2 += u2, delta2 += u2 and
  * ft -= Sigma_alpha u2 with Sigma_alpha = S - A22^(beta).  All dev [3][m]. */

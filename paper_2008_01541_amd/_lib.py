@@ -60,7 +60,8 @@ _SIGS = {
     "pd_region_add_f32": [_P, _P, C.c_double, _P],
     "pd_set_stream": [_P, _P],
     "pd_use_stream": [_P, _P],
-    "pd_factor": [_P, C.c_int32],
+    "pd_factor": [_P, C.c_int32, C.c_int32],
+    "pd_supply_rhs": [_P, _P],
     "pd_set_timing": [_P, C.c_int],
     "pd_get_timings": [_P, _P, _P],
     "pd_destroy": [_P],
@@ -243,9 +244,14 @@ class PDContext:
         self._chk(st)
         return None
 
-    def factor(self, n_workgroups=0):
+    def factor(self, n_workgroups=0, supply_rhs=False):
         """FP64 factorization of H ahead of global_solve (pd_factor)."""
-        self._chk(self._lib.pd_factor(self._ctx, int(n_workgroups)))
+        self._chk(self._lib.pd_factor(self._ctx, int(n_workgroups), 1 if supply_rhs else 0))
+
+    def supply_rhs(self, g):
+        """Right-hand side for a factorization started with supply_rhs=True."""
+        import torch
+        self._chk(self._lib.pd_supply_rhs(self._ctx, _ptr(g, torch.float64, 3 * self.m, "g")))
 
     def inner_update(self, u2, x2, delta2, ft):
         import torch

@@ -104,7 +104,11 @@ struct pd_ctx {
   // sweeps
   double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
   bool have_condense = false;
-  double* d_P = nullptr;              // tile parts of one level's dense product
+  double* d_P = nullptr;              // tile parts of a level's (or S's) dense product
+  int* d_gflag = nullptr;             // right-hand side supplied to a running factorization
+  int g_epoch = 0;                    // last value stored to d_gflag
+  bool deferred = false;              // the current factor awaits / holds a supplied RHS
+  bool rhs_supplied = false;          // pd_supply_rhs was called for it
   // penalties
   int32_t n_pen = 0, pen_cap = 0;
   int32_t* d_pidx = nullptr;
@@ -240,10 +244,11 @@ void free_now(pd_ctx* c, void* p) {
 // In-place lower Cholesky of the n x n matrix A (leading dimension lda, a
 // multiple of 16 so tiles start on 128-byte lines); tile inverses to d_linv,
 // transpose of the factor in the upper triangle.
-void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr, int n_wg = 0) {
+void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr, int n_wg = 0,
+              const int* gflag = nullptr, int gepoch = 0) {
   if (c->chol_dataflow) {
     potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
-                   n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st);
+                   n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, gflag, gepoch);
   } else {
     potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
   }
@@ -715,7 +720,9 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&c->d_v, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_xs, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_tmp, 3 * std::max<int64_t>(1, c->maxw)));
-  CK(c->alloc(&c->d_P, sweep_workspace(c->maxw)));
+  CK(c->alloc(&c->d_P, std::max(sweep_workspace(c->maxw), sweep_workspace(m))));
+  CK(c->alloc(&c->d_gflag, 1));
+  HIPCK(c, hipMemsetAsync(c->d_gflag, 0, sizeof(int), c->st));
   HIPCK(c, hipStreamSynchronize(c->st));
   return PD_OK;
 }
@@ -1005,8 +1012,14 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
     }
     {
       PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
-      if (fused) {
+      if (fused || c->deferred) {
+        // the forward substitution ran inside the factorization (for a
+        // deferred right-hand side: the one given to pd_supply_rhs)
+        if (c->deferred && !c->rhs_supplied)
+          return c->fail(PD_ERR_STATE, "pd_factor(supply_rhs) needs pd_supply_rhs before the solve");
         rhs_unpack(m, c->d_Yt, c->d_y, m, c->st);
+        c->deferred = false;
+        c->rhs_supplied = false;
       } else {
         trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
                       c->d_err, c->st);
@@ -1074,19 +1087,38 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
   return PD_OK;
 }
 
-pd_status pd_factor(pd_ctx* c, int32_t n_workgroups) {
+pd_status pd_factor(pd_ctx* c, int32_t n_workgroups, int32_t supply_rhs) {
   if (bad_ctx(c)) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
   if (!c->stale) return PD_OK;
   build_H(c);
   zero_int(c->d_info, c->st);
+  const bool defer = supply_rhs != 0 && c->chol_dataflow != 0;
   {
     PhaseTimer tm(c, PD_PHASE_FACTOR);
-    cholesky(c, c->d_H, c->ldH, (int)c->m, nullptr, n_workgroups);
+    if (defer) {
+      ++c->g_epoch;
+      cholesky(c, c->d_H, c->ldH, (int)c->m, c->d_Yt, n_workgroups, c->d_gflag, c->g_epoch);
+    } else {
+      cholesky(c, c->d_H, c->ldH, (int)c->m, nullptr, n_workgroups);
+    }
   }
+  c->deferred = defer;
+  c->rhs_supplied = false;
   c->stale = false;
   c->lp_stale = true;             // d_H was rebuilt
   return c->check("pd_factor");
+}
+
+pd_status pd_supply_rhs(pd_ctx* c, const double* g) {
+  if (bad_ctx(c) || !g) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  if (!c->deferred) return PD_OK;
+  PhaseTimer tm(c, PD_PHASE_ASSEMBLE);
+  rhs_pack((int)c->m, g, (int)c->m, c->d_Yt, c->st);
+  set_flag(c->d_gflag, c->g_epoch, c->st);
+  c->rhs_supplied = true;
+  return c->check("pd_supply_rhs");
 }
 
 pd_status pd_inner_update(pd_ctx* c, const double* u2, double* x2, double* delta2, double* ft) {
@@ -1095,7 +1127,8 @@ pd_status pd_inner_update(pd_ctx* c, const double* u2, double* x2, double* delta
   const int m = (int)c->m;
   PhaseTimer tm(c, PD_PHASE_INNER_UPDATE);
   inner_update(m, u2, x2, delta2, c->st);
-  symv3(c->d_S, m, m, u2, m, -1.0, 1.0, ft, m, c->st);
+  sweep_symv(c->d_S, m, m, u2, m, c->d_P, c->st);            // lower tiles of S only
+  sweep_assemble(m, c->d_P, ft, m, ft, m, c->st);            // ft -= S u2
   if (c->nbeta > 0) csr_spmv3(m, c->d_Abptr, c->d_Abcol, c->d_Abval, u2, m, 1.0, ft, m, ft, m, c->st);
   return c->check("pd_inner_update");
 }

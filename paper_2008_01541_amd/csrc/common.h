@@ -22,9 +22,13 @@ void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStrea
 // the epoch on the device (safe under graph replay).  sbuf: nt * NB * NB
 // doubles of workspace (partial sums of the first sub-diagonal tiles).
 // With Yt (64 x n, rows 0..2 = g^T) the forward substitution L^-1 g is fused
-// in (result in the same rows).
+// in (result in the same rows).  With gflag, Yt is filled while the
+// factorization runs: its tasks come after all tiles and wait until *gflag
+// equals gepoch (set with set_flag after Yt is written, e.g. on another stream).
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
-                    unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st);
+                    unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
+                    const int* gflag = nullptr, int gepoch = 0);
+void set_flag(int* f, int v, hipStream_t st);
 void rhs_pack(int n, const double* g, int ldg, double* Yt, hipStream_t st);
 void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st);
 // Fill kernels (used instead of memset so the calls can be graph-captured).

@@ -555,9 +555,11 @@ __device__ inline void stage_tile(double (*T)[LDS_LD], const double* __restrict_
 __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, int n, int nt,
                                                            double* linv_ws, double* sbuf,
                                                            int* flags, unsigned* ticket, int* info,
-                                                           int* err, double* Yt) {
+                                                           int* err, double* Yt, const int* gflag,
+                                                           int gepoch) {
   const int epoch = (int)ticket[1];
   const int rhs = Yt != nullptr ? 1 : 0;
+  const int ntile = nt * (nt + 1) / 2;
   int* sflags = flags + (nt + 1) * nt;
   // two 64 x 68 double tiles (69,632 bytes): operands of the accumulation,
   // then the tile and its inverse / Linv during the finishing step
@@ -575,12 +577,31 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     __syncthreads();
     const int q = s_task;
     if (q >= ntask) return;
-    int j = 0, start = 0;
-    while (start + (nt - j + rhs) <= q) {
-      start += nt - j + rhs;
-      ++j;
+    int i, j;
+    if (gflag) {
+      // right-hand side supplied during the factorization: its row comes
+      // after all tiles, and each of its tasks first waits for it
+      if (q < ntile) {
+        j = 0;
+        int start = 0;
+        while (start + (nt - j) <= q) start += nt - j++;
+        i = j + (q - start);
+      } else {
+        i = nt;
+        j = q - ntile;
+        if (t == 0 && !df_wait(gflag, gepoch, err)) s_ok = 0;
+        __syncthreads();
+        if (!s_ok) return;
+      }
+    } else {
+      j = 0;
+      int start = 0;
+      while (start + (nt - j + rhs) <= q) {
+        start += nt - j + rhs;
+        ++j;
+      }
+      i = j + (q - start);                 // i == nt: the right-hand-side row
     }
-    const int i = j + (q - start);         // i == nt: the right-hand-side row
     const bool rrow = (i == nt);
     const bool diag = (i == j), sub = !rrow && i == j + 1;
     double* Ai = rrow ? Yt : A;
@@ -715,13 +736,20 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 }
 
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
-                    unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st) {
+                    unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
+                    const int* gflag, int gepoch) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = nt * (nt + 1) / 2 + (Yt ? nt : 0);
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
   k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, sbuf, flags,
-                                                          ticket, info, err, Yt);
+                                                          ticket, info, err, Yt,
+                                                          Yt ? gflag : nullptr, gepoch);
 }
+
+__global__ void k_set_flag(int* f, int v) {
+  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+void set_flag(int* f, int v, hipStream_t st) { k_set_flag<<<1, 1, 0, st>>>(f, v); }
 
 // Yt[v + r * 64] = g[v * ldg + r] (v < 3) and back.
 __global__ void k_rhs_pack(int n, const double* __restrict__ g, int ldg, double* __restrict__ Yt) {

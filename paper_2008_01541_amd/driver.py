@@ -97,20 +97,26 @@ class Alg1Runner:
         c.backsub(self.delta2, self.x)
         return infos
 
-    def run_pipelined(self, n_iters, spheres_of=None, n_workgroups=0, factor_stream=None):
+    def run_pipelined(self, n_iters, spheres_of=None, n_workgroups=0, factor_stream=None,
+                      fuse_forward=False):
         """n_iters outer iterations with one inner iteration each, pipelined
         over two streams.  The factorization side of iteration k (detection,
         penalties, region local step, H = S + W^T C W and its Cholesky factor)
         needs only the region positions after the inner update of iteration
         k - 1, so it runs on a second stream while the back substitution of
         k - 1, the full local step and the condensation of k run on the context
-        stream; the triangular solves and the inner update join both.  The
-        arithmetic is that of outer_iteration(n_inner=1) except that the
-        forward substitution is not fused into the factorization, and that the
-        region positions are carried over from the inner update instead of
-        being gathered from x after the back substitution (the same values:
-        delta2 holds the single update).  spheres_of(k) gives the obstacle
-        spheres of iteration k (None keeps the current ones)."""
+        stream.  With fuse_forward the right-hand side, once assembled, is
+        handed to the running factorization (pd_supply_rhs), which then also
+        does the forward substitution (its tasks follow all tiles, so this only
+        pays off when the right-hand side arrives early); otherwise both
+        triangular solves follow the factorization.  The solves and the inner
+        update join both streams.  The arithmetic is that of
+        outer_iteration(n_inner=1) (without fuse_forward the forward
+        substitution is a separate solve), except that the region positions
+        are carried over from the inner update instead of being gathered from
+        x after the back substitution (the same values: delta2 holds the
+        single update).  spheres_of(k) gives the obstacle spheres of
+        iteration k (None keeps the current ones)."""
         torch = self.torch
         c = self.ctx
         s_main = c.stream
@@ -127,7 +133,9 @@ class Alg1Runner:
             self.detect()
             c.collision_update(self.idx, self.w, self.c, self.t, self.x2, self.fcol)
             c.local_step_region(self.x2, self.fb)
-            c.factor(n_workgroups)
+            ev_pen = torch.cuda.Event()          # penalties and f_beta ready
+            ev_pen.record(s_fac)
+            c.factor(n_workgroups, supply_rhs=fuse_forward)
             ev_fac = torch.cuda.Event()
             ev_fac.record(s_fac)
             # sweep side: finish iteration k - 1, start iteration k
@@ -138,8 +146,11 @@ class Alg1Runner:
             c.condense_rhs(self.f, self.ft)
             with torch.cuda.stream(s_main):
                 self.delta2.zero_()
-            s_main.wait_event(ev_fac)
+            s_main.wait_event(ev_pen)
             c.assemble_rhs(self.ft, self.fb, self.fcol, self.g)
+            if fuse_forward:
+                c.supply_rhs(self.g)
+            s_main.wait_event(ev_fac)
             c.global_solve(self.g, self.u)
             c.inner_update(self.u, self.x2, self.delta2, self.ft)
             ev_upd = torch.cuda.Event()

@@ -151,8 +151,9 @@ def test_alg1_iterations_match_oracle(torch_cuda, name, inner):
     assert worst <= 1e-9
 
 
-@pytest.mark.parametrize("name,n_wg", [("g9x7x6", 0), ("g16x15x8", 64)])
-def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg):
+@pytest.mark.parametrize("name,n_wg,fuse", [("g9x7x6", 0, True), ("g16x15x8", 64, False),
+                                             ("g16x15x8", 64, True)])
+def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg, fuse):
     """Two-stream pipelined iterations (the factorization of iteration k
     overlapping the back substitution of k - 1 and the condensation of k)
     against the oracle's sequential Alg. 1 with one inner iteration."""
@@ -166,7 +167,8 @@ def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg):
         run.set_spheres(sc.spheres.centers(f), sc.spheres.radii)
         sph[f] = run.spheres
     torch_cuda.cuda.synchronize()
-    run.run_pipelined(len(frames), spheres_of=lambda k: sph[frames[k]], n_workgroups=n_wg)
+    run.run_pipelined(len(frames), spheres_of=lambda k: sph[frames[k]], n_workgroups=n_wg,
+                      fuse_forward=fuse)
     x_or = sc.rest.copy()
     for f in frames:
         det = opd.sphere_detector(om, sc.proxy_local(), sc.spheres.centers(f), sc.spheres.radii,

@@ -79,3 +79,33 @@ def test_dataflow_indices_in_bounds(n, rhs):
             kmax = kend * NB - 1
             assert (r0 + mr - 1) + kmax * ldai < size_i
             assert (c0 + mc - 1) + kmax * lda < a_size
+
+
+def task_of_ticket_supplied_rhs(q, nt):
+    """Ticket order when the right-hand side arrives during the factorization:
+    all tiles column by column, then the right-hand-side row."""
+    ntile = nt * (nt + 1) // 2
+    if q < ntile:
+        j, start = 0, 0
+        while start + (nt - j) <= q:
+            start += nt - j
+            j += 1
+        return j + (q - start), j
+    return nt, q - ntile
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3, 7, 51, 102])
+def test_supplied_rhs_ticket_order(nt):
+    tasks = [task_of_ticket_supplied_rhs(q, nt) for q in range(nt * (nt + 1) // 2 + nt)]
+    assert sorted(tasks) == sorted(dataflow_tasks(nt, 1))
+    # every dependency of a task has a smaller ticket: tiles (i, k), (j, k) for
+    # k < j, Linv_j, the first sub-diagonal partial sum, and Y_k (k < j) for the RHS row
+    pos = {t: q for q, t in enumerate(tasks)}
+    for (i, j), q in pos.items():
+        deps = [(j, j)] if i != j else []
+        deps += [(i, k) for k in range(j)] + [(j, k) for k in range(j)]
+        if i == j and j > 0:
+            deps.append((j, j - 1))
+        for d in deps:
+            if d in pos and d != (i, j):
+                assert pos[d] < q, ((i, j), d)
