@@ -104,11 +104,9 @@ __device__ void gemm_acc(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
 // ---------------------------------------------------------------------------
 // Cholesky building blocks
 
-// DPP row broadcasts (row_newbcast: every lane of a row of 16 lanes reads lane
-// S of that row).  Written as volatile asm so that they stay in program order
-// and their results are consumed at once (the compiler otherwise hoists all of
-// them and spills); s_nop 1 covers the two wait states a DPP read needs after
-// a VALU write of its source.
+// DPP row broadcast (row_newbcast: every lane of a row of 16 lanes reads lane
+// S of that row), as volatile asm; s_nop 1 covers the two wait states a DPP
+// read needs after a VALU write of its source.
 template <int S>
 __device__ __forceinline__ double row_bcast(double v) {
   double o;
@@ -117,13 +115,9 @@ __device__ __forceinline__ double row_bcast(double v) {
                : "v"(v), "i"(S));
   return o;
 }
-// acc -= v(lane S of the row) * m
-template <int S>
-__device__ __forceinline__ void fnma_row_bcast(double& acc, double v, double m) {
-  asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-               : "+v"(acc)
-               : "v"(v), "v"(m), "i"(S));
-}
+// Per-step update blocks of the 16 x 16 diagonal-block Cholesky:
+// chol16_a_updates<C>(a) -> next pivot, chol16_x_updates<C>(a, x).
+#include "chol16_steps.inc"
 
 // 1/sqrt(d): hardware estimate refined by two Newton steps y <- y (3 - d y^2) / 2.
 __device__ __forceinline__ double rsqrt_newton(double d) {
@@ -139,22 +133,9 @@ __device__ __forceinline__ double rsqrt_newton(double d) {
 // Right-looking elimination of one 16 x 16 block, one pivot per step C: lane
 // r (mod 16) holds row r of the block in a[] and column r of the inverse in
 // x[] (initially the identity); the multipliers L(S, C) are broadcast along
-// each row of 16 lanes.  The pivot of step C + 1 is broadcast as soon as its
-// own update is done, so that its square root overlaps the rest of step C.
-template <int C, int S>
-__device__ __forceinline__ void chol16_update(double (&a)[16]) {
-  if constexpr (S < 16) {
-    fnma_row_bcast<S>(a[S], a[C], a[C]);
-    chol16_update<C, S + 1>(a);
-  }
-}
-template <int C, int S>
-__device__ __forceinline__ void inv16_update(const double (&a)[16], double (&x)[16]) {
-  if constexpr (S < 16) {
-    fnma_row_bcast<S>(x[S], a[C], x[C]);
-    inv16_update<C, S + 1>(a, x);
-  }
-}
+// each row of 16 lanes (one asm block of DPP operands per step and array).
+// The pivot of step C + 1 is broadcast as soon as its own update is done, so
+// that its square root can overlap the rest of step C.
 template <int C>
 __device__ __forceinline__ void chol16_step(double (&a)[16], double (&x)[16], double d, int r,
                                             int& bad) {
@@ -169,11 +150,9 @@ __device__ __forceinline__ void chol16_step(double (&a)[16], double (&x)[16], do
     x[C] *= y;
     double dn = 0.0;
     if constexpr (C + 1 < 16) {
-      fnma_row_bcast<C + 1>(a[C + 1], a[C], a[C]);
-      dn = row_bcast<C + 1>(a[C + 1]);
-      chol16_update<C, C + 2>(a);
+      dn = chol16_a_updates<C>(a);
+      chol16_x_updates<C>(a, x);
     }
-    inv16_update<C, C + 1>(a, x);
     chol16_step<C + 1>(a, x, dn, r, bad);
   }
 }
