@@ -85,6 +85,7 @@ struct pd_ctx {
   unsigned long long* d_ticket = nullptr;
   int* d_flags = nullptr;
   int* d_tflags = nullptr;            // tile-ready flags of the dataflow Cholesky
+  int* d_cumarks = nullptr;           // per-compute-unit marks of the dataflow Cholesky
   unsigned* d_tticket = nullptr;
   int chol_epoch = 0;
   int chol_dataflow = 1;              // 1: single-launch dataflow, 0: three launches per step
@@ -248,7 +249,8 @@ void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr, int n_
               const int* gflag = nullptr, int gepoch = 0) {
   if (c->chol_dataflow) {
     potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
-                   n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, gflag, gepoch);
+                   n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, gflag, gepoch,
+                   c->d_cumarks);
   } else {
     potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
   }
@@ -610,7 +612,9 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     const int64_t nt2 = ntmax * (ntmax + 2);
     CK(c->alloc(&c->d_tflags, nt2));
     CK(c->alloc(&c->d_tticket, 4));
+    CK(c->alloc(&c->d_cumarks, potrf_cu_slots()));
     HIPCK(c, hipMemsetAsync(c->d_tflags, 0, nt2 * sizeof(int), c->st));
+    HIPCK(c, hipMemsetAsync(c->d_cumarks, 0, potrf_cu_slots() * sizeof(int), c->st));
     HIPCK(c, hipMemsetAsync(c->d_tticket, 0, 4 * sizeof(unsigned), c->st));
     const char* mode = getenv("PDSCHUR_CHOL");
     if (mode && strcmp(mode, "tiled") == 0) c->chol_dataflow = 0;

@@ -25,9 +25,12 @@ void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStrea
 // in (result in the same rows).  With gflag, Yt is filled while the
 // factorization runs: its tasks come after all tiles and wait until *gflag
 // equals gepoch (set with set_flag after Yt is written, e.g. on another stream).
+// cu_marks (optional): potrf_cu_slots() zero-initialised ints, the per-unit
+// marks by which tasks off the critical path yield to a diagonal task.
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
                     unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
-                    const int* gflag = nullptr, int gepoch = 0);
+                    const int* gflag = nullptr, int gepoch = 0, int* cu_marks = nullptr);
+int potrf_cu_slots();
 void set_flag(int* f, int v, hipStream_t st);
 void rhs_pack(int n, const double* g, int ldg, double* Yt, hipStream_t st);
 void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st);

@@ -6,11 +6,11 @@
 #include <algorithm>
 #include <climits>
 #include "common.h"
+#include "tile_factor_f64.h"
 
 namespace pdk {
 
 constexpr int KC = 16;           // K-chunk staged through LDS per step
-constexpr int LDS_LD = NB + 4;   // padded LDS row (doubles)
 
 __device__ inline double coherent_load(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -98,171 +98,6 @@ __device__ void gemm_acc(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
       acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
       acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
     }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Cholesky building blocks
-
-// DPP row broadcast (row_newbcast: every lane of a row of 16 lanes reads lane
-// S of that row), as volatile asm; s_nop 1 covers the two wait states a DPP
-// read needs after a VALU write of its source.
-template <int S>
-__device__ __forceinline__ double row_bcast(double v) {
-  double o;
-  asm volatile("s_nop 1\n\tv_mov_b64_dpp %0, %1 row_newbcast:%2 row_mask:0xf bank_mask:0xf"
-               : "=v"(o)
-               : "v"(v), "i"(S));
-  return o;
-}
-// Per-step update blocks of the 16 x 16 diagonal-block Cholesky:
-// chol16_a_updates<C>(a) -> next pivot, chol16_x_updates<C>(a, x).
-#include "chol16_steps.inc"
-
-// 1/sqrt(d): hardware estimate refined by two Newton steps y <- y (3 - d y^2) / 2.
-__device__ __forceinline__ double rsqrt_newton(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const double r = fma(-0.5 * d * y, y, 0.5);
-    y = fma(y, r, y);
-  }
-  return y;
-}
-
-// Right-looking elimination of one 16 x 16 block, one pivot per step C: lane
-// r (mod 16) holds row r of the block in a[] and column r of the inverse in
-// x[] (initially the identity); the multipliers L(S, C) are broadcast along
-// each row of 16 lanes (one asm block of DPP operands per step and array).
-// The pivot of step C + 1 is broadcast as soon as its own update is done, so
-// that its square root can overlap the rest of step C.
-template <int C>
-__device__ __forceinline__ void chol16_step(double (&a)[16], double (&x)[16], double d, int r,
-                                            int& bad) {
-  if constexpr (C < 16) {
-    const bool ok = d > 0.0;
-    bad = (!ok && bad == 0) ? C + 1 : bad;
-    d = ok ? d : 1.0;
-    const double y = rsqrt_newton(d);
-    // column C of L: d y on the diagonal, a y below, 0 above (branch-free)
-    const double sc = (r > C) ? y : 0.0;
-    a[C] = fma(a[C], sc, (r == C) ? d * y : 0.0);
-    x[C] *= y;
-    double dn = 0.0;
-    if constexpr (C + 1 < 16) {
-      dn = chol16_a_updates<C>(a);
-      chol16_x_updates<C>(a, x);
-    }
-    chol16_step<C + 1>(a, x, dn, r, bad);
-  }
-}
-
-// Cholesky factor and inverse of the 16 x 16 diagonal block at (b0, b0) of the
-// LDS tile T, by one wave (the four rows of 16 lanes work redundantly).  L
-// replaces the lower part of the block (zeros above), its inverse goes to the
-// same block of X (zeros above).  The first non-positive pivot j of the block
-// (inside the first mr rows) is reported in *info as gbase + b0 + j + 1 and
-// replaced by 1.
-__device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[LDS_LD], int b0,
-                                               int mr, int gbase, int* info) {
-  const int lane = threadIdx.x & 63, r = lane & 15;
-  double a[16], x[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    a[c] = T[b0 + c][b0 + r];
-    x[c] = (c == r) ? 1.0 : 0.0;
-  }
-  int bad = 0;          // first non-positive pivot of the block, 1-based; 0: none
-  chol16_step<0>(a, x, row_bcast<0>(a[0]), r, bad);
-  if (lane == 0 && bad > 0 && b0 + bad - 1 < mr) atomicCAS(info, 0, gbase + b0 + bad);
-  if (lane < 16) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) T[b0 + c][b0 + r] = a[c];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) X[b0 + r][b0 + i] = x[i];
-  }
-}
-
-// C(m, n) += sum_k A(m, k) B(n, k) over one 16-deep block, m, n, k < 16, for
-// operands in LDS tiles (Ts[c][r] = tile(r, c)): A(m, k) = As[ak + k][am + m],
-// B(n, k) = Bs[bk + k][bn + n] (BT = false) or Bs[bn + n][bk + k] (BT = true).
-// Result: lane l, register q holds C(l % 16, l / 16 + 4 q).
-template <bool BT>
-__device__ inline void mma16(double4_t& acc, double (*As)[LDS_LD], int am, int ak,
-                             double (*Bs)[LDS_LD], int bn, int bk) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int k = 4 * s + (lane >> 4);
-    const double av = As[ak + k][am + (lane & 15)];
-    const double bv = BT ? Bs[bn + (lane & 15)][bk + k] : Bs[bk + k][bn + (lane & 15)];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv, av, acc, 0, 0, 0);
-  }
-}
-
-// Cholesky of a 64 x 64 tile held in LDS (T[c][r] = tile(r, c), lower part
-// valid, rows/cols >= mr padded with the identity) and the inverse of the
-// factor into X (X[c][r] = inverse(r, c), zero above the diagonal).  Right-
-// looking over 16-wide block columns: wave 0 factors and inverts the diagonal
-// block, the panel below becomes P Dinv^T and the trailing blocks are updated
-// on the matrix cores; the off-diagonal blocks of the inverse follow from
-// X_ij = -X_ii sum_{p=j}^{i-1} L_ip X_pj.  A non-positive pivot stores its
-// 1-based global index gbase + j + 1 in *info (first one wins) and is replaced
-// by 1 so that the factorization stays finite.  Only the lower triangle of T
-// is meaningful on return.
-__device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
-                                    int* info) {
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  // zero the six strictly upper 16 x 16 blocks of X: X[16 jb + c][16 ib + r], ib < jb
-  for (int e = t; e < 6 * 256; e += 256) {
-    const int blk = e >> 8, r = e & 15, c = (e >> 4) & 15;
-    const int ib = blk < 3 ? 0 : (blk < 5 ? 1 : 2);
-    const int jb = blk < 3 ? blk + 1 : (blk < 5 ? blk - 1 : 3);
-    X[16 * jb + c][16 * ib + r] = 0.0;
-  }
-  if (w == 0) chol16_inverse(T, X, 0, mr, gbase, info);
-  __syncthreads();
-  for (int kb = 0; kb < 3; ++kb) {
-    const int b0 = 16 * kb;
-    // panel: block row ib = kb + 1 + w becomes P Dinv^T
-    if (kb + 1 + w <= 3) {
-      const int ib = kb + 1 + w;
-      double4_t acc = {0.0, 0.0, 0.0, 0.0};
-      mma16<false>(acc, T, 16 * ib, b0, X, b0, b0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) T[b0 + (lane >> 4) + 4 * q][16 * ib + (lane & 15)] = acc[q];
-    }
-    __syncthreads();
-    // trailing blocks (ib, jb), kb < jb <= ib <= 3; wave 0 takes the next
-    // diagonal block and goes straight on to factor it
-    const int R = 3 - kb, nblk = R * (R + 1) / 2;
-    for (int bi = (w == 0 ? 0 : w); bi < nblk; bi += (w == 0 ? nblk : 3)) {
-      int jb = kb + 1, rem = bi;
-      while (rem >= 4 - jb) { rem -= 4 - jb; ++jb; }
-      const int ib = jb + rem;
-      double4_t acc = {0.0, 0.0, 0.0, 0.0};
-      mma16<false>(acc, T, 16 * ib, b0, T, 16 * jb, b0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) T[16 * jb + (lane >> 4) + 4 * q][16 * ib + (lane & 15)] -= acc[q];
-    }
-    if (w == 0) chol16_inverse(T, X, b0 + 16, mr, gbase, info);
-    __syncthreads();
-  }
-  // off-diagonal blocks of the inverse, block row by block row
-  for (int i = 1; i < 4; ++i) {
-    if (w < i) {
-      const int j = w;
-      double4_t acc = {0.0, 0.0, 0.0, 0.0};
-      for (int p = j; p < i; ++p) mma16<true>(acc, T, 16 * i, 16 * p, X, 16 * j, 16 * p);
-      // stage Y = sum_p L_ip X_pj in the X_ij slot, then X_ij = -X_ii Y
-#pragma unroll
-      for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = acc[q];
-      double4_t acc2 = {0.0, 0.0, 0.0, 0.0};
-      mma16<true>(acc2, X, 16 * i, 16 * i, X, 16 * j, 16 * i);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = -acc2[q];
-    }
-    __syncthreads();
   }
 }
 
@@ -407,7 +242,7 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
                               const double* __restrict__ Ar, int ldar, int r0, int mr,
                               const double* __restrict__ A, int lda, int c0,
                               int mc, int i, int j, int kend, int nt, const int* flags, int epoch,
-                              int* err, int* s_ok) {
+                              int* err, int* s_ok, const int* mark) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int r = t & 63, kq = t >> 6;
@@ -427,6 +262,7 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
     }
   };
   int fi = 0, fj = 0;          // thread 0: flags of the next step, read ahead
+  int fm = 0;                  // thread 0: this unit's courtesy mark (mark != NULL)
   if (t == 0) {
     if (!df_wait(&flags[i * nt], epoch, err) || !df_wait(&flags[j * nt], epoch, err)) *s_ok = 0;
   }
@@ -445,6 +281,7 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
       Bs[kq + 4 * q][r] = rb[q];
     }
     const bool nxt = k + 1 < kend;
+    if (t == 0 && fm == epoch) cu_pause(mark, epoch);
     if (t == 0 && nxt && (fi != epoch || fj != epoch)) {
       if (!df_wait(&flags[i * nt + k + 1], epoch, err) ||
           !df_wait(&flags[j * nt + k + 1], epoch, err))
@@ -458,6 +295,7 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
         fi = __hip_atomic_load(&flags[i * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         fj = __hip_atomic_load(&flags[j * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      if (t == 0 && mark) fm = __hip_atomic_load(mark, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
     for (int ks = 0; ks < NB / 4; ++ks) {
@@ -535,10 +373,11 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
                                                            double* linv_ws, double* sbuf,
                                                            int* flags, unsigned* ticket, int* info,
                                                            int* err, double* Yt, const int* gflag,
-                                                           int gepoch) {
+                                                           int gepoch, int* cu_marks) {
   const int epoch = (int)ticket[1];
   const int rhs = Yt != nullptr ? 1 : 0;
   const int ntile = nt * (nt + 1) / 2;
+  int* const mark = cu_marks ? cu_marks + cu_slot() : nullptr;
   int* sflags = flags + (nt + 1) * nt;
   // two 64 x 68 double tiles (69,632 bytes): operands of the accumulation,
   // then the tile and its inverse / Linv during the finishing step
@@ -607,8 +446,12 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
         }
     const int kend = diag ? max(j - 1, 0) : j;
     if (!df_accumulate(acc, buf0, buf1, Ai, ldai, r0, mr, A, lda, c0, mc, i, j, kend, nt, flags,
-                       epoch, err, &s_ok))
+                       epoch, err, &s_ok, critical ? nullptr : mark))
       return;
+    // the diagonal task's local phase: no waits from here to the inverse's flag
+    const auto mark_unit = [&]() {
+      if (t == 0 && mark) __hip_atomic_store(mark, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
     if (sub) {
       double* Sb = sbuf + (long)i * NB * NB;
 #pragma unroll
@@ -641,6 +484,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
         s_ok = 0;
       __syncthreads();
       if (!s_ok) return;
+      mark_unit();
       stage_tile(buf1, linv_ws + (long)(j - 1) * NB * NB);   // buf1[kk][c] = Linv(c, kk)
       {
         const double* Sb = sbuf + (long)j * NB * NB;
@@ -673,11 +517,16 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     acc_to_lds(acc, buf0, -1.0);                   // C = A_ij - sum_k L_ik L_jk^T
     __syncthreads();
     if (diag) {
+      if (j == 0) mark_unit();
       factor_tile_blocked(buf0, buf1, mr, r0, info);
       // only the inverse is read inside this launch: publish it first, then
       // write L (lower) and its transposed copy (strictly upper) for the solves
       double* Li = linv_ws + (long)j * NB * NB;
       for (int e = t; e < NB * NB; e += 256) coherent_store(&Li[e], buf1[e >> 6][e & 63]);
+      // the mark is cleared before the flag is stored (publish_flag waits for
+      // both), so the next diagonal task, which may run on this unit, sets its
+      // own mark after this clear
+      if (t == 0 && mark) __hip_atomic_store(mark, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       publish_flag(&flags[i * nt + j], epoch);
       for (int e = t; e < NB * NB; e += 256) {
         const int r = e & 63, c = e >> 6;
@@ -716,19 +565,20 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
                     unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
-                    const int* gflag, int gepoch) {
+                    const int* gflag, int gepoch, int* cu_marks) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = nt * (nt + 1) / 2 + (Yt ? nt : 0);
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
   k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, sbuf, flags,
                                                           ticket, info, err, Yt,
-                                                          Yt ? gflag : nullptr, gepoch);
+                                                          Yt ? gflag : nullptr, gepoch, cu_marks);
 }
 
 __global__ void k_set_flag(int* f, int v) {
   __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 void set_flag(int* f, int v, hipStream_t st) { k_set_flag<<<1, 1, 0, st>>>(f, v); }
+int potrf_cu_slots() { return CU_SLOTS; }
 
 // Yt[v + r * 64] = g[v * ldg + r] (v < 3) and back.
 __global__ void k_rhs_pack(int n, const double* __restrict__ g, int ldg, double* __restrict__ Yt) {
