@@ -93,8 +93,8 @@ struct pd_ctx {
   // low-precision factor for the refined solves
   float* d_H32 = nullptr;
   float* d_linv32 = nullptr;
-  float* d_y32 = nullptr;
-  float* d_xs32 = nullptr;
+  double* d_lpb = nullptr;            // workspaces of the float-factor solves (3 m each)
+  double* d_lpy = nullptr;
   double* d_dvec = nullptr;
   unsigned long long* d_lp_ticket = nullptr;
   int* d_lp_flags = nullptr;
@@ -983,8 +983,8 @@ pd_status ensure_lp_buffers(pd_ctx* c) {
   const int64_t m = c->m;
   CK(c->alloc(&c->d_H32, (int64_t)c->ldH32 * m));
   CK(c->alloc(&c->d_linv32, (int64_t)c->ntm * NB * NB));
-  CK(c->alloc(&c->d_y32, 3 * m));
-  CK(c->alloc(&c->d_xs32, 3 * m));
+  CK(c->alloc(&c->d_lpb, 3 * m));
+  CK(c->alloc(&c->d_lpy, 3 * m));
   CK(c->alloc(&c->d_dvec, m));
   CK(c->alloc(&c->d_lp_ticket, 2));
   CK(c->alloc(&c->d_lp_flags, 2 * (int64_t)c->ntm));
@@ -1056,20 +1056,21 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
     zero_int(c->d_info, c->st);
     PhaseTimer tm(c, PD_PHASE_FACTOR);
     equilibrate_convert(c->d_H, c->ldH, m, c->d_dvec, c->d_H32, c->ldH32, c->st);
-    potrf_dataflow_lp(c->d_H32, c->ldH32, m, c->d_linv32, c->d_tflags, c->d_tticket, c->d_info,
-                      c->d_err, c->n_wg, prec == PD_BF16_IR, c->st);
+    potrf_dataflow_lp(c->d_H32, c->ldH32, m, c->d_linv32, reinterpret_cast<float*>(c->d_sbuf),
+                      c->d_tflags, c->d_tticket, c->d_info, c->d_err, c->n_wg, prec == PD_BF16_IR,
+                      c->st, c->d_cumarks);
     c->lp_stale = false;
     c->lp_prec = (int)prec;
   }
   PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
-  trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, g, c->d_y32, c->d_xs32, u, 0,
+  trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, g, c->d_lpb, c->d_lpy, u, 0,
                  c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
   CK(c->check("pd_global_solve"));
   double rr = 0.0;
   int it = 0;
   CK(residual(c, g, u, &rr));
   while (!(rr <= c->ir_tol) && it < c->max_ir) {
-    trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, c->d_res, c->d_y32, c->d_xs32,
+    trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, c->d_res, c->d_lpb, c->d_lpy,
                    u, 1, c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
     ++it;
     CK(residual(c, g, u, &rr));

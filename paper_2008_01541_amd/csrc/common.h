@@ -48,18 +48,28 @@ void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const 
 void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
                     int ldy, double* x, int ldx, unsigned long long* ticket, int* flags,
                     int* err, hipStream_t st);
+// the same solves with a float factor (FP64 vectors and arithmetic)
+void trsv3_forward(const float* L, int ld, int n, const float* linv_ws, const double* g, int ldg,
+                   double* y, int ldy, unsigned long long* ticket, int* flags, int* err,
+                   hipStream_t st);
+void trsv3_backward(const float* L, int ld, int n, const float* linv_ws, const double* y, int ldy,
+                    double* x, int ldx, unsigned long long* ticket, int* flags, int* err,
+                    hipStream_t st);
 // y = alpha * A v + beta * y for symmetric A (full storage), 3 right-hand sides.
 void symv3(const double* A, int lda, int n, const double* v, int ldv, double alpha,
            double beta, double* y, int ldy, hipStream_t st);
 
-// low precision (FP32 / BF16-operand) factor of the equilibrated system
-void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, int* flags, unsigned* ticket,
-                       int* info, int* err, int n_wg, bool bf16, hipStream_t st);
+// low precision (FP32 / BF16-operand) factor of the equilibrated system, on
+// the schedule of potrf_dataflow (same flags layout; sbuf: nt * NB * NB floats)
+void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, float* sbuf, int* flags,
+                       unsigned* ticket, int* info, int* err, int n_wg, bool bf16, hipStream_t st,
+                       int* cu_marks = nullptr);
 void equilibrate_convert(const double* H, int ld, int n, double* d, float* H32, int ld32,
                          hipStream_t st);
-// x (+)= D L^-T L^-1 D r with L the FP32 factor of D H D (three right-hand sides).
+// x (+)= D L^-T L^-1 D r with L the FP32 factor of D H D (three right-hand
+// sides); b, y: 3 n doubles of workspace; flags: 2 nt ints, tickets[2].
 void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const double* d,
-                    const double* r, float* y, float* xs, double* x, int accumulate,
+                    const double* r, double* b, double* y, double* x, int accumulate,
                     unsigned long long* tickets, int* flags, int* err, hipStream_t st);
 
 // condensation sweeps, one interior level at a time: sweep_symv writes the

@@ -819,8 +819,9 @@ __device__ inline void trsv_reduce(double (*part)[3][NB], const double* base, in
 }
 
 // L y = g.  Tile row i: y_i = Linv_ii (g_i - sum_{p<i} L_ip y_p).
-__global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L, int ld, int n,
-                                                   int nt, const double* __restrict__ linv,
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int ld, int n,
+                                                   int nt, const T* __restrict__ linv,
                                                    const double* __restrict__ g, int ldg,
                                                    double* y, int ldy,
                                                    unsigned long long* ticket, int* flags,
@@ -843,28 +844,45 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L,
   const int r = t & 63, cg = t >> 6;
   const int i0 = TR * sr, nu = min(TR, nt - i0);
   for (int u = 0; u < nu; ++u) {
-    const double* Li = linv + (long)(i0 + u) * NB * NB;
+    const T* Li = linv + (long)(i0 + u) * NB * NB;
     double v16[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v16[q] = Li[t + 256 * q];
 #pragma unroll
     for (int q = 0; q < 16; ++q) Ls[u][(t >> 6) + 4 * q][t & 63] = v16[q];
   }
+  // the coupling tile L_{i0+1, i0} (this thread's row and 16 columns), read
+  // now so that its latency is off the path when the super-row finishes
+  static_assert(TR == 2, "the coupling prefetch assumes two tile rows per super-row");
+  T lc[16];
+  {
+    const int r1 = (i0 + 1) * NB + r;
+    const bool ok = nu > 1 && r1 < n;
+    const T* Lr = ok ? L + r1 + (long)(i0 * NB + cg * 16) * ld : L;
+    const long cs = ok ? (long)ld : 0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) lc[c] = Lr[c * cs] * (ok ? T(1) : T(0));
+  }
   double acc[TR][3];
 #pragma unroll
   for (int u = 0; u < TR; ++u) acc[u][0] = acc[u][1] = acc[u][2] = 0.0;
   for (int q = 0; q < sr; ++q) {
     // the four operand tiles L_{i_u, TR q + u'} (16 columns each) load while the flag is awaited
-    double lv[TR][TR][16];
+    // unconditional loads from a clamped row, then a select: no branch per
+    // load, so all of them are in flight together
+    T lv[TR][TR][16];
 #pragma unroll
     for (int u = 0; u < TR; ++u) {
       const int ru = (i0 + u) * NB + r;
+      const bool ok = u < nu && ru < n;
+      const T* Lr = L + (ok ? ru : 0) + (long)(TR * q * NB + cg * 16) * ld;
 #pragma unroll
       for (int w = 0; w < TR; ++w)
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
-          lv[u][w][c] = (u < nu && ru < n) ? L[(long)ru + (long)((TR * q + w) * NB + cg * 16 + c) * ld]
-                                           : 0.0;
+        for (int c = 0; c < 16; ++c) {
+          const T v = Lr[(long)(w * NB + c) * ld];
+          lv[u][w][c] = ok ? v : T(0);
+        }
     }
     if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
     __syncthreads();
@@ -881,25 +899,24 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L,
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int col = w * NB + cg * 16 + c;
-          acc[u][0] += lv[u][w][c] * ys[0][col];
-          acc[u][1] += lv[u][w][c] * ys[1][col];
-          acc[u][2] += lv[u][w][c] * ys[2][col];
+          acc[u][0] += (double)lv[u][w][c] * ys[0][col];
+          acc[u][1] += (double)lv[u][w][c] * ys[1][col];
+          acc[u][2] += (double)lv[u][w][c] * ys[2][col];
         }
     __syncthreads();
   }
   // finish the tile rows of this super-row in order
   for (int u = 0; u < nu; ++u) {
     const int i = i0 + u, r0 = i * NB, mr = min(NB, n - r0);
-    if (u > 0) {           // coupling to the rows finished above in this super-row
-      for (int w = 0; w < u; ++w)
+    if (u > 0) {           // coupling to the row finished above in this super-row
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const int col = cg * 16 + c;
-          const double l = (r < mr) ? L[(long)(r0 + r) + (long)((i0 + w) * NB + col) * ld] : 0.0;
-          acc[u][0] += l * ys[0][w * NB + col];
-          acc[u][1] += l * ys[1][w * NB + col];
-          acc[u][2] += l * ys[2][w * NB + col];
-        }
+      for (int c = 0; c < 16; ++c) {
+        const int col = cg * 16 + c;
+        const double l = (double)lc[c];
+        acc[u][0] += l * ys[0][col];
+        acc[u][1] += l * ys[1][col];
+        acc[u][2] += l * ys[2][col];
+      }
     }
     part[cg][0][r] = acc[u][0];
     part[cg][1][r] = acc[u][1];
@@ -936,8 +953,9 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const double* __restrict__ L,
 
 // L^T x = y, reading L^T from the upper triangle (U(r, c) = L(c, r) for c > r):
 // x_i = Linv_ii^T (y_i - sum_{p>i} U_ip x_p).  Super-rows from the bottom.
-__global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L, int ld, int n,
-                                                   int nt, const double* __restrict__ linv,
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsv3_bwd(const T* __restrict__ L, int ld, int n,
+                                                   int nt, const T* __restrict__ linv,
                                                    const double* __restrict__ y, int ldy,
                                                    double* x, int ldx,
                                                    unsigned long long* ticket, int* flags,
@@ -960,27 +978,45 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L,
   const int r = t & 63, cg = t >> 6;
   const int i0 = TR * sr, nu = min(TR, nt - i0);
   for (int u = 0; u < nu; ++u) {
-    const double* Li = linv + (long)(i0 + u) * NB * NB;
+    const T* Li = linv + (long)(i0 + u) * NB * NB;
     double v16[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v16[q] = Li[t + 256 * q];
 #pragma unroll
     for (int q = 0; q < 16; ++q) Ls[u][(t >> 6) + 4 * q][t & 63] = v16[q];
   }
+  // the coupling tile U_{i0, i0+1} (this thread's row of tile row i0, 16
+  // columns of tile i0 + 1), read now so that its latency is off the path
+  static_assert(TR == 2, "the coupling prefetch assumes two tile rows per super-row");
+  T lc[16];
+  {
+    const int wn = nu > 1 ? min(NB, n - (i0 + 1) * NB) : 0;
+    const int rr0 = i0 * NB + r;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int col = cg * 16 + c;
+      const bool ok = col < wn;
+      const T* p = ok ? L + rr0 + (long)((i0 + 1) * NB + col) * ld : L;
+      lc[c] = *p * (ok ? T(1) : T(0));
+    }
+  }
   double acc[TR][3];
 #pragma unroll
   for (int u = 0; u < TR; ++u) acc[u][0] = acc[u][1] = acc[u][2] = 0.0;
   for (int q = ns - 1; q > sr; --q) {
-    double lv[TR][TR][16];
+    T lv[TR][TR][16];
 #pragma unroll
     for (int u = 0; u < TR; ++u) {
       const int ru = (i0 + u) * NB + r;
+      const bool okr = u < nu && ru < n;
+      const T* Lr = L + (okr ? ru : 0);
 #pragma unroll
       for (int w = 0; w < TR; ++w)
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int col = (TR * q + w) * NB + cg * 16 + c;
-          lv[u][w][c] = (u < nu && ru < n && col < n) ? L[(long)ru + (long)col * ld] : 0.0;
+          // a multiply, not a select, so that the load is not put under a branch
+          lv[u][w][c] = Lr[(long)min(col, n - 1) * ld] * ((okr && col < n) ? T(1) : T(0));
         }
     }
     if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
@@ -999,25 +1035,22 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const double* __restrict__ L,
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int col = w * NB + cg * 16 + c;
-          acc[u][0] += lv[u][w][c] * xs[0][col];
-          acc[u][1] += lv[u][w][c] * xs[1][col];
-          acc[u][2] += lv[u][w][c] * xs[2][col];
+          acc[u][0] += (double)lv[u][w][c] * xs[0][col];
+          acc[u][1] += (double)lv[u][w][c] * xs[1][col];
+          acc[u][2] += (double)lv[u][w][c] * xs[2][col];
         }
     __syncthreads();
   }
   for (int u = nu - 1; u >= 0; --u) {
     const int i = i0 + u, r0 = i * NB, mr = min(NB, n - r0);
-    if (u + 1 < nu) {      // coupling to the rows finished below in this super-row
-      for (int w = u + 1; w < nu; ++w) {
-        const int wn = min(NB, n - (i0 + w) * NB);
+    if (u + 1 < nu) {      // coupling to the row finished below in this super-row
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const int col = cg * 16 + c;
-          const double l = (col < wn) ? L[(long)(r0 + r) + (long)((i0 + w) * NB + col) * ld] : 0.0;
-          acc[u][0] += l * xs[0][w * NB + col];
-          acc[u][1] += l * xs[1][w * NB + col];
-          acc[u][2] += l * xs[2][w * NB + col];
-        }
+      for (int c = 0; c < 16; ++c) {
+        const int col = cg * 16 + c;
+        const double l = (double)lc[c];
+        acc[u][0] += l * xs[0][NB + col];
+        acc[u][1] += l * xs[1][NB + col];
+        acc[u][2] += l * xs[2][NB + col];
       }
     }
     part[cg][0][r] = acc[u][0];
@@ -1058,14 +1091,28 @@ void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const 
                    int ldg, double* y, int ldy, unsigned long long* ticket, int* flags,
                    int* err, hipStream_t st) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_fwd<<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err);
+  k_trsv3_fwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err);
 }
 
 void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
                     int ldy, double* x, int ldx, unsigned long long* ticket, int* flags,
                     int* err, hipStream_t st) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_bwd<<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, flags, err);
+  k_trsv3_bwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, flags, err);
+}
+
+// The same solves with a float factor (FP64 vectors and arithmetic).
+void trsv3_forward(const float* L, int ld, int n, const float* linv_ws, const double* g, int ldg,
+                   double* y, int ldy, unsigned long long* ticket, int* flags, int* err,
+                   hipStream_t st) {
+  const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
+  k_trsv3_fwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err);
+}
+void trsv3_backward(const float* L, int ld, int n, const float* linv_ws, const double* y, int ldy,
+                    double* x, int ldx, unsigned long long* ticket, int* flags, int* err,
+                    hipStream_t st) {
+  const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
+  k_trsv3_bwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, flags, err);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,6 +6,7 @@
 // FP64 inputs/outputs; the refinement residual is computed in FP64 elsewhere.
 #include <algorithm>
 #include "common.h"
+#include "tile_factor_f64.h"
 
 namespace pdk {
 
@@ -98,46 +99,6 @@ __device__ void gemm_bf16_tile(AccF& acc, __bf16 (*As)[BF_LD], __bf16 (*Bs)[BF_L
   }
 }
 
-// FP32 Cholesky + inverse of an LDS tile (T[c][r] = tile(r, c)); see the FP64 version.
-__device__ void factor_tile_lds_f32(float (*T)[LP_LD], float (*X)[LP_LD], float* inv_d, int mr,
-                                    int gbase, int* info) {
-  const int t = threadIdx.x;
-  for (int j = 0; j < NB; ++j) {
-    __syncthreads();
-    float d = T[j][j];
-    if (!(d > 0.f)) {
-      if (t == 0 && j < mr) atomicCAS(info, 0, gbase + j + 1);
-      d = 1.f;
-    }
-    const float ljj = sqrtf(d);
-    const float il = 1.f / ljj;
-    __syncthreads();
-    if (t == 0) { T[j][j] = ljj; inv_d[j] = il; }
-    if (t > j && t < NB) T[j][t] *= il;
-    __syncthreads();
-    const int r = t & 63;
-    for (int c = j + 1 + (t >> 6); c < NB; c += 4)
-      if (r >= c) T[c][r] -= T[j][r] * T[j][c];
-  }
-  __syncthreads();
-  if (t < NB) {
-    const int c = t;
-    for (int i = 0; i < c; ++i) X[c][i] = 0.f;
-    X[c][c] = inv_d[c];
-    for (int i = c + 1; i < NB; ++i) {
-      float s0 = 0.f, s1 = 0.f;
-      int p = c;
-      for (; p + 1 < i; p += 2) {
-        s0 += T[p][i] * X[c][p];
-        s1 += T[p + 1][i] * X[c][p + 1];
-      }
-      if (p < i) s0 += T[p][i] * X[c][p];
-      X[c][i] = -(s0 + s1) * inv_d[i];
-    }
-  }
-  __syncthreads();
-}
-
 constexpr long LP_SPIN_LIMIT = 1L << 24;
 // Same publication protocol as the FP64 kernels: agent-coherent stores of
 // published data, vmcnt(0) + barrier, then a coherent flag store; consumers
@@ -173,12 +134,12 @@ constexpr int BFL = NB + 8;   // BF16 LDS row: 64 k values + pad (16-byte aligne
 template <bool BF16>
 __device__ bool lp_accumulate(AccF& acc, float (*buf0)[LP_LD], float (*buf1)[LP_LD],
                               const float* __restrict__ A, int lda, int r0, int mr, int c0, int mc,
-                              int i, int j, int nt, const int* flags, int epoch, int* err,
-                              int* s_ok) {
+                              int i, int j, int kend, int nt, const int* flags, int epoch,
+                              int* err, int* s_ok, const int* mark) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
   const int r = t & 63, kq = t >> 6;
-  if (j == 0) return true;
+  if (kend == 0) return true;
   float ra[16], rb[16];
   auto load_tile = [&](int k) {
 #pragma unroll
@@ -190,18 +151,18 @@ __device__ bool lp_accumulate(AccF& acc, float (*buf0)[LP_LD], float (*buf1)[LP_
   };
   __bf16 (*Ab)[BFL] = (__bf16 (*)[BFL]) & buf0[0][0];
   __bf16 (*Bb)[BFL] = (__bf16 (*)[BFL]) & buf1[0][0];
-  int fi = 0, fj = 0;
+  int fi = 0, fj = 0, fm = 0;
   if (t == 0) {
     if (!lp_wait(&flags[i * nt], epoch, err) || !lp_wait(&flags[j * nt], epoch, err)) *s_ok = 0;
   }
   __syncthreads();
   if (!*s_ok) return false;
   load_tile(0);
-  if (t == 0 && j > 1) {
+  if (t == 0 && kend > 1) {
     fi = __hip_atomic_load(&flags[i * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     fj = __hip_atomic_load(&flags[j * nt + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  for (int k = 0; k < j; ++k) {
+  for (int k = 0; k < kend; ++k) {
     __syncthreads();
     if (BF16) {
 #pragma unroll
@@ -216,7 +177,8 @@ __device__ bool lp_accumulate(AccF& acc, float (*buf0)[LP_LD], float (*buf1)[LP_
         buf1[kq + 4 * q][r] = rb[q];
       }
     }
-    const bool nxt = k + 1 < j;
+    const bool nxt = k + 1 < kend;
+    if (t == 0 && fm == epoch) cu_pause(mark, epoch);
     if (t == 0 && nxt && (fi != epoch || fj != epoch)) {
       if (!lp_wait(&flags[i * nt + k + 1], epoch, err) || !lp_wait(&flags[j * nt + k + 1], epoch, err))
         *s_ok = 0;
@@ -225,10 +187,11 @@ __device__ bool lp_accumulate(AccF& acc, float (*buf0)[LP_LD], float (*buf1)[LP_
     if (!*s_ok) return false;
     if (nxt) {
       load_tile(k + 1);
-      if (t == 0 && k + 2 < j) {
+      if (t == 0 && k + 2 < kend) {
         fi = __hip_atomic_load(&flags[i * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         fj = __hip_atomic_load(&flags[j * nt + k + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      if (t == 0 && mark) fm = __hip_atomic_load(mark, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (BF16) {
 #pragma unroll
@@ -266,20 +229,73 @@ __global__ void k_reset_counter_lp(unsigned* ctr) {
   ctr[1] = ctr[1] + 1u;
 }
 
-// Dataflow Cholesky of a float matrix (same schedule as the FP64 kernel).
+// T[e >> 6][e & 63] = src[e] for the 4096 elements of a float tile.
+__device__ inline void stage_tile_f(float (*T)[LP_LD], const float* __restrict__ src) {
+  const int t = threadIdx.x;
+  float v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = src[t + 256 * q];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) T[(t >> 6) + 4 * q][t & 63] = v[q];
+}
+
+// acc(r, c) += sum_kk As[kk][r] Bs[kk][c] over one 64-deep block (FP32 matrix cores).
+__device__ inline void lds_product_f(AccF& acc, float (*As)[LP_LD], float (*Bs)[LP_LD]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+#pragma unroll 4
+  for (int ks = 0; ks < NB / 4; ++ks) {
+    const int k = ks * 4 + (lane >> 4);
+    const float a0 = As[k][wr * 32 + (lane & 15)];
+    const float a1 = As[k][wr * 32 + 16 + (lane & 15)];
+    const float b0 = Bs[k][wc * 32 + (lane & 15)];
+    const float b1 = Bs[k][wc * 32 + 16 + (lane & 15)];
+    acc.c[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a0, acc.c[0][0], 0, 0, 0);
+    acc.c[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a0, acc.c[0][1], 0, 0, 0);
+    acc.c[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a1, acc.c[1][0], 0, 0, 0);
+    acc.c[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a1, acc.c[1][1], 0, 0, 0);
+  }
+}
+
+// T[c][r] = sign * acc(r, c)
+__device__ inline void accf_to_lds(const AccF& acc, float (*T)[LP_LD], float sign) {
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq) T[accf_col(nb, qq)][accf_row(mb)] = sign * acc.c[mb][nb][qq];
+}
+
+// Dataflow Cholesky of a float matrix, on the schedule of the FP64 kernel:
+//  * diagonal (j, j): accumulates k < j - 1, finishes the sub-diagonal tile
+//    L_{j,j-1} = (A_{j,j-1} - S_j) Linv_{j-1}^T from the partial sum S_j of
+//    the task below, adds its last product, then factors and inverts the tile
+//    in FP64 (the blocked tile factor of the FP64 kernel) and rounds L and
+//    Linv to FP32;
+//  * sub-diagonal (j + 1, j): S_{j+1} = sum_{k<j} L_{j+1,k} L_{j,k}^T (FP32)
+//    into sbuf, published with its own flag;
+//  * (i, j), i >= j + 2: accumulates k < j, waits for Linv_jj, forms
+//    L_ij = (A_ij - acc) Linv_jj^T.
+// The k < j products use FP32 operands or BF16 operands (FP32 accumulation);
+// the finishing products are FP32.  Flags: nt x nt tile flags, then nt unused,
+// then nt partial-sum flags (the layout of the FP64 kernel).
 template <bool BF16>
 __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda, int n, int nt,
-                                                              float* linv_ws, int* flags,
-                                                              unsigned* ticket, int* info,
-                                                              int* err) {
+                                                              float* linv_ws, float* sbuf,
+                                                              int* flags, unsigned* ticket,
+                                                              int* info, int* err, int* cu_marks) {
   const int epoch = (int)ticket[1];
-  __shared__ float buf0[NB][LP_LD];
-  __shared__ float buf1[NB][LP_LD];
-  __shared__ float inv_d[NB];
+  int* sflags = flags + (nt + 1) * nt;
+  int* const mark = cu_marks ? cu_marks + cu_slot() : nullptr;
+  // FP64 tile and inverse of the diagonal factor; the float operand tiles of
+  // the products live in the same memory
+  __shared__ double Tf[NB][LDS_LD];
+  __shared__ double Xf[NB][LDS_LD];
   __shared__ int s_task, s_ok;
+  float (*buf0)[LP_LD] = reinterpret_cast<float (*)[LP_LD]>(&Tf[0][0]);
+  float (*buf1)[LP_LD] = reinterpret_cast<float (*)[LP_LD]>(&Xf[0][0]);
   const int t = threadIdx.x;
-  const int lane = t & 63, w = t >> 6;
-  const int wr = w >> 1, wc = w & 1;
   const int ntask = nt * (nt + 1) / 2;
   for (;;) {
     __syncthreads();
@@ -296,14 +312,13 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
       ++j;
     }
     const int i = j + (q - start);
+    const bool diag = (i == j), sub = (i == j + 1);
+    const bool critical = diag || sub;
     const int r0 = i * NB, c0 = j * NB;
     const int mr = min(NB, n - r0), mc = min(NB, n - c0);
+    if (critical) __builtin_amdgcn_s_setprio(2);
+    // acc <- -A_ij (identity padding on the diagonal tile), or 0 for the partial sum
     AccF acc;
-    accf_zero(acc);
-    if (!lp_accumulate<BF16>(acc, buf0, buf1, A, lda, r0, mr, c0, mc, i, j, nt, flags, epoch, err,
-                             &s_ok))
-      return;
-    __syncthreads();
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -311,70 +326,134 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
           const int r = accf_row(mb), c = accf_col(nb, qq);
-          float v;
-          if (r < mr && c < mc) v = cload(&A[(long)(r0 + r) + (long)(c0 + c) * lda]) - acc.c[mb][nb][qq];
-          else v = (i == j && r == c) ? 1.f : 0.f;
-          buf0[c][r] = v;
+          acc.c[mb][nb][qq] = sub ? 0.f
+                            : (r < mr && c < mc) ? -cload(&A[(long)(r0 + r) + (long)(c0 + c) * lda])
+                                                 : ((diag && r == c) ? -1.f : 0.f);
         }
-    __syncthreads();
-    if (i == j) {
-      factor_tile_lds_f32(buf0, buf1, inv_d, mr, r0, info);
-      float* Li = linv_ws + (long)j * NB * NB;
-      for (int e = t; e < NB * NB; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        cstore(&Li[e], buf1[c][r]);
-        if (r < mr && c < mr)
-          cstore(&A[(long)(r0 + r) + (long)(r0 + c) * lda], (r >= c) ? buf0[c][r] : buf0[r][c]);
-      }
-    } else {
-      if (t == 0 && !lp_wait(&flags[j * nt + j], epoch, err)) s_ok = 0;
-      __syncthreads();
-      if (!s_ok) return;
-      const float* Li = linv_ws + (long)j * NB * NB;
-      for (int e = t; e < NB * NB; e += 256) buf1[e >> 6][e & 63] = Li[e];
-      __syncthreads();
-      accf_zero(acc);
-#pragma unroll 4
-      for (int ks = 0; ks < NB / 4; ++ks) {
-        const int k = ks * 4 + (lane >> 4);
-        const float a0 = buf0[k][wr * 32 + (lane & 15)];
-        const float a1 = buf0[k][wr * 32 + 16 + (lane & 15)];
-        const float b0 = buf1[k][wc * 32 + (lane & 15)];
-        const float b1 = buf1[k][wc * 32 + 16 + (lane & 15)];
-        acc.c[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a0, acc.c[0][0], 0, 0, 0);
-        acc.c[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a0, acc.c[0][1], 0, 0, 0);
-        acc.c[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a1, acc.c[1][0], 0, 0, 0);
-        acc.c[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a1, acc.c[1][1], 0, 0, 0);
-      }
-      __syncthreads();
+    const int kend = diag ? max(j - 1, 0) : j;
+    if (!lp_accumulate<BF16>(acc, buf0, buf1, A, lda, r0, mr, c0, mc, i, j, kend, nt, flags, epoch,
+                             err, &s_ok, critical ? nullptr : mark))
+      return;
+    if (sub) {
+      float* Sb = sbuf + (long)i * NB * NB;
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-          for (int qq = 0; qq < 4; ++qq) buf0[accf_col(nb, qq)][accf_row(mb)] = acc.c[mb][nb][qq];
+          for (int qq = 0; qq < 4; ++qq)
+            cstore(&Sb[accf_row(mb) + NB * accf_col(nb, qq)], acc.c[mb][nb][qq]);
+      lp_publish(&sflags[i], epoch);
+      __builtin_amdgcn_s_setprio(0);
+      continue;
+    }
+    if (diag && j > 0) {
+      const int cs = (j - 1) * NB;
+      __syncthreads();                             // last products done with buf0
+      {
+        const int r = t & 63;
+        float v[16];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq)
+          v[qq] = (r < mr) ? cload(&A[(long)(r0 + r) + (long)(cs + (t >> 6) + 4 * qq) * lda]) : 0.f;
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][r] = v[qq];
+      }
+      if (t == 0 && (!lp_wait(&sflags[j], epoch, err) ||
+                     !lp_wait(&flags[(j - 1) * nt + (j - 1)], epoch, err)))
+        s_ok = 0;
+      __syncthreads();
+      if (!s_ok) return;
+      if (t == 0 && mark) __hip_atomic_store(mark, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      stage_tile_f(buf1, linv_ws + (long)(j - 1) * NB * NB);   // buf1[kk][c] = Linv(c, kk)
+      {
+        const float* Sb = sbuf + (long)j * NB * NB;
+        float v[16];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) v[qq] = Sb[t + 256 * qq];
+#pragma unroll
+        for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][t & 63] -= v[qq];
+      }
+      __syncthreads();
+      AccF l;
+      accf_zero(l);
+      lds_product_f(l, buf0, buf1);                // L = (A - S) Linv^T
+      __syncthreads();
+      accf_to_lds(l, buf0, 1.f);
       __syncthreads();
       for (int e = t; e < NB * NB; e += 256) {
         const int r = e & 63, c = e >> 6;
-        if (r < mr) cstore(&A[(long)(r0 + r) + (long)(c0 + c) * lda], buf0[c][r]);
-        if (c < mr) cstore(&A[(long)(c0 + r) + (long)(r0 + c) * lda], buf0[r][c]);   // L^T copy
+        if (r < mr) cstore(&A[(long)(r0 + r) + (long)(cs + c) * lda], buf0[c][r]);
+      }
+      lds_product_f(acc, buf0, buf0);              // acc += L L^T, while the stores drain
+      lp_publish(&flags[j * nt + (j - 1)], epoch);
+      // transposed copy, read only by the backward solve after this launch
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (c < mr) A[(long)(cs + r) + (long)(r0 + c) * lda] = buf0[r][c];
       }
     }
-    lp_publish(&flags[i * nt + j], epoch);
+    __syncthreads();
+    if (diag) {
+      // C = A_jj - sum_k L_jk L_jk^T = -acc, factored in FP64
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq)
+            Tf[accf_col(nb, qq)][accf_row(mb)] = -(double)acc.c[mb][nb][qq];
+      __syncthreads();
+      if (j == 0 && t == 0 && mark)
+        __hip_atomic_store(mark, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      factor_tile_blocked(Tf, Xf, mr, r0, info);
+      float* Li = linv_ws + (long)j * NB * NB;
+      for (int e = t; e < NB * NB; e += 256) cstore(&Li[e], (float)Xf[e >> 6][e & 63]);
+      if (t == 0 && mark) __hip_atomic_store(mark, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      lp_publish(&flags[i * nt + j], epoch);
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (r < mr && c < mr)
+          A[(long)(r0 + r) + (long)(r0 + c) * lda] = (float)((r >= c) ? Tf[c][r] : Tf[r][c]);
+      }
+    } else {
+      accf_to_lds(acc, buf0, -1.f);                // C = A_ij - sum_k L_ik L_jk^T
+      if (t == 0 && !lp_wait(&flags[j * nt + j], epoch, err)) s_ok = 0;
+      __syncthreads();
+      if (!s_ok) return;
+      stage_tile_f(buf1, linv_ws + (long)j * NB * NB);
+      __syncthreads();
+      accf_zero(acc);
+      lds_product_f(acc, buf0, buf1);
+      __syncthreads();
+      accf_to_lds(acc, buf0, 1.f);
+      __syncthreads();
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (r < mr && c < mc) cstore(&A[(long)(r0 + r) + (long)(c0 + c) * lda], buf0[c][r]);
+      }
+      lp_publish(&flags[i * nt + j], epoch);
+      for (int e = t; e < NB * NB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        if (c < mr && r < mc) A[(long)(c0 + r) + (long)(r0 + c) * lda] = buf0[r][c];
+      }
+    }
+    if (critical) __builtin_amdgcn_s_setprio(0);
   }
 }
 
-void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, int* flags, unsigned* ticket,
-                       int* info, int* err, int n_wg, bool bf16, hipStream_t st) {
+void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, float* sbuf, int* flags,
+                       unsigned* ticket, int* info, int* err, int n_wg, bool bf16, hipStream_t st,
+                       int* cu_marks) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = nt * (nt + 1) / 2;
   k_reset_counter_lp<<<1, 1, 0, st>>>(ticket);
   if (bf16)
-    k_potrf_dataflow_lp<true><<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags,
-                                                                     ticket, info, err);
+    k_potrf_dataflow_lp<true><<<std::min(ntask, n_wg), 256, 0, st>>>(
+        A, lda, n, nt, linv_ws, sbuf, flags, ticket, info, err, cu_marks);
   else
-    k_potrf_dataflow_lp<false><<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, flags,
-                                                                      ticket, info, err);
+    k_potrf_dataflow_lp<false><<<std::min(ntask, n_wg), 256, 0, st>>>(
+        A, lda, n, nt, linv_ws, sbuf, flags, ticket, info, err, cu_marks);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,181 +494,32 @@ void equilibrate_convert(const double* H, int ld, int n, double* d, float* H32, 
 
 // ---------------------------------------------------------------------------
 // Triangular solves with the FP32 factor of D H D, three right-hand sides:
-//   forward:  y = L^-1 (D r)           (r FP64 in, y FP32 out)
-//   backward: x (+)= D L^-T y          (FP64 out, accumulate or overwrite)
-// Same ticket/epoch dataflow as the FP64 solves.
-constexpr long LPS_SPIN = 1L << 24;
-
-__device__ inline float wave_sum_f(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+//   b = D r,  L y = b,  L^T z = y,  x (+)= D z
+// (the float-factor instances of the FP64 solve kernels: FP64 vectors and
+// arithmetic, FP32 matrix reads).
+__global__ void k_scale3(int n, const double* __restrict__ d, const double* __restrict__ r,
+                         double* __restrict__ b) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  b[e] = r[e] * d[e % n];
 }
-
-__global__ __launch_bounds__(256) void k_trsv3_fwd_lp(const float* __restrict__ L, int ld, int n,
-                                                      int nt, const float* __restrict__ linv,
-                                                      const double* __restrict__ r,
-                                                      const double* __restrict__ d, float* y,
-                                                      unsigned long long* ticket, int* flags,
-                                                      int* err) {
-  __shared__ int s_row, s_epoch, s_ok;
-  __shared__ float ys[3][NB];
-  __shared__ float part[4][3][NB];
-  __shared__ float Ls[NB][NB + 1];
-  const int t = threadIdx.x;
-  if (t == 0) {
-    const unsigned long long tk = atomicAdd(ticket, 1ull);
-    s_row = (int)(tk % (unsigned long long)nt);
-    s_epoch = (int)(tk / (unsigned long long)nt) + 1;
-    s_ok = 1;
-  }
-  __syncthreads();
-  const int i = s_row, epoch = s_epoch;
-  const int r0 = i * NB, mr = min(NB, n - r0);
-  const int rr = t & 63, cg = t >> 6;
-  {
-    const float* Li = linv + (long)i * NB * NB;
-    for (int e = t; e < NB * NB; e += 256) Ls[e >> 6][e & 63] = Li[e];
-  }
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-  float lv[16];
-  if (i > 0) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) lv[q] = (rr < mr) ? L[(long)(r0 + rr) + (long)(cg * 16 + q) * ld] : 0.f;
-  }
-  for (int p = 0; p < i; ++p) {
-    if (t == 0 && !lp_wait(&flags[p], epoch, err)) s_ok = 0;
-    __syncthreads();
-    if (!s_ok) return;
-    if (t < 3 * NB) ys[t >> 6][t & 63] = cload(&y[(long)(t >> 6) * n + p * NB + (t & 63)]);
-    __syncthreads();
-    float cur[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cur[q] = lv[q];
-    if (p + 1 < i) {
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        lv[q] = (rr < mr) ? L[(long)(r0 + rr) + (long)((p + 1) * NB + cg * 16 + q) * ld] : 0.f;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = cg * 16 + q;
-      a0 += cur[q] * ys[0][c];
-      a1 += cur[q] * ys[1][c];
-      a2 += cur[q] * ys[2][c];
-    }
-    __syncthreads();
-  }
-  part[cg][0][rr] = a0;
-  part[cg][1][rr] = a1;
-  part[cg][2][rr] = a2;
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, q = t & 63;
-    const float b = (q < mr) ? (float)(r[(long)v * n + r0 + q] * d[r0 + q]) : 0.f;
-    ys[v][q] = b - (part[0][v][q] + part[1][v][q] + part[2][v][q] + part[3][v][q]);
-  }
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, q = t & 63;
-    float s = 0.f;
-    for (int c = 0; c <= q; ++c) s += Ls[c][q] * ys[v][c];
-    if (q < mr) cstore(&y[(long)v * n + r0 + q], s);
-  }
-  lp_publish(&flags[i], epoch);
-}
-
-// L^T x = y with L^T read from the upper triangle.
-__global__ __launch_bounds__(256) void k_trsv3_bwd_lp(const float* __restrict__ L, int ld, int n,
-                                                      int nt, const float* __restrict__ linv,
-                                                      const float* __restrict__ y,
-                                                      const double* __restrict__ d, float* xs,
-                                                      double* x, int accumulate,
-                                                      unsigned long long* ticket, int* flags,
-                                                      int* err) {
-  __shared__ int s_row, s_epoch, s_ok;
-  __shared__ float xsh[3][NB];
-  __shared__ float part[4][3][NB];
-  __shared__ float Ls[NB][NB + 1];
-  const int t = threadIdx.x;
-  if (t == 0) {
-    const unsigned long long tk = atomicAdd(ticket, 1ull);
-    s_row = nt - 1 - (int)(tk % (unsigned long long)nt);
-    s_epoch = (int)(tk / (unsigned long long)nt) + 1;
-    s_ok = 1;
-  }
-  __syncthreads();
-  const int i = s_row, epoch = s_epoch;
-  const int r0 = i * NB, mr = min(NB, n - r0);
-  const int rr = t & 63, cg = t >> 6;
-  {
-    const float* Li = linv + (long)i * NB * NB;
-    for (int e = t; e < NB * NB; e += 256) Ls[e >> 6][e & 63] = Li[e];
-  }
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-  float lv[16];
-  auto load_tile = [&](int p) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = p * NB + cg * 16 + q;
-      lv[q] = (rr < mr && col < n) ? L[(long)(r0 + rr) + (long)col * ld] : 0.f;
-    }
-  };
-  if (i < nt - 1) load_tile(nt - 1);
-  for (int p = nt - 1; p > i; --p) {
-    const int pr0 = p * NB, pmr = min(NB, n - pr0);
-    if (t == 0 && !lp_wait(&flags[p], epoch, err)) s_ok = 0;
-    __syncthreads();
-    if (!s_ok) return;
-    if (t < 3 * NB) {
-      const int v = t >> 6, cc = t & 63;
-      xsh[v][cc] = (cc < pmr) ? cload(&xs[(long)v * n + pr0 + cc]) : 0.f;
-    }
-    __syncthreads();
-    float cur[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cur[q] = lv[q];
-    if (p - 1 > i) load_tile(p - 1);
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int c = cg * 16 + q;
-      a0 += cur[q] * xsh[0][c];
-      a1 += cur[q] * xsh[1][c];
-      a2 += cur[q] * xsh[2][c];
-    }
-    __syncthreads();
-  }
-  part[cg][0][rr] = a0;
-  part[cg][1][rr] = a1;
-  part[cg][2][rr] = a2;
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, q = t & 63;
-    const float b = (q < mr) ? y[(long)v * n + r0 + q] : 0.f;
-    xsh[v][q] = b - (part[0][v][q] + part[1][v][q] + part[2][v][q] + part[3][v][q]);
-  }
-  __syncthreads();
-  if (t < 3 * NB) {
-    const int v = t >> 6, q = t & 63;
-    float s = 0.f;
-    for (int c = q; c < NB; ++c) s += Ls[q][c] * xsh[v][c];
-    if (q < mr) {
-      cstore(&xs[(long)v * n + r0 + q], s);
-      const double val = (double)s * d[r0 + q];
-      const long o = (long)v * n + r0 + q;
-      x[o] = accumulate ? x[o] + val : val;
-    }
-  }
-  lp_publish(&flags[i], epoch);
+__global__ void k_unscale3(int n, const double* __restrict__ d, const double* __restrict__ z,
+                           double* __restrict__ x, int accumulate) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const double v = z[e] * d[e % n];
+  x[e] = accumulate ? x[e] + v : v;
 }
 
 void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const double* d,
-                    const double* r, float* y, float* xs, double* x, int accumulate,
+                    const double* r, double* b, double* y, double* x, int accumulate,
                     unsigned long long* tickets, int* flags, int* err, hipStream_t st) {
   const int nt = (n + NB - 1) / NB;
-  k_trsv3_fwd_lp<<<nt, 256, 0, st>>>(L, ld, n, nt, linv_ws, r, d, y, tickets, flags, err);
-  k_trsv3_bwd_lp<<<nt, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, d, xs, x, accumulate, tickets + 1,
-                                     flags + nt, err);
+  const int g = (3 * n + 255) / 256;
+  k_scale3<<<g, 256, 0, st>>>(n, d, r, b);
+  trsv3_forward(L, ld, n, linv_ws, b, n, y, n, tickets, flags, err, st);
+  trsv3_backward(L, ld, n, linv_ws, y, n, b, n, tickets + 1, flags + nt, err, st);   // z into b
+  k_unscale3<<<g, 256, 0, st>>>(n, d, b, x, accumulate);
 }
 
 }  // namespace pdk
