@@ -23,23 +23,24 @@ namespace {
 constexpr int TS = 64;                 // tile size of the level products
 constexpr int SLOT = 3 * TS;           // doubles per part slot: [rhs][64]
 
-// One wave per lower tile (I, J): the wave loads the whole 64 x 64 tile into
-// registers (lane = row, 64 coalesced column loads in flight), adds the row
-// part Z_IJ x_J in-lane, and forms the col part Z_IJ^T x_I sixteen columns at
-// a time through a wave-private LDS transpose (lane = (column, row group),
-// then two cross-lane additions).  Row parts go to slot t(I, J) of Prow
-// (off-diagonal tiles), col parts to slot t(I, J) of Pcol.
+// One workgroup per lower tile (I, J), wave w owning columns 16 w .. 16 w + 15:
+// the wave loads its 64 x 16 block into registers (lane = row, sixteen
+// coalesced column loads in flight), adds its share of the row part Z_IJ x_J
+// in-lane, and forms the col part Z_IJ^T x_I of its sixteen columns through a
+// wave-private LDS transpose (lane = (column, row group), then two cross-lane
+// additions).  The four row-part shares are added in wave order.  Row parts go
+// to slot t(I, J) of Prow (off-diagonal tiles), col parts to slot t(I, J) of
+// Pcol.
 __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z, long ldz, int w,
                                                     int nb, const double* __restrict__ x, long ldx,
                                                     double* __restrict__ Prow,
                                                     double* __restrict__ Pcol) {
   __shared__ double Ts[4][TS][17];         // per wave: 64 rows x 16 columns (+1 pad)
-  __shared__ double xs[4][2][3][TS];       // per wave: x_J, x_I
+  __shared__ double xs[2][3][TS];          // x_J, x_I
+  __shared__ double rp[4][3][TS];          // per-wave shares of the row part
   const int t = threadIdx.x, lane = t & 63;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-  const int tt = blockIdx.x * 4 + wv;
-  const int ntiles = nb * (nb + 1) / 2;
-  if (tt >= ntiles) return;
+  const int tt = blockIdx.x;
   int I = (int)((sqrt(8.0 * (double)tt + 1.0) - 1.0) * 0.5);
   while ((I + 1) * (I + 2) / 2 <= tt) ++I;
   while (I * (I + 1) / 2 > tt) --I;
@@ -47,67 +48,74 @@ __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z
   const int J = tt - I * (I + 1) / 2;
   const int i0 = I * TS, j0 = J * TS;
   const int nr = min(TS, w - i0), nc = min(TS, w - j0);
-  // buffer loads: one 32-bit lane offset (the row) for all 64 columns, the
+  const int c0 = 16 * wv;                  // first column of this wave
+  const int ncw = max(0, min(16, nc - c0));
+  // buffer loads: one 32-bit lane offset (the row) for all sixteen columns, the
   // column offset in a scalar register; lanes past the last row get an offset
   // beyond the buffer's range and read zero
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(Z + (long)j0 * ldz), 0, (int)(nc * ldz * (long)sizeof(double)), 0x00020000);
+      (void*)(Z + (long)(j0 + (ncw > 0 ? c0 : 0)) * ldz), 0,
+      (int)(max(ncw, 1) * ldz * (long)sizeof(double)), 0x00020000);
   const int voff = lane < nr ? (i0 + lane) * (int)sizeof(double) : 0x7ffffff0;
-  double z[TS];
+  // columns past the last one (ragged tile) re-read the last column, so every
+  // address stays inside the matrix; they are zeroed below
+  double z[16];
+  if (ncw > 0) {
 #pragma unroll
-  for (int c = 0; c < TS; ++c)
-    z[c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                          rs, voff, c * (int)(ldz * sizeof(double)), 0));
-#pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    xs[wv][0][v][lane] = lane < nc ? x[(long)v * ldx + j0 + lane] : 0.0;
-    xs[wv][1][v][lane] = lane < nr ? x[(long)v * ldx + i0 + lane] : 0.0;
+    for (int c = 0; c < 16; ++c)
+      z[c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                            rs, voff, min(c, ncw - 1) * (int)(ldz * sizeof(double)), 0));
   }
-  if (nc < TS) {
-#pragma unroll
-    for (int c = 0; c < TS; ++c)
-      if (c >= nc) z[c] = 0.0;
+  for (int e = t; e < 2 * 3 * TS; e += 256) {
+    const int h = e / (3 * TS), v = (e / TS) % 3, r = e % TS;
+    const int base = h ? i0 : j0, lim = h ? nr : nc;
+    xs[h][v][r] = r < lim ? x[(long)v * ldx + base + r] : 0.0;
   }
-  // row part, lane = row
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+    if (c >= ncw) z[c] = 0.0;
+  __syncthreads();
+  // this wave's share of the row part, lane = row
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
-  for (int c = 0; c < TS; ++c) {
-    s0 += z[c] * xs[wv][0][0][c];
-    s1 += z[c] * xs[wv][0][1][c];
-    s2 += z[c] * xs[wv][0][2][c];
+  for (int c = 0; c < 16; ++c) {
+    s0 += z[c] * xs[0][0][c0 + c];
+    s1 += z[c] * xs[0][1][c0 + c];
+    s2 += z[c] * xs[0][2][c0 + c];
+  }
+  rp[wv][0][lane] = s0;
+  rp[wv][1][lane] = s1;
+  rp[wv][2][lane] = s2;
+  // col part of the sixteen columns: lane = (cc = lane & 15, rg = lane >> 4)
+  const int cc = lane & 15, rg = lane >> 4;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) Ts[wv][lane][c] = z[c];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = 16 * rg + q;
+    const double zz = Ts[wv][r][cc];
+    a0 += zz * xs[1][0][r];
+    a1 += zz * xs[1][1][r];
+    a2 += zz * xs[1][2][r];
+  }
+  a0 += __shfl_xor(a0, 16, 64);
+  a1 += __shfl_xor(a1, 16, 64);
+  a2 += __shfl_xor(a2, 16, 64);
+  a0 += __shfl_xor(a0, 32, 64);
+  a1 += __shfl_xor(a1, 32, 64);
+  a2 += __shfl_xor(a2, 32, 64);
+  double* pc = Pcol + (long)tt * SLOT;
+  if (lane < 16) {
+    pc[c0 + lane] = a0;
+    pc[TS + c0 + lane] = a1;
+    pc[2 * TS + c0 + lane] = a2;
   }
   if (I > J) {
-    double* pr = Prow + (long)tt * SLOT;
-    pr[lane] = s0;
-    pr[TS + lane] = s1;
-    pr[2 * TS + lane] = s2;
-  }
-  // col part, sixteen columns at a time: lane = (cc = lane & 15, rg = lane >> 4)
-  const int cc = lane & 15, rg = lane >> 4;
-  double* pc = Pcol + (long)tt * SLOT;
-#pragma unroll
-  for (int sb = 0; sb < 4; ++sb) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) Ts[wv][lane][c] = z[16 * sb + c];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int r = 16 * rg + q;
-      const double zz = Ts[wv][r][cc];
-      a0 += zz * xs[wv][1][0][r];
-      a1 += zz * xs[wv][1][1][r];
-      a2 += zz * xs[wv][1][2][r];
-    }
-    a0 += __shfl_xor(a0, 16, 64);
-    a1 += __shfl_xor(a1, 16, 64);
-    a2 += __shfl_xor(a2, 16, 64);
-    a0 += __shfl_xor(a0, 32, 64);
-    a1 += __shfl_xor(a1, 32, 64);
-    a2 += __shfl_xor(a2, 32, 64);
-    if (lane < 16) {
-      pc[16 * sb + lane] = a0;
-      pc[TS + 16 * sb + lane] = a1;
-      pc[2 * TS + 16 * sb + lane] = a2;
+    __syncthreads();
+    if (t < 3 * TS) {
+      const int v = t >> 6, r = t & 63;
+      Prow[(long)tt * SLOT + v * TS + r] = ((rp[0][v][r] + rp[1][v][r]) + rp[2][v][r]) + rp[3][v][r];
     }
   }
 }
@@ -151,7 +159,7 @@ void sweep_symv(const double* Z, long ldz, int w, const double* x, long ldx, dou
                 hipStream_t st) {
   if (w <= 0) return;
   const int nb = (w + TS - 1) / TS, ntiles = nb * (nb + 1) / 2;
-  k_sweep_symv<<<(ntiles + 3) / 4, 256, 0, st>>>(Z, ldz, w, nb, x, ldx, P, P + (long)ntiles * SLOT);
+  k_sweep_symv<<<ntiles, 256, 0, st>>>(Z, ldz, w, nb, x, ldx, P, P + (long)ntiles * SLOT);
 }
 
 void sweep_assemble(int w, const double* P, const double* base, long ldb, double* out, long ldo,
