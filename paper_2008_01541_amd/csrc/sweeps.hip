@@ -53,27 +53,40 @@ __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z
   // buffer loads: one 32-bit lane offset (the row) for all sixteen columns, the
   // column offset in a scalar register; lanes past the last row get an offset
   // beyond the buffer's range and read zero
+  // (base and size are wave-uniform; readfirstlane keeps the descriptor scalar)
+  const unsigned long long zb = reinterpret_cast<unsigned long long>(
+      Z + (long)(j0 + (ncw > 0 ? c0 : 0)) * ldz);
+  const unsigned zlo = __builtin_amdgcn_readfirstlane((unsigned)zb);
+  const unsigned zhi = __builtin_amdgcn_readfirstlane((unsigned)(zb >> 32));
+  const int zbytes = __builtin_amdgcn_readfirstlane((int)(max(ncw, 1) * ldz * (long)sizeof(double)));
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)(Z + (long)(j0 + (ncw > 0 ? c0 : 0)) * ldz), 0,
-      (int)(max(ncw, 1) * ldz * (long)sizeof(double)), 0x00020000);
+      reinterpret_cast<void*>(((unsigned long long)zhi << 32) | zlo), 0, zbytes, 0x00020000);
   const int voff = lane < nr ? (i0 + lane) * (int)sizeof(double) : 0x7ffffff0;
-  // columns past the last one (ragged tile) re-read the last column, so every
-  // address stays inside the matrix; they are zeroed below
-  double z[16];
-  if (ncw > 0) {
+  // x_J and x_I: two loads per thread (t and t + 256 of the 384 entries),
+  // issued before the tile so that waiting for them does not wait for it
+  double xv[2];
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-      z[c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                            rs, voff, min(c, ncw - 1) * (int)(ldz * sizeof(double)), 0));
-  }
-  for (int e = t; e < 2 * 3 * TS; e += 256) {
-    const int h = e / (3 * TS), v = (e / TS) % 3, r = e % TS;
+  for (int k = 0; k < 2; ++k) {
+    const int e = t + 256 * k;
+    const int h = e >= 3 * TS ? 1 : 0, v = (e / TS) % 3, r = e % TS;
     const int base = h ? i0 : j0, lim = h ? nr : nc;
-    xs[h][v][r] = r < lim ? x[(long)v * ldx + base + r] : 0.0;
+    const bool ok = e < 2 * 3 * TS && r < lim;
+    xv[k] = x[ok ? (long)v * ldx + base + r : 0] * (ok ? 1.0 : 0.0);
   }
+  // columns past the last one (ragged tile) re-read the last column, so every
+  // address stays inside the matrix: they meet zeros of x_J in the row part,
+  // and their col parts are never read
+  const int clast = __builtin_amdgcn_readfirstlane(max(ncw, 1) - 1);
+  double z[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c)
-    if (c >= ncw) z[c] = 0.0;
+    z[c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                          rs, voff, min(c, clast) * (int)(ldz * sizeof(double)), 0));
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int e = t + 256 * k;
+    if (e < 2 * 3 * TS) (&xs[0][0][0])[e] = xv[k];
+  }
   __syncthreads();
   // this wave's share of the row part, lane = row
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
