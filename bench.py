@@ -204,6 +204,8 @@ def main():
                          "983K-tet self-contact slit closed by a jaw rotation")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
+    ap.add_argument("--no-overlap-forward", action="store_true",
+                    help="pipelined run: forward solve after the factorization instead of during it")
     ap.add_argument("--factor-wg", type=int, default=384,
                     help="persistent workgroups of the factorization in the pipelined run "
                          "(fewer than 2 per CU leave room for the overlapped sweeps)")
@@ -267,11 +269,13 @@ def main():
         # substitution of k - 1 and the local step and condensation of k
         fac_stream = torch.cuda.Stream()
         run.run_pipelined(args.warmup, spheres_of=lambda k: sph[frames[k]],
-                          n_workgroups=args.factor_wg, factor_stream=fac_stream)
+                          n_workgroups=args.factor_wg, factor_stream=fac_stream,
+                          overlap_forward=not args.no_overlap_forward)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         run.run_pipelined(args.steps, spheres_of=lambda k: sph[frames[args.warmup + k]],
-                          n_workgroups=args.factor_wg, factor_stream=fac_stream)
+                          n_workgroups=args.factor_wg, factor_stream=fac_stream,
+                          overlap_forward=not args.no_overlap_forward)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pipe_value = args.steps / (t1 - t0)
@@ -330,6 +334,7 @@ def main():
         "eager_pd_iters_per_s": eager_value,
         "pipelined_pd_iters_per_s": pipe_value,
         "pipelined_factor_workgroups": None if args.no_pipeline else args.factor_wg,
+        "pipelined_forward_overlapped": None if args.no_pipeline else not args.no_overlap_forward,
         "graph_pd_iters_per_s": graph_value,
         "schur_cholesky_tflops": chol_tflops,
         "schur_cholesky_ms": fac_avg,

@@ -178,13 +178,19 @@ pd_status pd_global_solve(pd_ctx *ctx, const double *g, double *u, pd_precision 
  * factorization (default 2 per compute unit; fewer leave room for kernels of
  * the other stream); <= 0 keeps the default.
  * supply_rhs = 0: a following pd_global_solve(PD_FP64) runs both triangular
- * solves.  supply_rhs != 0: the forward substitution is fused into the
+ * solves.  supply_rhs = 1: the forward substitution is fused into the
  * factorization for a right-hand side handed over while it runs with
  * pd_supply_rhs, which must be enqueued on another stream before anything
  * waits for the factorization (otherwise its waits time out and the
  * factorization reports PD_ERR_HIP); the following pd_global_solve then only
  * runs the backward substitution, for that right-hand side (its g argument
- * is not read).  A no-op when the factor is current.  Non-positive pivots
+ * is not read).  supply_rhs = 2: the following pd_global_solve(PD_FP64) may
+ * be enqueued on another stream without waiting for the factorization: its
+ * forward substitution starts at once and follows the factorization's tile
+ * flags row block by row block, and its backward substitution waits for the
+ * factorization's end (both through events the library records); nothing
+ * else may use the context's factor in between.  Other values:
+ * PD_ERR_INVALID.  A no-op when the factor is current.  Non-positive pivots
  * are reported by a later pd_global_solve with info. */
 pd_status pd_factor(pd_ctx *ctx, int32_t n_workgroups, int32_t supply_rhs);
 

@@ -244,9 +244,13 @@ class PDContext:
         self._chk(st)
         return None
 
-    def factor(self, n_workgroups=0, supply_rhs=False):
-        """FP64 factorization of H ahead of global_solve (pd_factor)."""
-        self._chk(self._lib.pd_factor(self._ctx, int(n_workgroups), 1 if supply_rhs else 0))
+    def factor(self, n_workgroups=0, supply_rhs=False, overlap_forward=False):
+        """FP64 factorization of H ahead of global_solve (pd_factor); with
+        overlap_forward the next global_solve may be enqueued on another stream
+        while it runs (mode 2), with supply_rhs the forward solve is fused in
+        (mode 1)."""
+        mode = 2 if overlap_forward else (1 if supply_rhs else 0)
+        self._chk(self._lib.pd_factor(self._ctx, int(n_workgroups), mode))
 
     def supply_rhs(self, g):
         """Right-hand side for a factorization started with supply_rhs=True."""

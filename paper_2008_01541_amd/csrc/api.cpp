@@ -110,6 +110,9 @@ struct pd_ctx {
   int g_epoch = 0;                    // last value stored to d_gflag
   bool deferred = false;              // the current factor awaits / holds a supplied RHS
   bool rhs_supplied = false;          // pd_supply_rhs was called for it
+  bool overlap = false;               // the forward solve may overlap the running factorization
+  hipEvent_t ev_fstart = nullptr;     // factorization epoch advanced (its flags may be polled)
+  hipEvent_t ev_fdone = nullptr;      // factorization finished
   // penalties
   int32_t n_pen = 0, pen_cap = 0;
   int32_t* d_pidx = nullptr;
@@ -133,6 +136,8 @@ struct pd_ctx {
   }
   ~pd_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (ev_fstart) (void)hipEventDestroy(ev_fstart);
+    if (ev_fdone) (void)hipEventDestroy(ev_fdone);
   }
 
   pd_status fail(pd_status s, const char* fmt, ...) {
@@ -246,11 +251,11 @@ void free_now(pd_ctx* c, void* p) {
 // multiple of 16 so tiles start on 128-byte lines); tile inverses to d_linv,
 // transpose of the factor in the upper triangle.
 void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr, int n_wg = 0,
-              const int* gflag = nullptr, int gepoch = 0) {
+              const int* gflag = nullptr, int gepoch = 0, hipEvent_t after_reset = nullptr) {
   if (c->chol_dataflow) {
     potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
                    n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, gflag, gepoch,
-                   c->d_cumarks);
+                   c->d_cumarks, after_reset);
   } else {
     potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
   }
@@ -1024,6 +1029,14 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
         rhs_unpack(m, c->d_Yt, c->d_y, m, c->st);
         c->deferred = false;
         c->rhs_supplied = false;
+      } else if (c->overlap) {
+        // the factorization may still run on another stream: the forward
+        // solve follows its tile flags, the backward one waits for its end
+        HIPCK(c, hipStreamWaitEvent(c->st, c->ev_fstart, 0));
+        trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
+                      c->d_err, c->st, c->d_tflags, c->d_tticket);
+        HIPCK(c, hipStreamWaitEvent(c->st, c->ev_fdone, 0));
+        c->overlap = false;
       } else {
         trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
                       c->d_err, c->st);
@@ -1096,19 +1109,29 @@ pd_status pd_factor(pd_ctx* c, int32_t n_workgroups, int32_t supply_rhs) {
   if (bad_ctx(c)) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
   if (!c->stale) return PD_OK;
+  if (supply_rhs < 0 || supply_rhs > 2)
+    return c->fail(PD_ERR_INVALID, "supply_rhs must be 0, 1 or 2 (got %d)", (int)supply_rhs);
+  const bool defer = supply_rhs == 1 && c->chol_dataflow != 0;
+  const bool overlap = supply_rhs == 2 && c->chol_dataflow != 0;
+  if (overlap && !c->ev_fstart) {
+    HIPCK(c, hipEventCreateWithFlags(&c->ev_fstart, hipEventDisableTiming));
+    HIPCK(c, hipEventCreateWithFlags(&c->ev_fdone, hipEventDisableTiming));
+  }
   build_H(c);
   zero_int(c->d_info, c->st);
-  const bool defer = supply_rhs != 0 && c->chol_dataflow != 0;
   {
     PhaseTimer tm(c, PD_PHASE_FACTOR);
     if (defer) {
       ++c->g_epoch;
       cholesky(c, c->d_H, c->ldH, (int)c->m, c->d_Yt, n_workgroups, c->d_gflag, c->g_epoch);
     } else {
-      cholesky(c, c->d_H, c->ldH, (int)c->m, nullptr, n_workgroups);
+      cholesky(c, c->d_H, c->ldH, (int)c->m, nullptr, n_workgroups, nullptr, 0,
+               overlap ? c->ev_fstart : nullptr);
     }
   }
+  if (overlap) HIPCK(c, hipEventRecord(c->ev_fdone, c->st));
   c->deferred = defer;
+  c->overlap = overlap;
   c->rhs_supplied = false;
   c->stale = false;
   c->lp_stale = true;             // d_H was rebuilt

@@ -27,9 +27,13 @@ void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStrea
 // equals gepoch (set with set_flag after Yt is written, e.g. on another stream).
 // cu_marks (optional): potrf_cu_slots() zero-initialised ints, the per-unit
 // marks by which tasks off the critical path yield to a diagonal task.
+// after_reset (optional): recorded once the launch epoch is advanced, before
+// the factorization kernel (work on other streams may wait for it and then
+// poll the tile flags of the running factorization).
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
                     unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
-                    const int* gflag = nullptr, int gepoch = 0, int* cu_marks = nullptr);
+                    const int* gflag = nullptr, int gepoch = 0, int* cu_marks = nullptr,
+                    hipEvent_t after_reset = nullptr);
 int potrf_cu_slots();
 void set_flag(int* f, int v, hipStream_t st);
 void rhs_pack(int n, const double* g, int ldg, double* Yt, hipStream_t st);
@@ -42,9 +46,12 @@ void copy_i32(long n, const int32_t* src, int32_t* dst, hipStream_t st);
 void trtri_from_factor(const double* L, int ldl, int n, const double* linv_ws, double* M,
                        double* X, int ldx, hipStream_t st);
 void lauum_full(const double* X, int ldx, int n, double* Z, int ldz, hipStream_t st);
+// fflags/fticket: the tile flags and ticket of a dataflow Cholesky of L still
+// running on another stream (forward solve overlapped with it), or null.
 void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const double* g,
                    int ldg, double* y, int ldy, unsigned long long* ticket, int* flags,
-                   int* err, hipStream_t st);
+                   int* err, hipStream_t st, const int* fflags = nullptr,
+                   const unsigned* fticket = nullptr);
 void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
                     int ldy, double* x, int ldx, unsigned long long* ticket, int* flags,
                     int* err, hipStream_t st);

@@ -565,10 +565,11 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
                     unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
-                    const int* gflag, int gepoch, int* cu_marks) {
+                    const int* gflag, int gepoch, int* cu_marks, hipEvent_t after_reset) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = nt * (nt + 1) / 2 + (Yt ? nt : 0);
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
+  if (after_reset) (void)hipEventRecord(after_reset, st);
   k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, sbuf, flags,
                                                           ticket, info, err, Yt,
                                                           Yt ? gflag : nullptr, gepoch, cu_marks);
@@ -819,13 +820,19 @@ __device__ inline void trsv_reduce(double (*part)[3][NB], const double* base, in
 }
 
 // L y = g.  Tile row i: y_i = Linv_ii (g_i - sum_{p<i} L_ip y_p).
+// With fflags, the factor is still being computed by a dataflow Cholesky
+// launch on another stream (its tile flags and its ticket[2], whose epoch
+// ticket[1] that launch uses): each super-row first waits until the diagonal
+// tile of its last row is published, which implies that every tile of its
+// rows and both tile inverses are final.
 template <typename T>
 __global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int ld, int n,
                                                    int nt, const T* __restrict__ linv,
                                                    const double* __restrict__ g, int ldg,
                                                    double* y, int ldy,
                                                    unsigned long long* ticket, int* flags,
-                                                   int* err) {
+                                                   int* err, const int* fflags,
+                                                   const unsigned* fticket) {
   __shared__ int s_row, s_epoch, s_ok;
   __shared__ double Ls[TR][NB][NB + 1];     // Ls[u][c][r] = Linv_{i_u}(r, c)
   __shared__ double ys[3][TR * NB];         // y of a finished super-row / of this one
@@ -843,6 +850,15 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int 
   const int sr = s_row, epoch = s_epoch;
   const int r = t & 63, cg = t >> 6;
   const int i0 = TR * sr, nu = min(TR, nt - i0);
+  if (fflags) {
+    if (t == 0) {
+      const int fe = (int)__hip_atomic_load(&fticket[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int il = i0 + nu - 1;
+      if (!df_wait(&fflags[il * nt + il], fe, err)) s_ok = 0;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+  }
   for (int u = 0; u < nu; ++u) {
     const T* Li = linv + (long)(i0 + u) * NB * NB;
     double v16[16];
@@ -1089,9 +1105,10 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const T* __restrict__ L, int 
 
 void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const double* g,
                    int ldg, double* y, int ldy, unsigned long long* ticket, int* flags,
-                   int* err, hipStream_t st) {
+                   int* err, hipStream_t st, const int* fflags, const unsigned* fticket) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_fwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err);
+  k_trsv3_fwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err,
+                                          fflags, fticket);
 }
 
 void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
@@ -1106,7 +1123,8 @@ void trsv3_forward(const float* L, int ld, int n, const float* linv_ws, const do
                    double* y, int ldy, unsigned long long* ticket, int* flags, int* err,
                    hipStream_t st) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_fwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err);
+  k_trsv3_fwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err,
+                                         nullptr, nullptr);
 }
 void trsv3_backward(const float* L, int ld, int n, const float* linv_ws, const double* y, int ldy,
                     double* x, int ldx, unsigned long long* ticket, int* flags, int* err,

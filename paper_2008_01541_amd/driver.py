@@ -98,7 +98,7 @@ class Alg1Runner:
         return infos
 
     def run_pipelined(self, n_iters, spheres_of=None, n_workgroups=0, factor_stream=None,
-                      fuse_forward=False):
+                      fuse_forward=False, overlap_forward=True):
         """n_iters outer iterations with one inner iteration each, pipelined
         over two streams.  The factorization side of iteration k (detection,
         penalties, region local step, H = S + W^T C W and its Cholesky factor)
@@ -108,9 +108,12 @@ class Alg1Runner:
         stream.  With fuse_forward the right-hand side, once assembled, is
         handed to the running factorization (pd_supply_rhs), which then also
         does the forward substitution (its tasks follow all tiles, so this only
-        pays off when the right-hand side arrives early); otherwise both
-        triangular solves follow the factorization.  The solves and the inner
-        update join both streams.  The arithmetic is that of
+        pays off when the right-hand side arrives early); with overlap_forward
+        (the default) the forward solve is enqueued on the context stream
+        without waiting for the factorization and follows its tile flags, and
+        the backward solve waits for its end; otherwise both triangular solves
+        follow the factorization.  The solves and the inner update join both
+        streams.  The arithmetic is that of
         outer_iteration(n_inner=1) (without fuse_forward the forward
         substitution is a separate solve), except that the region positions
         are carried over from the inner update instead of being gathered from
@@ -135,7 +138,8 @@ class Alg1Runner:
             c.local_step_region(self.x2, self.fb)
             ev_pen = torch.cuda.Event()          # penalties and f_beta ready
             ev_pen.record(s_fac)
-            c.factor(n_workgroups, supply_rhs=fuse_forward)
+            overlap = overlap_forward and not fuse_forward
+            c.factor(n_workgroups, supply_rhs=fuse_forward, overlap_forward=overlap)
             ev_fac = torch.cuda.Event()
             ev_fac.record(s_fac)
             # sweep side: finish iteration k - 1, start iteration k
@@ -150,7 +154,8 @@ class Alg1Runner:
             c.assemble_rhs(self.ft, self.fb, self.fcol, self.g)
             if fuse_forward:
                 c.supply_rhs(self.g)
-            s_main.wait_event(ev_fac)
+            if not overlap:
+                s_main.wait_event(ev_fac)
             c.global_solve(self.g, self.u)
             c.inner_update(self.u, self.x2, self.delta2, self.ft)
             ev_upd = torch.cuda.Event()

@@ -151,12 +151,17 @@ def test_alg1_iterations_match_oracle(torch_cuda, name, inner):
     assert worst <= 1e-9
 
 
-@pytest.mark.parametrize("name,n_wg,fuse", [("g9x7x6", 0, True), ("g16x15x8", 64, False),
-                                             ("g16x15x8", 64, True)])
-def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg, fuse):
+@pytest.mark.parametrize("name,n_wg,fuse,overlap", [("g9x7x6", 0, True, False),
+                                                     ("g16x15x8", 64, False, False),
+                                                     ("g16x15x8", 64, True, False),
+                                                     ("g16x15x8", 64, False, True),
+                                                     ("g16x15x8", 0, False, True)])
+def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg, fuse, overlap):
     """Two-stream pipelined iterations (the factorization of iteration k
-    overlapping the back substitution of k - 1 and the condensation of k)
-    against the oracle's sequential Alg. 1 with one inner iteration."""
+    overlapping the back substitution of k - 1 and the condensation of k;
+    with overlap the forward solve also runs during the factorization,
+    following its tile flags) against the oracle's sequential Alg. 1 with one
+    inner iteration."""
     from paper_2008_01541_amd.driver import Alg1Runner
     sc = SMALL_SCENES[name]()
     om = oracle_model(sc)
@@ -168,7 +173,7 @@ def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg, fuse):
         sph[f] = run.spheres
     torch_cuda.cuda.synchronize()
     run.run_pipelined(len(frames), spheres_of=lambda k: sph[frames[k]], n_workgroups=n_wg,
-                      fuse_forward=fuse)
+                      fuse_forward=fuse, overlap_forward=overlap)
     x_or = sc.rest.copy()
     for f in frames:
         det = opd.sphere_detector(om, sc.proxy_local(), sc.spheres.centers(f), sc.spheres.radii,
