@@ -507,11 +507,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
       }
       lds_product(acc, buf0, buf0);                // acc += L L^T, while the stores drain
       publish_flag(&flags[j * nt + (j - 1)], epoch);
-      // transposed copy: U(cs + r', r0 + c') = L(r0 + c', cs + r')
-      for (int e = t; e < NB * NB; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        if (c < mr) A[(long)(cs + r) + (long)(r0 + c) * lda] = buf0[r][c];
-      }
+      // (its transposed copy is written after the tile, off the critical path)
     }
     __syncthreads();
     acc_to_lds(acc, buf0, -1.0);                   // C = A_ij - sum_k L_ik L_jk^T
@@ -532,6 +528,27 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
         const int r = e & 63, c = e >> 6;
         if (r < mr && c < mr)
           A[(long)(r0 + r) + (long)(r0 + c) * lda] = (r >= c) ? buf0[c][r] : buf0[r][c];
+      }
+      if (j > 0) {
+        // transposed copy of the sub-diagonal tile finished above, read back
+        // (coalesced, coherent) and turned through LDS:
+        // U(cs + r', r0 + c') = L(r0 + c', cs + r')
+        const int cs = (j - 1) * NB;
+        {
+          const int r = t & 63;
+          double v[16];
+#pragma unroll
+          for (int qq = 0; qq < 16; ++qq)
+            v[qq] = (r < mr) ? coherent_load(&A[(long)(r0 + r) + (long)(cs + (t >> 6) + 4 * qq) * lda])
+                             : 0.0;
+#pragma unroll
+          for (int qq = 0; qq < 16; ++qq) buf1[(t >> 6) + 4 * qq][r] = v[qq];
+        }
+        __syncthreads();
+        for (int e = t; e < NB * NB; e += 256) {
+          const int r = e & 63, c = e >> 6;
+          if (c < mr) A[(long)(cs + r) + (long)(r0 + c) * lda] = buf1[r][c];
+        }
       }
     } else {
       if (t == 0 && !df_wait(&flags[j * nt + j], epoch, err)) s_ok = 0;

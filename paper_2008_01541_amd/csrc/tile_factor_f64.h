@@ -25,15 +25,14 @@ __device__ __forceinline__ double row_bcast(double v) {
 // chol16_a_updates<C>(a) -> next pivot, chol16_x_updates<C>(a, x).
 #include "chol16_steps.inc"
 
-// 1/sqrt(d): hardware estimate refined by two Newton steps y <- y (3 - d y^2) / 2.
+// 1/sqrt(d): the hardware estimate (relative error up to about 5e-8 on this
+// chip) refined by one third-order step, y <- y (1 + e/2 + 3 e^2/8) with
+// e = 1 - d y^2: four dependent operations for an error of about 2.4 ulp (two
+// Newton steps reach the same accuracy in six).
 __device__ __forceinline__ double rsqrt_newton(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const double r = fma(-0.5 * d * y, y, 0.5);
-    y = fma(y, r, y);
-  }
-  return y;
+  const double y = __builtin_amdgcn_rsq(d);
+  const double e = fma(-(d * y), y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // Right-looking elimination of one 16 x 16 block, one pivot per step C: lane
