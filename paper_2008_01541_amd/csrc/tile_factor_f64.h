@@ -110,11 +110,14 @@ __device__ inline void mma16(double4_t& acc, double (*As)[LDS_LD], int am, int a
 // factor into X (X[c][r] = inverse(r, c), zero above the diagonal).  Right-
 // looking over 16-wide block columns: wave 0 factors and inverts the diagonal
 // block, the panel below becomes P Dinv^T and the trailing blocks are updated
-// on the matrix cores; the off-diagonal blocks of the inverse follow from
-// X_ij = -X_ii sum_{p=j}^{i-1} L_ip X_pj.  A non-positive pivot stores its
-// 1-based global index gbase + j + 1 in *info (first one wins) and is replaced
-// by 1 so that the factorization stays finite.  Only the lower triangle of T
-// is meaningful on return.
+// on the matrix cores.  The off-diagonal blocks of the inverse follow from
+// X_ij = -X_ii Y_ij, Y_ij = sum_{p=j}^{i-1} L_ip X_pj; wave 1 + j owns block
+// column j of the inverse and does that work while wave 0 factors the next
+// diagonal block (the staged Y_ij waits in the X_ij slot until X_ii exists),
+// so only the last block row is left after the final diagonal block.  A
+// non-positive pivot stores its 1-based global index gbase + j + 1 in *info
+// (first one wins) and is replaced by 1 so that the factorization stays
+// finite.  Only the lower triangle of T is meaningful on return.
 __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
                                     int* info) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -125,6 +128,19 @@ __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double 
     const int jb = blk < 3 ? blk + 1 : (blk < 5 ? blk - 1 : 3);
     X[16 * jb + c][16 * ib + r] = 0.0;
   }
+  // Y_ij into the X_ij slot / X_ij = -X_ii Y_ij in place (one wave each)
+  const auto inv_stage = [&](int i, int j) {
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int p = j; p < i; ++p) mma16<true>(acc, T, 16 * i, 16 * p, X, 16 * j, 16 * p);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = acc[q];
+  };
+  const auto inv_finish = [&](int i, int j) {
+    double4_t acc = {0.0, 0.0, 0.0, 0.0};
+    mma16<true>(acc, X, 16 * i, 16 * i, X, 16 * j, 16 * i);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = -acc[q];
+  };
   if (w == 0) chol16_inverse(T, X, 0, mr, gbase, info);
   __syncthreads();
   for (int kb = 0; kb < 3; ++kb) {
@@ -150,25 +166,20 @@ __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double 
 #pragma unroll
       for (int q = 0; q < 4; ++q) T[16 * jb + (lane >> 4) + 4 * q][16 * ib + (lane & 15)] -= acc[q];
     }
-    if (w == 0) chol16_inverse(T, X, b0 + 16, mr, gbase, info);
-    __syncthreads();
-  }
-  // off-diagonal blocks of the inverse, block row by block row
-  for (int i = 1; i < 4; ++i) {
-    if (w < i) {
-      const int j = w;
-      double4_t acc = {0.0, 0.0, 0.0, 0.0};
-      for (int p = j; p < i; ++p) mma16<true>(acc, T, 16 * i, 16 * p, X, 16 * j, 16 * p);
-      // stage Y = sum_p L_ip X_pj in the X_ij slot, then X_ij = -X_ii Y
-#pragma unroll
-      for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = acc[q];
-      double4_t acc2 = {0.0, 0.0, 0.0, 0.0};
-      mma16<true>(acc2, X, 16 * i, 16 * i, X, 16 * j, 16 * i);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = -acc2[q];
+    if (w == 0) {
+      chol16_inverse(T, X, b0 + 16, mr, gbase, info);
+    } else {
+      // meanwhile, block column j = w - 1 of the inverse: finish row kb,
+      // stage row kb + 1 (the panels up to kb and X_kk are final)
+      const int j = w - 1;
+      if (j < kb) inv_finish(kb, j);
+      if (j <= kb) inv_stage(kb + 1, j);
     }
     __syncthreads();
   }
+  // last block row of the inverse: X_3j = -X_33 Y_3j
+  if (w >= 1) inv_finish(3, w - 1);
+  __syncthreads();
 }
 
 // Compute-unit courtesy.  The diagonal tasks form the critical path of the
