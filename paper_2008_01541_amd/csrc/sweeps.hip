@@ -27,15 +27,16 @@ constexpr int SLOT = 3 * TS;           // doubles per part slot: [rhs][64]
 // the wave loads its 64 x 16 block into registers (lane = row, sixteen
 // coalesced column loads in flight), adds its share of the row part Z_IJ x_J
 // in-lane, and forms the col part Z_IJ^T x_I of its sixteen columns through a
-// wave-private LDS transpose (lane = (column, row group), then two cross-lane
-// additions).  The four row-part shares are added in wave order.  Row parts go
-// to slot t(I, J) of Prow (off-diagonal tiles), col parts to slot t(I, J) of
-// Pcol.
+// wave-private LDS transpose, 32 rows at a time (lane = (column, row group),
+// then two cross-lane additions).  The four row-part shares are added in wave
+// order.  Row parts go to slot t(I, J) of Prow (off-diagonal tiles), col parts
+// to slot t(I, J) of Pcol.  26 KB of LDS per workgroup, so that the products
+// still find room next to a running factorization.
 __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z, long ldz, int w,
                                                     int nb, const double* __restrict__ x, long ldx,
                                                     double* __restrict__ Prow,
                                                     double* __restrict__ Pcol) {
-  __shared__ double Ts[4][TS][17];         // per wave: 64 rows x 16 columns (+1 pad)
+  __shared__ double Ts[4][TS / 2][17];     // per wave: 32 rows x 16 columns (+1 pad)
   __shared__ double xs[2][3][TS];          // x_J, x_I
   __shared__ double rp[4][3][TS];          // per-wave shares of the row part
   const int t = threadIdx.x, lane = t & 63;
@@ -95,22 +96,35 @@ __global__ __launch_bounds__(256) void k_sweep_symv(const double* __restrict__ Z
     s0 += z[c] * xs[0][0][c0 + c];
     s1 += z[c] * xs[0][1][c0 + c];
     s2 += z[c] * xs[0][2][c0 + c];
+    // four columns at a time: keeps the scheduler from loading all 48
+    // operands of the row part into registers at once
+    if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
   rp[wv][0][lane] = s0;
   rp[wv][1][lane] = s1;
   rp[wv][2][lane] = s2;
-  // col part of the sixteen columns: lane = (cc = lane & 15, rg = lane >> 4)
+  // col part of the sixteen columns, 32 rows at a time: lane = (cc = lane & 15, rg = lane >> 4)
   const int cc = lane & 15, rg = lane >> 4;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) Ts[wv][lane][c] = z[c];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int r = 16 * rg + q;
-    const double zz = Ts[wv][r][cc];
-    a0 += zz * xs[1][0][r];
-    a1 += zz * xs[1][1][r];
-    a2 += zz * xs[1][2][r];
+  for (int h = 0; h < 2; ++h) {
+    // the transpose goes through wave-private LDS: the wave barriers keep the
+    // compiler from moving a lane's loads across other lanes' stores
+    __builtin_amdgcn_wave_barrier();
+    if ((lane >> 5) == h) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) Ts[wv][lane & 31][c] = z[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = 8 * rg + q;
+      const double zz = Ts[wv][r][cc];
+      a0 += zz * xs[1][0][32 * h + r];
+      a1 += zz * xs[1][1][32 * h + r];
+      a2 += zz * xs[1][2][32 * h + r];
+      if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
   }
   a0 += __shfl_xor(a0, 16, 64);
   a1 += __shfl_xor(a1, 16, 64);

@@ -138,6 +138,7 @@ __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double 
   const auto inv_finish = [&](int i, int j) {
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
     mma16<true>(acc, X, 16 * i, 16 * i, X, 16 * j, 16 * i);
+    __builtin_amdgcn_wave_barrier();      // all lanes have read Y before X_ij overwrites it
 #pragma unroll
     for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = -acc[q];
   };
@@ -173,6 +174,9 @@ __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double 
       // stage row kb + 1 (the panels up to kb and X_kk are final)
       const int j = w - 1;
       if (j < kb) inv_finish(kb, j);
+      // X_{kb,j} just written by other lanes of this wave is read below: the
+      // wave barrier keeps the compiler from moving loads across those stores
+      __builtin_amdgcn_wave_barrier();
       if (j <= kb) inv_stage(kb + 1, j);
     }
     __syncthreads();
