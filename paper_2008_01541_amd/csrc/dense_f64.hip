@@ -836,6 +836,31 @@ __device__ inline void trsv_reduce(double (*part)[3][NB], const double* base, in
   }
 }
 
+// Loads of a column panel of a column-major matrix through a buffer
+// descriptor: the row goes in the lane offset, the column (relative to the
+// panel's first one) in the scalar offset, so that a load needs no 64-bit
+// address registers.  Byte offsets stay below 2^32 within a panel.
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t panel_rsrc(const T* L, long ld, int col0, int ncol) {
+  const unsigned long long b = reinterpret_cast<unsigned long long>(L + (long)col0 * ld);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  const unsigned long long bytes = (unsigned long long)ncol * ld * sizeof(T);
+  const unsigned nrec = bytes < 0xffffffffull ? (unsigned)bytes : 0xffffffffu;
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo),
+                                           0, (int)__builtin_amdgcn_readfirstlane(nrec), 0x00020000);
+}
+template <typename T>
+__device__ inline T panel_load(__amdgpu_buffer_rsrc_t rs, int voff, int soff);
+template <>
+__device__ inline double panel_load<double>(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+template <>
+__device__ inline float panel_load<float>(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+
 // L y = g.  Tile row i: y_i = Linv_ii (g_i - sum_{p<i} L_ip y_p).
 // With fflags, the factor is still being computed by a dataflow Cholesky
 // launch on another stream (its tile flags and its ticket[2], whose epoch
@@ -843,7 +868,7 @@ __device__ inline void trsv_reduce(double (*part)[3][NB], const double* base, in
 // tile of its last row is published, which implies that every tile of its
 // rows and both tile inverses are final.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int ld, int n,
+__global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, int ld, int n,
                                                    int nt, const T* __restrict__ linv,
                                                    const double* __restrict__ g, int ldg,
                                                    double* y, int ldy,
@@ -866,6 +891,7 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int 
   __syncthreads();
   const int sr = s_row, epoch = s_epoch;
   const int r = t & 63, cg = t >> 6;
+  const int cgs = __builtin_amdgcn_readfirstlane(cg);    // cg is uniform per wave
   const int i0 = TR * sr, nu = min(TR, nt - i0);
   if (fflags) {
     if (t == 0) {
@@ -903,19 +929,21 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int 
     // the four operand tiles L_{i_u, TR q + u'} (16 columns each) load while the flag is awaited
     // unconditional loads from a clamped row, then a select: no branch per
     // load, so all of them are in flight together
+    // (rows past the edge re-read row 0 and are masked by a multiply, so no
+    // load is put under a branch)
     T lv[TR][TR][16];
+    const __amdgpu_buffer_rsrc_t prs = panel_rsrc(L, ld, TR * q * NB, TR * NB);
 #pragma unroll
     for (int u = 0; u < TR; ++u) {
       const int ru = (i0 + u) * NB + r;
       const bool ok = u < nu && ru < n;
-      const T* Lr = L + (ok ? ru : 0) + (long)(TR * q * NB + cg * 16) * ld;
+      const int voff = (ok ? ru : 0) * (int)sizeof(T);
 #pragma unroll
       for (int w = 0; w < TR; ++w)
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const T v = Lr[(long)(w * NB + c) * ld];
-          lv[u][w][c] = ok ? v : T(0);
-        }
+        for (int c = 0; c < 16; ++c)
+          lv[u][w][c] = panel_load<T>(prs, voff, (w * NB + cgs * 16 + c) * ld * (int)sizeof(T)) *
+                        (ok ? T(1) : T(0));
     }
     if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
     __syncthreads();
@@ -925,17 +953,22 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int 
       ys[v][cc] = coherent_load(&y[(long)v * ldy + TR * q * NB + cc]);
     }
     __syncthreads();
+    // each operand of ys is read once and used for every tile row; four
+    // columns at a time, so that the operands are not all held at once
 #pragma unroll
-    for (int u = 0; u < TR; ++u)
+    for (int w = 0; w < TR; ++w)
 #pragma unroll
-      for (int w = 0; w < TR; ++w)
+      for (int c = 0; c < 16; ++c) {
+        const int col = w * NB + cg * 16 + c;
+        const double y0 = ys[0][col], y1 = ys[1][col], y2 = ys[2][col];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const int col = w * NB + cg * 16 + c;
-          acc[u][0] += (double)lv[u][w][c] * ys[0][col];
-          acc[u][1] += (double)lv[u][w][c] * ys[1][col];
-          acc[u][2] += (double)lv[u][w][c] * ys[2][col];
+        for (int u = 0; u < TR; ++u) {
+          acc[u][0] += (double)lv[u][w][c] * y0;
+          acc[u][1] += (double)lv[u][w][c] * y1;
+          acc[u][2] += (double)lv[u][w][c] * y2;
         }
+        if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
     __syncthreads();
   }
   // finish the tile rows of this super-row in order
@@ -987,7 +1020,7 @@ __global__ __launch_bounds__(256) void k_trsv3_fwd(const T* __restrict__ L, int 
 // L^T x = y, reading L^T from the upper triangle (U(r, c) = L(c, r) for c > r):
 // x_i = Linv_ii^T (y_i - sum_{p>i} U_ip x_p).  Super-rows from the bottom.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsv3_bwd(const T* __restrict__ L, int ld, int n,
+__global__ __launch_bounds__(256, 2) void k_trsv3_bwd(const T* __restrict__ L, int ld, int n,
                                                    int nt, const T* __restrict__ linv,
                                                    const double* __restrict__ y, int ldy,
                                                    double* x, int ldx,
@@ -1009,6 +1042,7 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const T* __restrict__ L, int 
   __syncthreads();
   const int sr = s_row, epoch = s_epoch;
   const int r = t & 63, cg = t >> 6;
+  const int cgs = __builtin_amdgcn_readfirstlane(cg);    // cg is uniform per wave
   const int i0 = TR * sr, nu = min(TR, nt - i0);
   for (int u = 0; u < nu; ++u) {
     const T* Li = linv + (long)(i0 + u) * NB * NB;
@@ -1038,18 +1072,22 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const T* __restrict__ L, int 
   for (int u = 0; u < TR; ++u) acc[u][0] = acc[u][1] = acc[u][2] = 0.0;
   for (int q = ns - 1; q > sr; --q) {
     T lv[TR][TR][16];
+    const int pc0 = TR * q * NB;
+    const __amdgpu_buffer_rsrc_t prs = panel_rsrc(L, ld, pc0, min(TR * NB, n - pc0));
 #pragma unroll
     for (int u = 0; u < TR; ++u) {
       const int ru = (i0 + u) * NB + r;
       const bool okr = u < nu && ru < n;
-      const T* Lr = L + (okr ? ru : 0);
+      const int voff = (okr ? ru : 0) * (int)sizeof(T);
 #pragma unroll
       for (int w = 0; w < TR; ++w)
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          const int col = (TR * q + w) * NB + cg * 16 + c;
-          // a multiply, not a select, so that the load is not put under a branch
-          lv[u][w][c] = Lr[(long)min(col, n - 1) * ld] * ((okr && col < n) ? T(1) : T(0));
+          const int col = (TR * q + w) * NB + cgs * 16 + c;
+          // columns past the edge re-read the last one; a multiply, not a
+          // select, masks them, so that the load is not put under a branch
+          lv[u][w][c] = panel_load<T>(prs, voff, (min(col, n - 1) - pc0) * ld * (int)sizeof(T)) *
+                        ((okr && col < n) ? T(1) : T(0));
         }
     }
     if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
@@ -1061,17 +1099,22 @@ __global__ __launch_bounds__(256) void k_trsv3_bwd(const T* __restrict__ L, int 
       xs[v][cc] = (cc < qn) ? coherent_load(&x[(long)v * ldx + TR * q * NB + cc]) : 0.0;
     }
     __syncthreads();
+    // each operand of xs is read once and used for every tile row; four
+    // columns at a time, so that the operands are not all held at once
 #pragma unroll
-    for (int u = 0; u < TR; ++u)
+    for (int w = 0; w < TR; ++w)
 #pragma unroll
-      for (int w = 0; w < TR; ++w)
+      for (int c = 0; c < 16; ++c) {
+        const int col = w * NB + cg * 16 + c;
+        const double y0 = xs[0][col], y1 = xs[1][col], y2 = xs[2][col];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          const int col = w * NB + cg * 16 + c;
-          acc[u][0] += (double)lv[u][w][c] * xs[0][col];
-          acc[u][1] += (double)lv[u][w][c] * xs[1][col];
-          acc[u][2] += (double)lv[u][w][c] * xs[2][col];
+        for (int u = 0; u < TR; ++u) {
+          acc[u][0] += (double)lv[u][w][c] * y0;
+          acc[u][1] += (double)lv[u][w][c] * y1;
+          acc[u][2] += (double)lv[u][w][c] * y2;
         }
+        if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+      }
     __syncthreads();
   }
   for (int u = nu - 1; u >= 0; --u) {
