@@ -304,3 +304,36 @@ def test_slit_self_contact_alg1_matches_oracle(torch_cuda):
             worst = max(worst, np.abs(run.positions() - x_or).max() / scale)
     assert active > 0                                  # the lips did collide
     assert worst <= 1e-9
+
+
+def test_factor_modes(torch_cuda):
+    """pd_factor rejects unknown modes before enqueuing anything, and a factor
+    started in mode 2 (forward solve allowed to overlap it) gives the same
+    solve, bit for bit, as mode 0 (the same solve kernels) on one stream."""
+    sc = SMALL_SCENES["g16x15x8"]()
+    ctx = gpu_context(sc)
+    m = ctx.m
+    rng = np.random.default_rng(5)
+    sel = rng.choice(m, size=12, replace=False)
+    idx = np.full((12, 8), -1, dtype=np.int32)
+    idx[:, 0] = sel
+    w = np.zeros((12, 8)); w[:, 0] = 1.0
+    c = np.full(12, 1e6)
+    t = rng.normal(size=(3, 12))
+    x2 = dev(np.zeros((3, m)))
+    fcol = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    g = dev(rng.normal(size=(3, m)))
+    u_ref = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    u_ovl = torch_cuda.empty_like(u_ref)
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), x2, fcol)
+    ctx.factor()                                   # mode 0: both solves after the factor
+    ctx.global_solve(g, u_ref)
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), x2, fcol)    # factor stale again
+    from paper_2008_01541_amd import PDError
+    assert ctx._lib.pd_factor(ctx._ctx, 0, 3) == -1
+    with pytest.raises(PDError):
+        ctx._chk(ctx._lib.pd_factor(ctx._ctx, 0, -1))
+    ctx.factor(overlap_forward=True)
+    ctx.global_solve(g, u_ovl)
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(u_ref, u_ovl)
