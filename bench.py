@@ -138,6 +138,55 @@ def precision_modes(run, spheres, inner, iters=6):
     return res
 
 
+def warmstart_leg(run, args):
+    """Learned warm start on the slab: the network (4m -> 512 -> 512 -> 3m) is
+    trained on frames the plain FP64 solver generates along seeded sphere
+    trajectories, then cold start (previous converged state) and warm start
+    are compared frame by frame on a held-out trajectory: outer iterations
+    to ||x_k - x_{k-1}|| <= 1e-6 ||x_k - X|| and wall time per frame.  The
+    cold result judges every warm one (replaced if further than 1e-6)."""
+    import torch
+    import pd_inputs as P
+    from paper_2008_01541_amd.warmstart import WarmStart, evaluate, generate_trajectory
+    try:
+        t0 = time.perf_counter()
+        Xs, Ys = [], []
+        for k in range(args.ws_train):
+            tr = P.slab56_trajectory(100 + k)
+            X, Y, it = generate_trajectory(run, tr.centers, tr.radii, n_frames=args.ws_frames, tol=1e-6)
+            Xs.append(X)
+            Ys.append(Y)
+            print(f"warm start: training trajectory {k + 1}/{args.ws_train}, "
+                  f"{np.mean(it):.1f} outer iterations per frame", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        gen_s = time.perf_counter() - t0
+        X, Y = torch.cat(Xs), torch.cat(Ys)
+        ws = WarmStart(run.ctx.m, hidden=512, seed=4, max_batch=32)
+        t0 = time.perf_counter()
+        hist = ws.train(X, Y, epochs=args.ws_epochs, lr=1e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        tr = P.slab56_trajectory(999)
+        rows = evaluate(run, ws, tr.centers, tr.radii, n_frames=args.ws_frames, tol=1e-6)
+        warm = [r for r in rows if "warm_iters" in r]
+        cold_it = float(np.mean([r["cold_iters"] for r in warm]))
+        warm_it = float(np.mean([r["warm_iters"] for r in warm]))
+        cold_s = float(sum(r["cold_s"] for r in warm))
+        warm_s = float(sum(r["warm_s"] for r in warm))
+        return {"train_frames": int(X.shape[0]), "train_trajectories": args.ws_train,
+                "epochs": args.ws_epochs, "loss_first": hist[0], "loss_last": hist[-1],
+                "generate_s": round(gen_s, 2), "train_s": round(train_s, 2),
+                "eval_frames": len(warm),
+                "cold_outer_iters_per_frame": cold_it, "warm_outer_iters_per_frame": warm_it,
+                "iters_saved_frac": 1.0 - warm_it / cold_it if cold_it > 0 else None,
+                "cold_frames_per_s": len(warm) / cold_s, "warm_frames_per_s": len(warm) / warm_s,
+                "wall_saved_frac": 1.0 - warm_s / cold_s,
+                "fell_back": int(sum(1 for r in warm if r.get("fell_back"))),
+                "rel_diff_max": float(max(r["rel_diff"] for r in warm))}
+    except Exception as e:              # report, do not hide, a failing leg
+        return {"error": str(e)}
+
+
 def bench_slit(args):
     """Self-contact stress workload: 64 x 64 x 40 slit grid (983,040 tets,
     176,215 nodes, 12,155-node region, 2,990 lip pairs), jaw closing over the
@@ -199,6 +248,11 @@ def main():
     ap.add_argument("--inner", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-modes", action="store_true")
+    ap.add_argument("--warmstart", action="store_true",
+                    help="add the learned warm-start leg (train, then cold vs warm frames; ~2 min)")
+    ap.add_argument("--ws-train", type=int, default=3, help="warm start: training trajectories")
+    ap.add_argument("--ws-frames", type=int, default=24, help="warm start: frames per trajectory")
+    ap.add_argument("--ws-epochs", type=int, default=40, help="warm start: training epochs")
     ap.add_argument("--workload", default="slab56", choices=["slab56", "slit64"],
                     help="slab56: the 602K-tet slab with spheres (default); slit64: the "
                          "983K-tet self-contact slit closed by a jaw rotation")
@@ -350,6 +404,8 @@ def main():
     }
     if not args.no_precision_modes:
         out["precision_modes"] = precision_modes(run, sph[frames[-1]], args.inner)
+    if args.warmstart:
+        out["warm_start"] = warmstart_leg(run, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, frames[-1])
     print(json.dumps(out))

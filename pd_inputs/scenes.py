@@ -126,6 +126,20 @@ def scene_slab56(seed=2, drift=False):
                        outer_iters=10, inner_iters=1, steps=100)
 
 
+def slab56_trajectory(seed):
+    """Sphere trajectory on the 56 x 56 x 32 slab for the learned warm start:
+    16 spheres (centres U[8,48]^2, radius U[0.5,2]) pressed in at
+    depth_i(s) = d_i r_i s / 40 with d_i ~ U[0.2,0.8], each drifting
+    laterally U[-0.2,0.2]^2 per frame; frames s = 1, 2, ... ."""
+    rng = np.random.default_rng(seed)
+    ns = 16
+    xy = rng.uniform(8.0, 48.0, size=(2, ns))
+    r = rng.uniform(0.5, 2.0, size=ns)
+    d = rng.uniform(0.2, 0.8, size=ns)
+    dr = rng.uniform(-0.2, 0.2, size=(2, ns))
+    return SphereSchedule(base_xy=xy, radii=r, top_z=32.0, depth_rate=d * r / 40.0, drift=dr)
+
+
 def scene_small(nx, ny, nz, h=1.0, region_top_layers=2, seed=7, n_spheres=2,
                 depth_frac=0.02, k_pen=1.0e6):
     """Small grids for exhaustive checks: region = the top `region_top_layers`
