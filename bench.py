@@ -265,8 +265,8 @@ def main():
                          "(fewer than 2 per CU leave room for the overlapped sweeps)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="time only the single-stream iterations")
-    ap.add_argument("--graph", action="store_true",
-                    help="also time replays of a HIP graph of one iteration (experimental)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip timing replays of a HIP graph of one outer iteration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the hot path "
@@ -335,29 +335,31 @@ def main():
         pipe_value = args.steps / (t1 - t0)
         value = max(value, pipe_value)
     graph_value = None
-    if args.graph:
+    graph_error = None
+    if not args.no_graph:
         # one outer iteration captured into a HIP graph; frames change by
         # copying the next sphere positions into the captured input buffer
-        sph_buf = run.spheres.clone()
-        run.spheres = sph_buf
-        x_save = run.x.clone()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream):
-            run.outer_iteration(n_inner=args.inner)
-        torch.cuda.synchronize()
-        run.x.copy_(x_save)
-        for it in range(args.warmup):
-            sph_buf.copy_(sph[frames[it]])
-            g.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for it in range(args.warmup, nit):
-            sph_buf.copy_(sph[frames[it]])
-            g.replay()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        graph_value = args.steps / (t1 - t0)
-        value = max(value, graph_value)
+        try:
+            sph_buf = run.spheres.clone()
+            run.spheres = sph_buf
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                run.outer_iteration(n_inner=args.inner)
+            torch.cuda.synchronize()
+            for it in range(args.warmup):
+                sph_buf.copy_(sph[frames[it]])
+                g.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for it in range(args.warmup, nit):
+                sph_buf.copy_(sph[frames[it]])
+                g.replay()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            graph_value = args.steps / (t1 - t0)
+            value = max(value, graph_value)
+        except Exception as e:          # report, do not hide, a failing leg
+            graph_error = str(e)
     ms_per_step = 1e3 / value
     m = ctx.m
     fac_ms, fac_n = tim["factor"]
@@ -390,6 +392,7 @@ def main():
         "pipelined_factor_workgroups": None if args.no_pipeline else args.factor_wg,
         "pipelined_forward_overlapped": None if args.no_pipeline else not args.no_overlap_forward,
         "graph_pd_iters_per_s": graph_value,
+        **({"graph_error": graph_error} if graph_error else {}),
         "schur_cholesky_tflops": chol_tflops,
         "schur_cholesky_ms": fac_avg,
         "inner_iteration_ms": inner_ms,

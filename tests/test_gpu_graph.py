@@ -9,9 +9,6 @@ import pd_inputs as P
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.skip(reason="replays of a torch.cuda.graph capture of one outer iteration "
-                         "deviate from eager execution by ~2e-3 (deterministic); cause not yet "
-                         "found, so the benchmark times eager launches only")
 def test_graph_replay_matches_eager():
     import torch
     from paper_2008_01541_amd.driver import Alg1Runner
