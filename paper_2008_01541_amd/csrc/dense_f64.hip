@@ -252,13 +252,8 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const long kc = (long)(k * NB + kq + 4 * q);
-#ifdef PD_COHERENT_OPERAND_LOADS
-      ra[q] = (r < mr) ? coherent_load(&Ar[(long)(r0 + r) + kc * ldar]) : 0.0;
-      rb[q] = (r < mc) ? coherent_load(&A[(long)(c0 + r) + kc * lda]) : 0.0;
-#else
       ra[q] = (r < mr) ? Ar[(long)(r0 + r) + kc * ldar] : 0.0;
       rb[q] = (r < mc) ? A[(long)(c0 + r) + kc * lda] : 0.0;
-#endif
     }
   };
   int fi = 0, fj = 0;          // thread 0: flags of the next step, read ahead
