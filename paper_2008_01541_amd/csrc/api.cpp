@@ -119,6 +119,9 @@ struct pd_ctx {
   double *d_pw = nullptr, *d_pc = nullptr, *d_pt = nullptr;
   int32_t* d_pact = nullptr;          // active penalties (c != 0), increasing
   int32_t* d_pnact = nullptr;         // their count (device)
+  int32_t* d_prow = nullptr;          // incidence of the active slots on region rows: row pointers
+  int32_t* d_pcur = nullptr;          // (m + 1), cursors (m), keys (8 per penalty)
+  int32_t* d_pent = nullptr;
   bool stale = true;
 
   // optional per-phase timing with HIP events recorded on the stream
@@ -740,12 +743,15 @@ pd_status ensure_pen_cap(pd_ctx* c, int32_t n) {
   if (n <= c->pen_cap) return PD_OK;
   int32_t cap = std::max<int32_t>(n, 2 * c->pen_cap);
   for (void* p : {(void*)c->d_pidx, (void*)c->d_pw, (void*)c->d_pc, (void*)c->d_pt,
-                  (void*)c->d_pact})
+                  (void*)c->d_pact, (void*)c->d_pent})
     if (p) {
       HIPCK(c, hipStreamSynchronize(c->st));
       free_now(c, p);
     }
   if (!c->d_pnact) CK(c->alloc(&c->d_pnact, 1));
+  if (!c->d_prow) CK(c->alloc(&c->d_prow, c->m + 1));
+  if (!c->d_pcur) CK(c->alloc(&c->d_pcur, std::max<int64_t>(c->m, 1)));
+  CK(c->alloc(&c->d_pent, 8 * (int64_t)cap));
   CK(c->alloc(&c->d_pact, cap));
   CK(c->alloc(&c->d_pidx, 8 * (int64_t)cap));
   CK(c->alloc(&c->d_pw, 8 * (int64_t)cap));
@@ -916,8 +922,9 @@ pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, cons
     copy_f64(3 * (long)n_pen, t, c->d_pt, c->st);
   }
   c->n_pen = n_pen;
-  compact_active(n_pen, c->d_pc, c->d_pact, c->d_pnact, c->st);
-  penalty_apply(n_pen, c->d_pact, c->d_pnact, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 1.0, x2,
+  penalty_prepare(n_pen, (int)c->m, c->d_pc, c->d_pidx, c->d_pact, c->d_pnact, c->d_prow,
+                  c->d_pcur, c->d_pent, c->st);
+  penalty_apply(n_pen, c->d_pact, c->d_prow, c->d_pent, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 1.0, x2,
                 (int)c->m, nullptr, 0, f_col, c->st);
   c->stale = true;
   c->lp_stale = true;
@@ -957,8 +964,8 @@ void build_H(pd_ctx* c) {
   PhaseTimer tm(c, PD_PHASE_HBUILD);
   copy_lower_tiles(c->d_S, m, c->d_H, c->ldH, m, c->st);
   if (c->n_pen > 0)
-    penalty_apply(c->n_pen, c->d_pact, c->d_pnact, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0,
-                  nullptr, m, c->d_H, c->ldH, nullptr, c->st);
+    penalty_apply(c->n_pen, c->d_pact, c->d_prow, c->d_pent, c->d_pidx, c->d_pw, c->d_pc, c->d_pt,
+                  0.0, nullptr, m, c->d_H, c->ldH, nullptr, c->st);
 }
 
 // res = g - (S + P) u in FP64; returns max over columns of ||res|| / ||g|| (synchronizes).
@@ -967,8 +974,8 @@ pd_status residual(pd_ctx* c, const double* g, const double* u, double* rel) {
   HIPCK(c, hipMemcpyAsync(c->d_res, g, 3 * (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   symv3(c->d_S, m, m, u, m, -1.0, 1.0, c->d_res, m, c->st);
   if (c->n_pen > 0) {
-    penalty_apply(c->n_pen, c->d_pact, c->d_pnact, c->d_pidx, c->d_pw, c->d_pc, c->d_pt, 0.0, u, m,
-                  nullptr, 0, c->d_y, c->st);
+    penalty_apply(c->n_pen, c->d_pact, c->d_prow, c->d_pent, c->d_pidx, c->d_pw, c->d_pc, c->d_pt,
+                  0.0, u, m, nullptr, 0, c->d_y, c->st);
     axpy3_sum(m, c->d_res, c->d_y, nullptr, c->d_res, c->st);
   }
   colnorm2_3(m, c->d_res, c->d_norms, c->st);

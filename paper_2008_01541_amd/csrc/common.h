@@ -121,14 +121,19 @@ void detect_spheres(int n_prox, const int32_t* prox, int n_sph, const double* sp
                     hipStream_t st);
 void detect_pairs(int n_pairs, const int32_t* pairs, double k, const double* x2, int m,
                   int32_t* idx, double* w, double* c, double* t, hipStream_t st);
-// act[0..*cnt) <- indices j < n_pen with c[j] != 0, increasing (device count).
-void compact_active(int n_pen, const double* c, int32_t* act, int32_t* cnt, hipStream_t st);
-// Over the active penalties act[0..*nact):
+// act[0..*cnt) <- indices j < n_pen with c[j] != 0, increasing (device count);
+// rowptr (m + 1) and ent (8 n_pen) <- for every region row a, the keys 8 q + s
+// of the active slots naming it (act[q], slot s), increasing; cursor: m ints
+// of scratch.
+void penalty_prepare(int n_pen, int m, const double* c, const int32_t* idx, int32_t* act,
+                     int32_t* cnt, int32_t* rowptr, int32_t* cursor, int32_t* ent, hipStream_t st);
+// Over the active penalties, through the incidence built by penalty_prepare:
 // row a of H (lower part) += (W^T C W)[a, :]  when H != NULL;
 // fcol[:, a] = -(W^T C (W x2 - tscale * t))[a]  when fcol != NULL.
-void penalty_apply(int n_pen, const int32_t* act, const int32_t* nact, const int32_t* idx,
-                   const double* w, const double* c, const double* t, double tscale,
-                   const double* x2, int m, double* H, int ldh, double* fcol, hipStream_t st);
+void penalty_apply(int n_pen, const int32_t* act, const int32_t* rowptr, const int32_t* ent,
+                   const int32_t* idx, const double* w, const double* c, const double* t,
+                   double tscale, const double* x2, int m, double* H, int ldh, double* fcol,
+                   hipStream_t st);
 // out = (sum ||x - xp||^2, sum ||x - X||^2) over the listed nodes (device, 2 doubles).
 void change_norms(int64_t cnt, const int32_t* ids, const double* x, const double* xp,
                   const double* X, int64_t n, double* out, hipStream_t st);

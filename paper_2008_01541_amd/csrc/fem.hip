@@ -505,40 +505,94 @@ void detect_spheres(int n_prox, const int32_t* prox, int n_sph, const double* sp
                                                      c, t);
 }
 
-// Active-penalty list: act[0..cnt) = indices j with c[j] != 0 in increasing
-// order (one workgroup, block-wide prefix sums; deterministic).
-__global__ __launch_bounds__(1024) void k_compact_active(int n_pen, const double* __restrict__ c,
-                                                         int32_t* __restrict__ act,
-                                                         int32_t* __restrict__ cnt) {
-  __shared__ int32_t wsum[16];
-  __shared__ int32_t base;
+// Active penalties and their incidence on the region rows, one workgroup
+// (block-wide prefix sums; deterministic):
+//  * act[0..*cnt) = indices j < n_pen with c[j] != 0, increasing;
+//  * ent[rowptr[a] .. rowptr[a + 1]) = keys 8 q + s of the slots s of the
+//    active penalties act[q] that name region row a, increasing.
+// Counts and cursors live in cursor[] (global; read back with L1-bypassing
+// atomic loads after the atomic updates); the fill order of a row is then
+// fixed by sorting its keys.
+__device__ inline int block_exclusive_scan(int v, int* wsum, int* total) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  if (t == 0) base = 0;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(x, o, 64);
+    if (lane >= o) x += u;
+  }
+  __syncthreads();                         // wsum may still be read by a previous call
+  if (lane == 63) wsum[w] = x;
   __syncthreads();
+  int off = 0, tot = 0;
+  for (int q = 0; q < 16; ++q) {
+    if (q < w) off += wsum[q];
+    tot += wsum[q];
+  }
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ __launch_bounds__(1024) void k_penalty_prepare(int n_pen, int m, const double* __restrict__ c,
+                                                          const int32_t* __restrict__ idx,
+                                                          int32_t* __restrict__ act,
+                                                          int32_t* __restrict__ cnt,
+                                                          int32_t* __restrict__ rowptr,
+                                                          int32_t* cursor, int32_t* ent) {
+  __shared__ int32_t wsum[16];
+  const int t = threadIdx.x;
+  // active list
+  int na = 0;
   for (int j0 = 0; j0 < n_pen; j0 += 1024) {
     const int j = j0 + t;
     const int f = (j < n_pen && c[j] != 0.0) ? 1 : 0;
-    // inclusive scan inside the wave
-    int v = f;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int u = __shfl_up(v, o, 64);
-      if (lane >= o) v += u;
-    }
-    if (lane == 63) wsum[w] = v;
-    __syncthreads();
-    int off = base;
-    for (int q = 0; q < w; ++q) off += wsum[q];
-    if (f) act[off + v - 1] = j;
-    __syncthreads();
-    if (t == 0) {
-      int tot = 0;
-      for (int q = 0; q < 16; ++q) tot += wsum[q];
-      base += tot;
-    }
-    __syncthreads();
+    int tot;
+    const int pos = block_exclusive_scan(f, wsum, &tot);
+    if (f) act[na + pos] = j;
+    na += tot;
   }
-  if (t == 0) *cnt = base;
+  if (t == 0) *cnt = na;
+  // per-row counts
+  for (int a = t; a < m; a += 1024) __hip_atomic_store(&cursor[a], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  for (int e = t; e < 8 * na; e += 1024) {
+    const int r = idx[(int64_t)act[e >> 3] * 8 + (e & 7)];
+    if (r >= 0 && r < m) atomicAdd(&cursor[r], 1);
+  }
+  __syncthreads();
+  // row pointers; the cursors restart at the row starts
+  int base = 0;
+  for (int a0 = 0; a0 < m; a0 += 1024) {
+    const int a = a0 + t;
+    const int v = a < m ? __hip_atomic_load(&cursor[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    int tot;
+    const int pos = block_exclusive_scan(v, wsum, &tot);
+    if (a < m) {
+      rowptr[a] = base + pos;
+      __hip_atomic_store(&cursor[a], base + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    base += tot;
+  }
+  if (t == 0) rowptr[m] = base;
+  __syncthreads();
+  // fill, then order each row's keys
+  for (int e = t; e < 8 * na; e += 1024) {
+    const int r = idx[(int64_t)act[e >> 3] * 8 + (e & 7)];
+    if (r >= 0 && r < m) ent[atomicAdd(&cursor[r], 1)] = e;
+  }
+  __syncthreads();
+  for (int a = t; a < m; a += 1024) {
+    const int e0 = rowptr[a], e1 = rowptr[a + 1];
+    for (int i = e0 + 1; i < e1; ++i) {
+      const int key = ent[i];
+      int k = i - 1;
+      while (k >= e0 && ent[k] > key) {
+        ent[k + 1] = ent[k];
+        --k;
+      }
+      ent[k + 1] = key;
+    }
+  }
 }
 
 // Two-sided contact of paired region nodes (a = lower lip, b = upper lip):
@@ -574,93 +628,73 @@ void detect_pairs(int n_pairs, const int32_t* pairs, double k, const double* x2,
 }
 
 // Penalty terms, one thread per region node a (row a of W^T C W and entry a
-// of f_col), scanning the active penalties in increasing index order:
+// of f_col), over the active slots that name a (its incidence list, in
+// increasing penalty order):
 //   H[a + b*ldh] += c_j w_ja w_jb  for b <= a   (lower triangle, H may be NULL)
 //   fcol[:, a]    = -sum_j c_j w_ja (W_j x2 - tscale t_j)
-constexpr int PCH = 128;
-__global__ __launch_bounds__(256) void k_penalty_apply(int n_pen, const int32_t* __restrict__ act,
-                                                       const int32_t* __restrict__ nact,
-                                                       const int32_t* __restrict__ idx,
-                                                       const double* __restrict__ w,
-                                                       const double* __restrict__ c,
-                                                       const double* __restrict__ t,
-                                                       double tscale,
-                                                       const double* __restrict__ x2, int m,
-                                                       double* H, int ldh, double* fcol) {
-  __shared__ int32_t si[PCH][8];
-  __shared__ double sw[PCH][8];
-  __shared__ double sc[PCH];
-  __shared__ double sr[3][PCH];
+__global__ __launch_bounds__(64) void k_penalty_apply(int n_pen, const int32_t* __restrict__ act,
+                                                      const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ ent,
+                                                      const int32_t* __restrict__ idx,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ c,
+                                                      const double* __restrict__ t,
+                                                      double tscale,
+                                                      const double* __restrict__ x2, int m,
+                                                      double* H, int ldh, double* fcol) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  const int na = *nact;
+  if (a >= m) return;
   double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-  for (int base = 0; base < na; base += PCH) {
-    const int cnt = min(PCH, na - base);
-    __syncthreads();
-    for (int e = threadIdx.x; e < cnt * 8; e += blockDim.x) {
-      const int j = act[base + (e >> 3)];
-      si[e >> 3][e & 7] = idx[(int64_t)j * 8 + (e & 7)];
-      sw[e >> 3][e & 7] = w[(int64_t)j * 8 + (e & 7)];
-    }
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) sc[e] = c[act[base + e]];
-    __syncthreads();
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+  const int e1 = rowptr[a + 1];
+  for (int e = rowptr[a]; e < e1; ++e) {
+    const int key = ent[e];
+    const int j = act[key >> 3], s = key & 7;
+    const int32_t* ij = idx + (int64_t)j * 8;
+    const double* wj = w + (int64_t)j * 8;
+    const double coef = c[j] * wj[s];
+    if (fcol) {
       double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-      if (fcol) {
-        const int j = act[base + e];
-        for (int s = 0; s < 8; ++s) {
-          const int b = si[e][s];
-          if (b < 0 || b >= m) continue;
-          const double ws = sw[e][s];
-          r0 += ws * x2[b];
-          r1 += ws * x2[m + b];
-          r2 += ws * x2[2 * m + b];
-        }
-        r0 -= tscale * t[j];
-        r1 -= tscale * t[n_pen + j];
-        r2 -= tscale * t[2 * n_pen + j];
+      for (int sb = 0; sb < 8; ++sb) {
+        const int b = ij[sb];
+        if (b < 0 || b >= m) continue;
+        const double ws = wj[sb];
+        r0 += ws * x2[b];
+        r1 += ws * x2[m + b];
+        r2 += ws * x2[2 * m + b];
       }
-      sr[0][e] = r0;
-      sr[1][e] = r1;
-      sr[2][e] = r2;
+      r0 -= tscale * t[j];
+      r1 -= tscale * t[n_pen + j];
+      r2 -= tscale * t[2 * n_pen + j];
+      f0 -= coef * r0;
+      f1 -= coef * r1;
+      f2 -= coef * r2;
     }
-    __syncthreads();
-    if (a < m) {
-      for (int jj = 0; jj < cnt; ++jj) {
-        const double cj = sc[jj];
-        for (int s = 0; s < 8; ++s) {
-          if (si[jj][s] != a) continue;
-          const double coef = cj * sw[jj][s];
-          f0 -= coef * sr[0][jj];
-          f1 -= coef * sr[1][jj];
-          f2 -= coef * sr[2][jj];
-          if (H) {
-            for (int sb = 0; sb < 8; ++sb) {
-              const int b = si[jj][sb];
-              if (b >= 0 && b <= a) H[(int64_t)a + (int64_t)b * ldh] += coef * sw[jj][sb];
-            }
-          }
-        }
+    if (H) {
+      for (int sb = 0; sb < 8; ++sb) {
+        const int b = ij[sb];
+        if (b >= 0 && b <= a) H[(int64_t)a + (int64_t)b * ldh] += coef * wj[sb];
       }
     }
   }
-  if (a < m && fcol) {
+  if (fcol) {
     fcol[a] = f0;
     fcol[m + a] = f1;
     fcol[2 * m + a] = f2;
   }
 }
 
-void compact_active(int n_pen, const double* c, int32_t* act, int32_t* cnt, hipStream_t st) {
-  k_compact_active<<<1, 1024, 0, st>>>(n_pen, c, act, cnt);
+void penalty_prepare(int n_pen, int m, const double* c, const int32_t* idx, int32_t* act,
+                     int32_t* cnt, int32_t* rowptr, int32_t* cursor, int32_t* ent, hipStream_t st) {
+  k_penalty_prepare<<<1, 1024, 0, st>>>(n_pen, m, c, idx, act, cnt, rowptr, cursor, ent);
 }
 
-void penalty_apply(int n_pen, const int32_t* act, const int32_t* nact, const int32_t* idx,
-                   const double* w, const double* c, const double* t, double tscale,
-                   const double* x2, int m, double* H, int ldh, double* fcol, hipStream_t st) {
+void penalty_apply(int n_pen, const int32_t* act, const int32_t* rowptr, const int32_t* ent,
+                   const int32_t* idx, const double* w, const double* c, const double* t,
+                   double tscale, const double* x2, int m, double* H, int ldh, double* fcol,
+                   hipStream_t st) {
   if (m > 0)
-    k_penalty_apply<<<grid1(m, 64), 64, 0, st>>>(n_pen, act, nact, idx, w, c, t, tscale, x2, m, H,
-                                                 ldh, fcol);
+    k_penalty_apply<<<grid1(m, 64), 64, 0, st>>>(n_pen, act, rowptr, ent, idx, w, c, t, tscale, x2,
+                                                 m, H, ldh, fcol);
 }
 
 // Sum of squares of each of the three columns of a [3][m], one workgroup per
