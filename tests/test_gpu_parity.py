@@ -124,6 +124,40 @@ def test_penalty_solve_matches_oracle(torch_cuda, name):
     assert rel(host(u, (3, -1)), u2_or) <= TOL
 
 
+def test_penalty_incidence_many(torch_cuda):
+    """Penalty terms with more region rows and more active penalties than one
+    pass of the preparation workgroup covers (1,024 each), up to eight nodes
+    per penalty, a node named by 250 penalties and nodes named twice within
+    one penalty: f_col against the oracle, and the FP64 solve's own residual
+    (H assembled through the rows' incidence lists, the residual's P u through
+    the same lists on the f_col branch)."""
+    sc = P.scene_small(40, 40, 4, region_top_layers=2, seed=3, n_spheres=1)
+    ctx = gpu_context(sc)
+    m = ctx.m
+    assert m > 1024
+    rng = np.random.default_rng(21)
+    npen = 2500
+    idx = np.full((npen, 8), -1, dtype=np.int32)
+    w = np.zeros((npen, 8))
+    for j in range(npen):
+        k = 1 + j % 8
+        idx[j, :k] = rng.choice(m, size=k, replace=False)
+        w[j, :k] = rng.uniform(-1, 1, size=k)
+    idx[::10, 0] = 7                         # a node shared by 250 penalties
+    idx[3::50, 1] = idx[3::50, 0]            # the same node in two slots of a penalty
+    c = rng.uniform(1e3, 1e6, size=npen)
+    c[::7] = 0.0
+    t = rng.normal(size=(3, npen))
+    x2 = rng.normal(size=(3, m))
+    fcol = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), dev(x2), fcol)
+    assert rel(host(fcol, (3, -1)), ocol.penalty_force(m, idx, w, c, t, x2)) <= TOL
+    g = rng.normal(size=(3, m))
+    u = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    info = ctx.global_solve(dev(g), u, want_info=True)
+    assert info["bad_pivot"] == 0 and info["rel_residual"] <= 1e-11
+
+
 def _run_alg1_pair(torch, sc, outer, inner, steps):
     from paper_2008_01541_amd.driver import Alg1Runner
     om = oracle_model(sc)
