@@ -98,7 +98,7 @@ class Alg1Runner:
         return infos
 
     def run_pipelined(self, n_iters, spheres_of=None, n_workgroups=0, factor_stream=None,
-                      fuse_forward=False, overlap_forward=True):
+                      fuse_forward=False, overlap_forward=True, before_local=None):
         """n_iters outer iterations with one inner iteration each, pipelined
         over two streams.  The factorization side of iteration k (detection,
         penalties, region local step, H = S + W^T C W and its Cholesky factor)
@@ -119,7 +119,10 @@ class Alg1Runner:
         are carried over from the inner update instead of being gathered from
         x after the back substitution (the same values: delta2 holds the
         single update).  spheres_of(k) gives the obstacle spheres of
-        iteration k (None keeps the current ones)."""
+        iteration k (None keeps the current ones); before_local(k), if given,
+        runs on the context stream between the back substitution of k - 1 and
+        the full local step of k (e.g. to move prescribed Dirichlet nodes in
+        x, as a caller of outer_iteration would before each call)."""
         torch = self.torch
         c = self.ctx
         s_main = c.stream
@@ -146,6 +149,9 @@ class Alg1Runner:
             c.use_stream(s_main)
             if k > 0:
                 c.backsub(self.delta2, self.x)
+            if before_local is not None:
+                with torch.cuda.stream(s_main):
+                    before_local(k)
             c.local_step_full(self.x, self.f)
             c.condense_rhs(self.f, self.ft)
             with torch.cuda.stream(s_main):

@@ -340,6 +340,41 @@ def test_slit_self_contact_alg1_matches_oracle(torch_cuda):
     assert worst <= 1e-9
 
 
+def test_slit_pipelined_matches_oracle(torch_cuda):
+    """The slit on two streams: factorization of iteration k beside the back
+    substitution of k - 1 and the local step and condensation of k, the jaw
+    pose of each iteration applied between them (before_local); one inner
+    iteration per outer one, against the oracle."""
+    from paper_2008_01541_amd.driver import Alg1Runner
+    from oracle import collision as ocol
+    torch = torch_cuda
+    sc = P.scene_slit(10, 10, 8, 4, 6, seed=5, steps=6)
+    om = opd.PDModel(sc.rest, sc.tets, sc.mu, sc.dirichlet, sc.region)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, np.zeros(0, np.int64),
+                         sc.k_pen)
+        run.use_pairs(sc.pairs)
+        steps = [1 + k // 2 for k in range(12)]
+        bottom = torch.tensor(sc.bottom, device="cuda").long()
+        poses = [torch.tensor(sc.prescribed(sc.rest, st)[:, sc.bottom], device="cuda") for st in steps]
+
+        def before_local(k):
+            run.x.view(3, -1)[:, bottom] = poses[k]
+
+        run.run_pipelined(12, n_workgroups=8, factor_stream=torch.cuda.Stream(),
+                          before_local=before_local)
+    torch.cuda.synchronize()
+    pl = sc.pairs_local()
+    det = lambda x2: ocol.detect_pairs(x2, pl, sc.k_pen)
+    x_or = sc.rest.copy()
+    for st in steps:
+        x_or = sc.prescribed(x_or, st)
+        x_or = opd.alg1_outer_iteration(om, x_or, det, n_inner=1)
+    scale = np.abs(x_or - sc.rest).max()
+    assert np.abs(run.positions() - x_or).max() / scale <= 1e-9
+
+
 def test_factor_modes(torch_cuda):
     """pd_factor rejects unknown modes before enqueuing anything, and a factor
     started in mode 2 (forward solve allowed to overlap it) gives the same
