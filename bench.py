@@ -187,6 +187,51 @@ def warmstart_leg(run, args):
         return {"error": str(e)}
 
 
+def bench_dense_chol(args):
+    """Standalone dense FP64 Cholesky (pd_chol_factor) of a synthetic SPD matrix
+    of order n (symmetric U[-0.5, 0.5] entries, n/2 added to the diagonal),
+    in place, timed with HIP events around each factorization (a fresh copy
+    of the matrix is restored before each one, outside the timed region)."""
+    import torch
+    from paper_2008_01541_amd import DenseCholesky
+    n = args.dense_chol
+    lda = (n + 15) // 16 * 16
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.rand(n, n, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    a = (x + x.T) * 0.5
+    a.diagonal().add_(0.5 * n)
+    del x
+    pristine = torch.zeros(n, lda, dtype=torch.float64, device="cuda")   # row c = column c
+    pristine[:, :n] = a
+    work = torch.empty_like(pristine)
+    chol = DenseCholesky(n, stream)
+    ms = []
+    for it in range(args.warmup + args.steps):
+        work.copy_(pristine)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        chol.factor(work.view(-1), n, lda, want_info=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            ms.append(e0.elapsed_time(e1))
+    info = chol.factor(work.view(-1).copy_(pristine.view(-1)), n, lda)
+    L = torch.tril(work[:, :n].T)
+    v = torch.rand(n, 3, dtype=torch.float64, device="cuda", generator=g)
+    res = (L @ (L.T @ v) - a @ v).norm() / (a @ v).norm()
+    best, mean = min(ms), sum(ms) / len(ms)
+    tf = n ** 3 / 3.0 / (mean * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "dense FP64 Cholesky TFLOP/s (n^3/3 flop per factorization)",
+        "value": tf, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "dense_spd", "n": n, "lda": lda},
+        "ms_mean": mean, "ms_best": best, "tflops_best": n ** 3 / 3.0 / (best * 1e-3) / 1e12,
+        "frac_of_fp64_peak": tf / 78.6, "info": info, "rel_residual": float(res)}))
+
+
 def bench_slit(args):
     """Self-contact stress workload: 64 x 64 x 40 slit grid (983,040 tets,
     176,215 nodes, 12,155-node region, 2,990 lip pairs), jaw closing over the
@@ -286,6 +331,9 @@ def main():
                          "default 384 for slab56, 448 for slit64)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="time only the single-stream iterations")
+    ap.add_argument("--dense-chol", type=int, default=0,
+                    help="time only the standalone dense FP64 Cholesky at this order "
+                         "(e.g. 19494 = 3 x 6,498, the coupled form's size)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip timing replays of a HIP graph of one outer iteration")
     args = ap.parse_args()
@@ -306,6 +354,8 @@ def main():
         del src, dst
     if args.factor_wg <= 0:
         args.factor_wg = 448 if args.workload == "slit64" else 384
+    if args.dense_chol > 0:
+        return bench_dense_chol(args)
     if args.workload == "slit64":
         return bench_slit(args)
     sc = P.scene_slab56()

@@ -221,6 +221,33 @@ pd_status pd_backsub(pd_ctx *ctx, const double *delta2, double *x);
  * Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
  * Parameter packing (host float32): W1 [n_h1][n_in], b1 [n_h1], W2 [n_h2][n_h1],
  * b2 [n_h2], W3 [n_out][n_h2], b3 [n_out] (row-major, concatenated). */
+/* ---- Standalone dense FP64 Cholesky -------------------------------------
+ * The single-launch dataflow factorization that pd_global_solve / pd_factor
+ * apply to H = S + P (Alg. 1 step 4.3; Sec. 4.4 Step 2: one dense Cholesky
+ * of the collision-region system per penalty change), for callers that need
+ * the factorization of their own SPD matrix. */
+typedef struct pd_chol pd_chol;
+
+/* Workspace for matrices of order up to n_max (tile inverses and partial sums
+ * 2 x ceil(n_max / 64) x 64 x 64 doubles, ready flags); factorizations are
+ * enqueued on hip_stream.  Synchronous.  n_max <= 0 -> PD_ERR_INVALID. */
+pd_status pd_chol_create(int64_t n_max, void *hip_stream, pd_chol **out);
+
+/* In place: A dev [n x n] column-major, leading dimension lda (a multiple of
+ * 16 doubles, lda >= n; 0 < n <= n_max), symmetric positive definite, lower
+ * triangle read.  On return the lower triangle holds L (A = L L^T) and the
+ * strictly upper triangle holds L^T.  n_workgroups > 0 caps the persistent
+ * workgroups (default two per compute unit).  info_host == NULL: enqueue only.
+ * Otherwise the call synchronizes and *info_host receives 0, or the 1-based
+ * index of the first non-positive pivot (PD_ERR_NOT_SPD; that pivot is
+ * replaced by 1 and the factorization runs to the end).  Calls on one handle
+ * must not overlap.  Invalid arguments -> PD_ERR_INVALID, nothing enqueued. */
+pd_status pd_chol_factor(pd_chol *h, double *A, int64_t lda, int64_t n, int32_t n_workgroups,
+                         int32_t *info_host);
+
+/* Waits for the handle's stream and frees the workspace. */
+pd_status pd_chol_destroy(pd_chol *h);
+
 typedef struct pd_mlp pd_mlp;
 
 /* Creates the network with the given initial parameters (host, packed as

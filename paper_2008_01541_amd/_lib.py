@@ -55,6 +55,9 @@ _SIGS = {
     "pd_mlp_forward": [_P, _P, _P, C.c_int32],
     "pd_mlp_train_step": [_P, _P, _P, C.c_int32, C.c_float, C.POINTER(C.c_double), _P],
     "pd_mlp_destroy": [_P],
+    "pd_chol_create": [C.c_int64, _P, C.POINTER(_P)],
+    "pd_chol_factor": [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32)],
+    "pd_chol_destroy": [_P],
     "pd_displacement_change": [_P, _P, _P, _P],
     "pd_warmstart_input": [_P, _P, _P, C.c_float, C.c_int32, _P, _P, _P],
     "pd_region_add_f32": [_P, _P, C.c_double, _P],
@@ -311,6 +314,53 @@ class PDContext:
         import torch
         self._chk(self._lib.pd_backsub(self._ctx, _ptr(delta2, torch.float64, 3 * self.m, "delta2"),
                                        _ptr(x, torch.float64, 3 * self.n, "x")))
+
+
+class DenseCholesky:
+    """Standalone dense FP64 Cholesky (pd_chol_* entry points): in-place
+    factorization of a device matrix of order up to n_max."""
+
+    def __init__(self, n_max, stream=None):
+        import torch
+        lib = load_library()
+        self._lib = lib
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        st = lib.pd_chol_create(int(n_max), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != PD_OK:
+            raise PDError(st, "pd_chol_create failed")
+        self._h = h
+        self.n_max = int(n_max)
+
+    def factor(self, A, n, lda, n_workgroups=0, want_info=True):
+        """A: device float64 tensor holding an n x n matrix column-major with
+        leading dimension lda (lda * n elements).  Returns the pivot info (0 if
+        positive definite) when want_info, else None (enqueue only)."""
+        import torch
+        ptr = _ptr(A, torch.float64, int(lda) * int(n), "A")
+        if not want_info:
+            st = self._lib.pd_chol_factor(self._h, ptr, int(lda), int(n), int(n_workgroups), None)
+            if st != PD_OK:
+                raise PDError(st, "pd_chol_factor failed")
+            return None
+        info = C.c_int32(0)
+        st = self._lib.pd_chol_factor(self._h, ptr, int(lda), int(n), int(n_workgroups),
+                                      C.byref(info))
+        if st not in (PD_OK, PD_ERR_NOT_SPD):
+            raise PDError(st, "pd_chol_factor failed")
+        return int(info.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pd_chol_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class MLP:
