@@ -67,3 +67,19 @@ def test_dense_cholesky_rejects_bad_arguments(torch_cuda):
     with pytest.raises(PDError):
         chol.factor(dA, 128, 128)                   # n above n_max
     chol.close()
+
+
+@pytest.mark.parametrize("n_wg", [1, 3])
+def test_dense_cholesky_few_workgroups(torch_cuda, n_wg):
+    """Every task waits only on tasks with smaller tickets, so the persistent
+    schedule completes with any number of workgroups, one included."""
+    from paper_2008_01541_amd import DenseCholesky
+    n, lda = 300, 304
+    a = _spd(n, 11)
+    dA = _to_device(torch_cuda, a, lda)
+    chol = DenseCholesky(n)
+    assert chol.factor(dA, n, lda, n_workgroups=n_wg) == 0
+    lo = np.tril(dA.cpu().numpy().reshape(n, lda)[:, :n].T)
+    ref = np.linalg.cholesky(a)
+    assert np.abs(lo - ref).max() <= 1e-12 * np.abs(ref).max()
+    chol.close()
