@@ -290,7 +290,7 @@ def bench_slit(args):
     m = ctx.m
     fac = tim["factor"][0] / max(tim["factor"][1], 1)
     tf = m ** 3 / 3.0 / (fac * 1e-3) / 1e12
-    print(json.dumps({
+    out = {
         "metric": "collision-region PD iters/sec (self-contact slit); Schur Cholesky TFLOP/s",
         "value": max(eager_value, pipe_value or 0.0), "unit": "PD iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
@@ -302,7 +302,11 @@ def bench_slit(args):
         "active_pairs_last": act,
         "schur_cholesky_tflops": tf, "schur_cholesky_ms": fac,
         "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
-        "schur_build_s": build_s}))
+        "schur_build_s": build_s}
+    if not args.no_precision_modes:
+        # the refined low-precision solves on the same state (last jaw pose)
+        out["precision_modes"] = precision_modes(run, run.spheres, args.inner)
+    print(json.dumps(out))
 
 
 def main():
