@@ -39,11 +39,14 @@ def test_mlp_forward_and_gradients_match_oracle(shape, B):
     for k in g_or:
         assert _rel(gd[k], g_or[k]) <= 1e-4, k
     assert loss == pytest.approx(omlp.loss(Y_or, T), rel=1e-4)
-    # against pure float64 the BF16 rounding points cost a few percent (deep K sums)
-    Y64, c64 = omlp.forward(p32, X.astype(np.float64), emulate=False)
+    # P17 against pure float64: the float64 network takes the ReLU decisions
+    # of the BF16 pass (a decision made by floating point is taken in the same
+    # precision on both sides); what remains is BF16 operand rounding, a few
+    # unit roundoffs (2^-8) normwise.
+    Y64, c64 = omlp.forward(p32, X.astype(np.float64), emulate=False, masks=(cache[1], cache[3]))
     g64 = omlp.backward(p32, c64, Y64, T.astype(np.float64), emulate=False)
     for k in g64:
-        assert _rel(gd[k], g64[k]) <= 6e-2, k
+        assert _rel(gd[k], g64[k]) <= 2e-2, k
 
 
 def test_mlp_adam_steps_match_oracle():

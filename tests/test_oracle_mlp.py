@@ -56,6 +56,29 @@ def test_emulated_gradients_close_to_float64():
         assert np.linalg.norm(gq[k] - g[k]) <= 2e-2 * np.linalg.norm(g[k])
 
 
+@pytest.mark.parametrize("shape,B", [((300, 96, 80, 200), 33), ((2600, 64, 64, 1950), 64)])
+def test_emulated_gradients_close_to_float64_with_shared_relu_decisions(shape, B):
+    """Deep products (K = 2,600) and hidden layers where a few pre-activations
+    sit within the BF16 rounding error of zero: with the ReLU decisions of the
+    BF16 pass, the float64 gradients differ only by operand rounding
+    (normwise <= 2e-2, about 1e-3 per rounding stage)."""
+    rng = np.random.default_rng(12)
+    p = mlp.init_params(*shape, seed=11)
+    for k in ["b1", "b2", "b3"]:
+        p[k] = 0.05 * rng.normal(size=p[k].shape)
+    X = rng.normal(size=(B, shape[0]))
+    T = rng.normal(size=(B, shape[3]))
+    Yq, cq = mlp.forward(p, X, emulate=True)
+    gq = mlp.backward(p, cq, Yq, T, emulate=True)
+    Y, c = mlp.forward(p, X, emulate=False, masks=(cq[1], cq[3]))
+    g = mlp.backward(p, c, Y, T, emulate=False)
+    for k in g:
+        assert np.linalg.norm(gq[k] - g[k]) <= 2e-2 * np.linalg.norm(g[k]), k
+    # with its own decisions the float64 pass is the plain network
+    Y0, c0 = mlp.forward(p, X, emulate=False)
+    assert np.array_equal(c0[1], (X @ p["W1"].T + p["b1"]) > 0)
+
+
 def test_adam_first_step_is_signed_lr():
     """With bias correction the first Adam step moves every coordinate by
     lr * g / (|g| + eps) ~ lr * sign(g)."""

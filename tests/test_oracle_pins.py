@@ -425,3 +425,60 @@ def test_slit_schur_route_equals_full_solve():
     u_full = spla.spsolve(A, b.T).T
     u_schur = pd.three_step_solve(m, b, pen)
     assert np.linalg.norm(u_schur - u_full) <= 1e-11 * np.linalg.norm(u_full)
+
+
+def test_corotated_energy_closed_form():
+    """E(x) = min_R E_hat(x, R) (Sec. 3.2): for F = Q1 diag(s) Q2 with proper
+    rotations Q1, Q2 the minimum is mu Vol sum_i (s_i - 1)^2; for an inverted F
+    (one negative factor, R restricted to SO(3)) the smallest singular value
+    enters as (sigma_3 + 1)^2; and no random rotation does better."""
+    rng = np.random.default_rng(41)
+    rest = np.array([[0.0, 1.0, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0], [0.0, 0.0, 0.0, 1.0]]) * 0.7
+    tets = np.array([[0], [1], [2], [3]])
+    B, vol = fem.shape_matrices(rest, tets)
+    for inverted in (False, True):
+        for _ in range(5):
+            s = np.sort(rng.uniform(0.3, 1.8, size=3))[::-1]
+            Q1, Q2 = _rand_rotation(rng), _rand_rotation(rng)
+            d = s.copy()
+            if inverted:
+                d[2] = -d[2]
+            F = Q1 @ np.diag(d) @ Q2
+            x = F @ rest + rng.normal(size=(3, 1))
+            e = fem.corotated_energy(x, tets, B, vol, MU)
+            if inverted:
+                want = (s[0] - 1) ** 2 + (s[1] - 1) ** 2 + (s[2] + 1) ** 2
+            else:
+                want = np.sum((s - 1) ** 2)
+            want *= MU * vol[0]
+            assert e == pytest.approx(want, rel=1e-12)
+            for _ in range(20):
+                Rr = _rand_rotation(rng)[None]
+                assert fem.pd_energy(x, tets, B, vol, MU, Rr) >= e * (1 - 1e-12)
+
+
+def test_alg1_nested_iteration_reaches_plain_pd_fixed_point():
+    """The inner loop only reorganises the minimisation (Sec. 4.5): Alg. 1 with
+    three inner iterations, iterated to convergence, stops at the fixed point of
+    plain full-mesh PD (f_tot = 0 with R = polar(F) and the penalty set
+    consistent with the positions), not at a different state."""
+    s, m, det = _pushed_scene_state(nx=4, ny=3, nz=3, steps=3)
+
+    def converge(step, tol=1e-12, cap=3000):
+        x = s.rest.copy()
+        for it in range(cap):
+            xn = step(x)
+            if np.linalg.norm(xn - x) <= tol * np.linalg.norm(xn - s.rest):
+                return xn, it + 1
+            x = xn
+        raise AssertionError("no convergence")
+
+    x_plain, it_plain = converge(lambda x: pd.plain_pd_iteration(m, x, det))
+    x_nest, it_nest = converge(lambda x: pd.alg1_outer_iteration(m, x, det, n_inner=3))
+    disp = np.linalg.norm(x_plain - s.rest)
+    assert disp > 0 and (det(x_plain[:, m.i2])[2] > 0).any()
+    assert np.linalg.norm(x_nest - x_plain) <= 1e-9 * disp
+    # the nested state is itself a fixed point of the plain iteration
+    assert np.linalg.norm(pd.plain_pd_iteration(m, x_nest, det) - x_nest) <= 1e-10 * disp
+    # and the inner loop needs no more outer iterations than plain PD
+    assert it_nest <= it_plain
