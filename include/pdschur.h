@@ -158,16 +158,29 @@ pd_status pd_assemble_rhs(pd_ctx *ctx, const double *ft, const double *f_beta,
  * PD_FP64: FP64 Cholesky and triangular solves.
  * PD_FP32_IR / PD_BF16_IR: the Jacobi-equilibrated D H D is factored in FP32
  * (tile products on FP32 matrix cores, or with BF16 operands and FP32
- * accumulation); u is refined with the residual g - H u computed in FP64
- * until max_v ||r_v|| / ||g_v|| <= 1e-8 or 30 correction steps.  These modes
- * synchronize the stream once per step.  If the tolerance is not reached the
- * call returns PD_ERR_IR_STALLED with u = the last iterate (the caller may
- * solve again with PD_FP64; fell_back is then reported by the caller).
- * info (host) may be NULL; when given, the call synchronizes and fills it.
- * A non-positive pivot -> PD_ERR_NOT_SPD (only detected when the call
- * synchronizes, i.e. with info or in the refined modes). */
+ * accumulation); that factor preconditions conjugate gradients on H u = g,
+ * with H applied in FP64 (the residual g - H u stays FP64), one independent
+ * iteration per coordinate column, until max_v ||g_v - H u_v|| / ||g_v|| <=
+ * tol (default 1e-8, recomputed from u at the end) or max_steps steps
+ * (default 100; see pd_set_refinement).  These modes synchronize the stream
+ * once per step.  If the tolerance is not reached, or the low-precision
+ * factor meets a non-positive pivot: with fallback on (the default) the call
+ * factors H in FP64, solves, and returns PD_OK with info->fell_back = 1; with
+ * fallback off it returns PD_ERR_IR_STALLED (PD_ERR_NOT_SPD for the pivot)
+ * with u = the last iterate.
+ * info (host) may be NULL; when given, the call synchronizes and fills it
+ * (ir_iters = conjugate-gradient steps taken).
+ * A non-positive pivot of the FP64 factor -> PD_ERR_NOT_SPD (only detected
+ * when the call synchronizes, i.e. with info or in the refined modes). */
 pd_status pd_global_solve(pd_ctx *ctx, const double *g, double *u, pd_precision prec,
                           pd_solve_info *info);
+
+/* Settings of the refined modes of pd_global_solve: at most max_steps
+ * (0..100000) conjugate-gradient steps, relative residual tolerance tol > 0,
+ * fallback = 1 to factor in FP64 when the refinement does not reach tol
+ * (fell_back reported in pd_solve_info), 0 to return PD_ERR_IR_STALLED.
+ * Defaults: 100, 1e-8, 1.  Invalid values -> PD_ERR_INVALID, unchanged. */
+pd_status pd_set_refinement(pd_ctx *ctx, int32_t max_steps, double tol, int32_t fallback);
 
 /* FP64 factorization of H = S + W^T C W ahead of the solve (Alg. 1 step 4.3,
  * Sec. 4.4 Step 2), for callers that overlap it with other work: H only
@@ -234,8 +247,9 @@ typedef struct pd_chol pd_chol;
 pd_status pd_chol_create(int64_t n_max, void *hip_stream, pd_chol **out);
 
 /* In place: A dev [n x n] column-major, leading dimension lda (a multiple of
- * 16 doubles, lda >= n; 0 < n <= n_max), symmetric positive definite, lower
- * triangle read.  On return the lower triangle holds L (A = L L^T) and the
+ * 16 doubles, lda >= n; 0 < n <= n_max), A itself aligned to 128 bytes (so
+ * that no two 64 x 64 tiles share a cache line; e.g. not an offset view into
+ * a larger allocation), symmetric positive definite, lower triangle read.  On return the lower triangle holds L (A = L L^T) and the
  * strictly upper triangle holds L^T.  n_workgroups > 0 caps the persistent
  * workgroups (default two per compute unit).  info_host == NULL: enqueue only.
  * Otherwise the call synchronizes and *info_host receives 0, or the 1-based
@@ -247,6 +261,7 @@ pd_status pd_chol_factor(pd_chol *h, double *A, int64_t lda, int64_t n, int32_t 
 
 /* Waits for the handle's stream and frees the workspace. */
 pd_status pd_chol_destroy(pd_chol *h);
+
 
 typedef struct pd_mlp pd_mlp;
 
@@ -270,6 +285,16 @@ pd_status pd_mlp_forward(pd_mlp *mlp, const float *x, float *y, int32_t batch);
  * receives the loss before the update; giving it synchronizes. */
 pd_status pd_mlp_train_step(pd_mlp *mlp, const float *x, const float *target, int32_t batch,
                             float lr, double *loss_host, float *grads_host);
+
+/* Training batches: dst [B][n_cols] (dev float) <- rows rows[b] (dev int32,
+ * each in [0, n_rows)) of src [n_rows][n_cols] (dev float), the first
+ * n_scaled columns multiplied by scale (standardisation of increments). */
+pd_status pd_mlp_gather_rows(pd_mlp *mlp, const float *src, int32_t n_rows, int32_t n_cols,
+                             const int32_t *rows, int32_t B, int32_t n_scaled, float scale,
+                             float *dst);
+
+/* *out_host <- mean of |a[i]| over n floats (dev).  Synchronizes. */
+pd_status pd_mlp_abs_mean(pd_mlp *mlp, const float *a, int64_t n, double *out_host);
 
 pd_status pd_mlp_destroy(pd_mlp *mlp);
 

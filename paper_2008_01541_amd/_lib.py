@@ -1,6 +1,8 @@
 """ctypes binding of include/pdschur.h (argument marshalling only)."""
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -55,6 +57,8 @@ _SIGS = {
     "pd_mlp_forward": [_P, _P, _P, C.c_int32],
     "pd_mlp_train_step": [_P, _P, _P, C.c_int32, C.c_float, C.POINTER(C.c_double), _P],
     "pd_mlp_destroy": [_P],
+    "pd_mlp_gather_rows": [_P, _P, C.c_int32, C.c_int32, _P, C.c_int32, C.c_int32, C.c_float, _P],
+    "pd_mlp_abs_mean": [_P, _P, C.c_int64, C.POINTER(C.c_double)],
     "pd_chol_create": [C.c_int64, _P, C.POINTER(_P)],
     "pd_chol_factor": [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32)],
     "pd_chol_destroy": [_P],
@@ -64,6 +68,7 @@ _SIGS = {
     "pd_set_stream": [_P, _P],
     "pd_use_stream": [_P, _P],
     "pd_factor": [_P, C.c_int32, C.c_int32],
+    "pd_set_refinement": [_P, C.c_int32, C.c_double, C.c_int32],
     "pd_supply_rhs": [_P, _P],
     "pd_set_timing": [_P, C.c_int],
     "pd_get_timings": [_P, _P, _P],
@@ -73,6 +78,51 @@ PHASES = ["local_full", "condense", "detect", "collision", "local_region", "asse
           "hbuild", "factor", "solve", "inner_update", "backsub"]
 
 _lib = None
+
+# Handles (contexts, factorizations, networks) still open.  They are closed by
+# an exit handler registered after torch, so it runs before torch's own exit
+# handlers and before the HIP runtime and any profiler tool are torn down;
+# after it, __del__ never calls into the library (objects collected during
+# interpreter teardown would otherwise free device memory and events after the
+# runtime is gone).
+_open_handles = weakref.WeakSet()
+_exiting = False
+
+
+def _close_all_at_exit():
+    global _exiting
+    for h in list(_open_handles):
+        try:
+            h.close()
+        except Exception:
+            pass
+    _exiting = True
+
+
+class _Handle:
+    """Base of the objects owning a library handle: explicit close(), also as
+    a context manager; __del__ closes only before interpreter exit."""
+
+    def _register(self):
+        _open_handles.add(self)
+
+    def close(self):
+        raise NotImplementedError
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        if _exiting:
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def library_path():
@@ -95,6 +145,8 @@ def load_library():
         f.restype = C.c_int
     lib.pd_last_error.argtypes = [_P]
     lib.pd_last_error.restype = C.c_char_p
+    import torch  # noqa: F401  (its exit handlers must run after ours)
+    atexit.register(_close_all_at_exit)
     _lib = lib
     return lib
 
@@ -115,7 +167,7 @@ def _ptr(t, dtype=None, numel=None, name="tensor"):
     return t.data_ptr()
 
 
-class PDContext:
+class PDContext(_Handle):
     """One built mesh (pd_schur_build) and its per-iteration entry points."""
 
     def __init__(self, rest, tets, region, dirichlet, mu, stream=None):
@@ -142,6 +194,7 @@ class PDContext:
         if st != PD_OK:
             raise PDError(st, lib.pd_last_error(None).decode())
         self._ctx = ctx
+        self._register()
         m, n1, nb, na, nl = (C.c_int64() for _ in range(5))
         self._chk(lib.pd_query(ctx, C.byref(m), C.byref(n1), C.byref(nb), C.byref(na),
                                C.byref(nl)))
@@ -159,12 +212,6 @@ class PDContext:
         if getattr(self, "_ctx", None):
             self._lib.pd_destroy(self._ctx)
             self._ctx = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     # --- entry points (names as in the C ABI) ------------------------------
     def get_schur(self, S):
@@ -247,6 +294,11 @@ class PDContext:
         self._chk(st)
         return None
 
+    def set_refinement(self, max_steps=100, tol=1e-8, fallback=True):
+        """Settings of the refined solves (pd_set_refinement)."""
+        self._chk(self._lib.pd_set_refinement(self._ctx, int(max_steps), float(tol),
+                                              1 if fallback else 0))
+
     def factor(self, n_workgroups=0, supply_rhs=False, overlap_forward=False):
         """FP64 factorization of H ahead of global_solve (pd_factor); with
         overlap_forward the next global_solve may be enqueued on another stream
@@ -316,7 +368,7 @@ class PDContext:
                                        _ptr(x, torch.float64, 3 * self.n, "x")))
 
 
-class DenseCholesky:
+class DenseCholesky(_Handle):
     """Standalone dense FP64 Cholesky (pd_chol_* entry points): in-place
     factorization of a device matrix of order up to n_max."""
 
@@ -331,6 +383,7 @@ class DenseCholesky:
         if st != PD_OK:
             raise PDError(st, "pd_chol_create failed")
         self._h = h
+        self._register()
         self.n_max = int(n_max)
 
     def factor(self, A, n, lda, n_workgroups=0, want_info=True):
@@ -356,14 +409,8 @@ class DenseCholesky:
             self._lib.pd_chol_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
-
-class MLP:
+class MLP(_Handle):
     """Warm-start network (pd_mlp_* entry points)."""
 
     def __init__(self, n_in, n_h1, n_h2, n_out, max_batch, params_flat, stream=None):
@@ -383,18 +430,13 @@ class MLP:
         if st != PD_OK:
             raise PDError(st, "pd_mlp_create failed")
         self._h = h
+        self._register()
         self.max_batch = max_batch
 
     def close(self):
         if getattr(self, "_h", None):
             self._lib.pd_mlp_destroy(self._h)
             self._h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     def params(self):
         out = np.empty(self.n_params, dtype=np.float32)
@@ -421,6 +463,30 @@ class MLP:
         if st != PD_OK:
             raise PDError(st, "pd_mlp_train_step failed")
         return loss.value if want_loss else None
+
+    def gather_rows(self, src, rows, dst, n_scaled=0, scale=1.0):
+        """dst[b] = src[rows[b]] with the first n_scaled columns times scale
+        (pd_mlp_gather_rows); src, dst 2-D float32 device tensors."""
+        import torch
+        n_rows, n_cols = src.shape
+        B = rows.numel()
+        if dst.shape != (B, n_cols):
+            raise ValueError("dst must be [len(rows), n_cols]")
+        st = self._lib.pd_mlp_gather_rows(self._h, _ptr(src, torch.float32, n_rows * n_cols, "src"),
+                                          n_rows, n_cols, _ptr(rows, torch.int32, B, "rows"), B,
+                                          int(n_scaled), float(scale),
+                                          _ptr(dst, torch.float32, B * n_cols, "dst"))
+        if st != PD_OK:
+            raise PDError(st, "pd_mlp_gather_rows failed")
+
+    def abs_mean(self, a):
+        import torch
+        out = C.c_double()
+        st = self._lib.pd_mlp_abs_mean(self._h, _ptr(a, torch.float32, a.numel(), "a"), a.numel(),
+                                       C.byref(out))
+        if st != PD_OK:
+            raise PDError(st, "pd_mlp_abs_mean failed")
+        return out.value
 
     def gradients(self, x, target):
         import torch

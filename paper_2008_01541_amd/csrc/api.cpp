@@ -88,7 +88,6 @@ struct pd_ctx {
   int* d_cumarks = nullptr;           // per-compute-unit marks of the dataflow Cholesky
   unsigned* d_tticket = nullptr;
   int chol_epoch = 0;
-  int chol_dataflow = 1;              // 1: single-launch dataflow, 0: three launches per step
   int n_wg = 512;
   // low-precision factor for the refined solves
   float* d_H32 = nullptr;
@@ -100,8 +99,14 @@ struct pd_ctx {
   int* d_lp_flags = nullptr;
   int lp_prec = -1;                   // precision of the current low-precision factor
   bool lp_stale = true;
-  int max_ir = 30;
+  int lp_info = -1;                   // its first non-positive pivot (0: none; -1: not read yet)
+  int max_ir = 100;
   double ir_tol = 1e-8;
+  int ir_fallback = 1;                // refactor in FP64 when the refinement stalls
+  double* d_cgp = nullptr;            // conjugate-gradient vectors (3 m each) and scalars
+  double* d_cgq = nullptr;
+  double* d_cgz = nullptr;
+  double* d_cgs = nullptr;
   // sweeps
   double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
   bool have_condense = false;
@@ -255,13 +260,9 @@ void free_now(pd_ctx* c, void* p) {
 // transpose of the factor in the upper triangle.
 void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr, int n_wg = 0,
               const int* gflag = nullptr, int gepoch = 0, hipEvent_t after_reset = nullptr) {
-  if (c->chol_dataflow) {
-    potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
-                   n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, gflag, gepoch,
-                   c->d_cumarks, after_reset);
-  } else {
-    potrf_tiled(A, lda, n, c->d_linv, c->d_info, c->st);
-  }
+  potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
+                 n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, gflag, gepoch,
+                 c->d_cumarks, after_reset);
 }
 
 inline int pad_to(int64_t v, int q) { return (int)((v + q - 1) / q * q); }
@@ -398,7 +399,6 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   for (int k = 0; k < K; ++k) c->maxldw = std::max<int64_t>(c->maxldw, c->ldw[k]);
   c->ldH = pad_to(m, 16);
   c->ldH32 = pad_to(m, 32);
-  for (int64_t w = 0; w < 1; ++w) {}
   if (c->maxw > 46340 || m > 46340) return c->fail(PD_ERR_INVALID, "dense block too large");
 
   // ---- element geometry and stiffness on the GPU
@@ -624,8 +624,6 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     HIPCK(c, hipMemsetAsync(c->d_tflags, 0, nt2 * sizeof(int), c->st));
     HIPCK(c, hipMemsetAsync(c->d_cumarks, 0, potrf_cu_slots() * sizeof(int), c->st));
     HIPCK(c, hipMemsetAsync(c->d_tticket, 0, 4 * sizeof(unsigned), c->st));
-    const char* mode = getenv("PDSCHUR_CHOL");
-    if (mode && strcmp(mode, "tiled") == 0) c->chol_dataflow = 0;
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
@@ -766,6 +764,7 @@ bool bad_ctx(const pd_ctx* c) { return c == nullptr; }
 thread_local std::string g_build_error;
 
 }  // namespace
+
 
 // ===========================================================================
 extern "C" {
@@ -990,6 +989,84 @@ pd_status residual(pd_ctx* c, const double* g, const double* u, double* rel) {
   return PD_OK;
 }
 
+// nq = -(S + P) p in FP64 (three columns).
+void neg_apply_H(pd_ctx* c, const double* p, double* nq) {
+  const int m = (int)c->m;
+  symv3(c->d_S, m, m, p, m, -1.0, 0.0, nq, m, c->st);
+  if (c->n_pen > 0) {
+    penalty_apply(c->n_pen, c->d_pact, c->d_prow, c->d_pent, c->d_pidx, c->d_pw, c->d_pc, c->d_pt,
+                  0.0, p, m, nullptr, 0, c->d_y, c->st);
+    axpy3_sum(m, nq, c->d_y, nullptr, nq, c->st);
+  }
+}
+
+// z = M^-1 r with M = D^-1 L L^T D^-1 from the low-precision factor.
+void lp_precondition(pd_ctx* c, const double* r, double* z) {
+  trsv3_lp_solve(c->d_H32, c->ldH32, (int)c->m, c->d_linv32, c->d_dvec, r, c->d_lpb, c->d_lpy, z,
+                 0, c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
+}
+
+// max over columns of ||r_v|| / ||g_v|| from squared norms computed on the
+// device (synchronizes).
+pd_status column_ratio(pd_ctx* c, const double* r, const double* g, double* rel) {
+  const int m = (int)c->m;
+  colnorm2_3(m, r, c->d_norms, c->st);
+  colnorm2_3(m, g, c->d_norms + 3, c->st);
+  double nrm[6];
+  HIPCK(c, hipMemcpyAsync(nrm, c->d_norms, 6 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCK(c, hipStreamSynchronize(c->st));
+  double rr = 0.0;
+  for (int v = 0; v < 3; ++v)
+    if (nrm[3 + v] > 0) rr = std::max(rr, std::sqrt(nrm[v] / nrm[3 + v]));
+    else if (nrm[v] > 0) rr = std::numeric_limits<double>::infinity();
+  *rel = rr;
+  return PD_OK;
+}
+
+// Preconditioned conjugate gradients on H u = g from the initial u, the
+// low-precision factor as preconditioner, H applied in FP64.  The updated
+// residual is checked after every step; once it meets the tolerance the true
+// residual g - H u is recomputed, and the iteration restarts from it if
+// rounding has separated the two.  Returns the true relative residual and
+// the number of steps.
+pd_status refine_pcg(pd_ctx* c, const double* g, double* u, double* rel, int* steps) {
+  const int m = (int)c->m;
+  double* r = c->d_res;
+  double* p = c->d_cgp;
+  double* nq = c->d_cgq;
+  double* z = c->d_cgz;
+  double* rz[2] = {c->d_cgs, c->d_cgs + 3};
+  double* pnq = c->d_cgs + 6;
+  double rr = 0.0;
+  int it = 0;
+  CK(residual(c, g, u, &rr));             // r = g - H u
+  while (!(rr <= c->ir_tol) && it < c->max_ir) {
+    // (re)start from the true residual in r
+    lp_precondition(c, r, z);
+    copy_f64(3 * (long)m, z, p, c->st);
+    dot3(m, r, z, rz[0], c->st);
+    int cur = 0;
+    double upd = rr;
+    while (it < c->max_ir) {
+      neg_apply_H(c, p, nq);
+      dot3(m, p, nq, pnq, c->st);
+      cg_update(m, rz[cur], pnq, p, nq, u, r, c->st);
+      ++it;
+      CK(column_ratio(c, r, g, &upd));
+      if (upd <= c->ir_tol || !std::isfinite(upd)) break;
+      lp_precondition(c, r, z);
+      dot3(m, r, z, rz[cur ^ 1], c->st);
+      cg_direction(m, rz[cur ^ 1], rz[cur], z, p, c->st);
+      cur ^= 1;
+    }
+    CK(residual(c, g, u, &rr));
+    if (!std::isfinite(upd) || !std::isfinite(rr)) break;
+  }
+  *rel = rr;
+  *steps = it;
+  return PD_OK;
+}
+
 pd_status ensure_lp_buffers(pd_ctx* c) {
   if (c->d_H32) return PD_OK;
   const int64_t m = c->m;
@@ -998,6 +1075,10 @@ pd_status ensure_lp_buffers(pd_ctx* c) {
   CK(c->alloc(&c->d_lpb, 3 * m));
   CK(c->alloc(&c->d_lpy, 3 * m));
   CK(c->alloc(&c->d_dvec, m));
+  CK(c->alloc(&c->d_cgp, 3 * m));
+  CK(c->alloc(&c->d_cgq, 3 * m));
+  CK(c->alloc(&c->d_cgz, 3 * m));
+  CK(c->alloc(&c->d_cgs, 16));
   CK(c->alloc(&c->d_lp_ticket, 2));
   CK(c->alloc(&c->d_lp_flags, 2 * (int64_t)c->ntm));
   HIPCK(c, hipMemsetAsync(c->d_lp_ticket, 0, 2 * sizeof(unsigned long long), c->st));
@@ -1019,7 +1100,7 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
     if (c->stale) {
       build_H(c);
       zero_int(c->d_info, c->st);
-      fused = c->chol_dataflow != 0;
+      fused = true;
       if (fused) rhs_pack(m, g, m, c->d_Yt, c->st);
       PhaseTimer tm(c, PD_PHASE_FACTOR);
       cholesky(c, c->d_H, c->ldH, m, fused ? c->d_Yt : nullptr);
@@ -1081,23 +1162,62 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
                       c->st, c->d_cumarks);
     c->lp_stale = false;
     c->lp_prec = (int)prec;
-  }
-  PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
-  trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, g, c->d_lpb, c->d_lpy, u, 0,
-                 c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
-  CK(c->check("pd_global_solve"));
-  double rr = 0.0;
-  int it = 0;
-  CK(residual(c, g, u, &rr));
-  while (!(rr <= c->ir_tol) && it < c->max_ir) {
-    trsv3_lp_solve(c->d_H32, c->ldH32, m, c->d_linv32, c->d_dvec, c->d_res, c->d_lpb, c->d_lpy,
-                   u, 1, c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
-    ++it;
-    CK(residual(c, g, u, &rr));
+    c->lp_info = -1;
   }
   int hinfo = 0, herr = 0;
-  HIPCK(c, hipMemcpy(&hinfo, c->d_info, sizeof(int), hipMemcpyDeviceToHost));
-  HIPCK(c, hipMemcpy(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+  double rr = 0.0;
+  int it = 0;
+  {
+    PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
+    // a non-positive pivot of the low-precision factor leaves no usable
+    // preconditioner: check it before iterating
+    if (c->lp_info < 0) {
+      HIPCK(c, hipMemcpyAsync(&c->lp_info, c->d_info, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      HIPCK(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      HIPCK(c, hipStreamSynchronize(c->st));
+    }
+    hinfo = c->lp_info;
+    if (!hinfo && !herr) {
+      lp_precondition(c, g, u);
+      CK(c->check("pd_global_solve"));
+      CK(refine_pcg(c, g, u, &rr, &it));
+      HIPCK(c, hipMemcpy(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    }
+  }
+  if (herr) return c->fail(PD_ERR_HIP, "dependency wait timed out");
+  const bool stalled = hinfo != 0 || !(rr <= c->ir_tol);
+  if (stalled && c->ir_fallback) {
+    // FP64 factor and solve of the same H
+    build_H(c);
+    zero_int(c->d_info, c->st);
+    {
+      PhaseTimer tm(c, PD_PHASE_FACTOR);
+      cholesky(c, c->d_H, c->ldH, m, nullptr);
+    }
+    c->stale = false;
+    {
+      PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
+      trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
+                    c->d_err, c->st);
+      trsv3_backward(c->d_H, c->ldH, m, c->d_linv, c->d_y, m, u, m, c->d_ticket + 1,
+                     c->d_flags + c->ntm, c->d_err, c->st);
+    }
+    CK(c->check("pd_global_solve"));
+    CK(residual(c, g, u, &rr));
+    int finfo = 0;
+    HIPCK(c, hipMemcpy(&finfo, c->d_info, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCK(c, hipMemcpy(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (info) {
+      info->ir_iters = it;
+      info->bad_pivot = finfo;
+      info->fell_back = 1;
+      info->reserved = 0;
+      info->rel_residual = rr;
+    }
+    if (herr) return c->fail(PD_ERR_HIP, "dependency wait timed out");
+    if (finfo) return c->fail(PD_ERR_NOT_SPD, "non-positive pivot at %d", finfo);
+    return PD_OK;
+  }
   if (info) {
     info->ir_iters = it;
     info->bad_pivot = hinfo;
@@ -1105,10 +1225,21 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
     info->reserved = 0;
     info->rel_residual = rr;
   }
-  if (herr) return c->fail(PD_ERR_HIP, "dependency wait timed out");
   if (hinfo) return c->fail(PD_ERR_NOT_SPD, "non-positive pivot at %d", hinfo);
   if (!(rr <= c->ir_tol))
     return c->fail(PD_ERR_IR_STALLED, "refinement reached %.3e after %d steps", rr, it);
+  return PD_OK;
+}
+
+pd_status pd_set_refinement(pd_ctx* c, int32_t max_steps, double tol, int32_t fallback) {
+  if (bad_ctx(c)) return PD_ERR_INVALID;
+  if (max_steps < 0 || max_steps > 100000 || !(tol > 0.0) || !std::isfinite(tol) ||
+      (fallback != 0 && fallback != 1))
+    return c->fail(PD_ERR_INVALID, "bad refinement settings (%d, %g, %d)", max_steps, tol,
+                   fallback);
+  c->max_ir = max_steps;
+  c->ir_tol = tol;
+  c->ir_fallback = fallback;
   return PD_OK;
 }
 
@@ -1118,8 +1249,8 @@ pd_status pd_factor(pd_ctx* c, int32_t n_workgroups, int32_t supply_rhs) {
   if (!c->stale) return PD_OK;
   if (supply_rhs < 0 || supply_rhs > 2)
     return c->fail(PD_ERR_INVALID, "supply_rhs must be 0, 1 or 2 (got %d)", (int)supply_rhs);
-  const bool defer = supply_rhs == 1 && c->chol_dataflow != 0;
-  const bool overlap = supply_rhs == 2 && c->chol_dataflow != 0;
+  const bool defer = supply_rhs == 1;
+  const bool overlap = supply_rhs == 2;
   if (overlap && !c->ev_fstart) {
     HIPCK(c, hipEventCreateWithFlags(&c->ev_fstart, hipEventDisableTiming));
     HIPCK(c, hipEventCreateWithFlags(&c->ev_fdone, hipEventDisableTiming));

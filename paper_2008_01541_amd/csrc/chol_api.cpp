@@ -66,7 +66,11 @@ pd_status pd_chol_create(int64_t n_max, void* stream, pd_chol** out) {
 
 pd_status pd_chol_factor(pd_chol* h, double* A, int64_t lda, int64_t n, int32_t n_workgroups,
                          int32_t* info_host) {
-  if (!h || !A || n <= 0 || n > h->n_max || lda < n || lda % 16 != 0 || lda > INT32_MAX)
+  // Tiles are published across workgroups with write-through stores and read
+  // back with ordinary cached loads; that is only safe when no two tiles share
+  // a 128-byte line, i.e. every column (and so every tile) starts on one.
+  if (!h || !A || n <= 0 || n > h->n_max || lda < n || lda % 16 != 0 || lda > INT32_MAX ||
+      reinterpret_cast<uintptr_t>(A) % 128 != 0)
     return PD_ERR_INVALID;
   zero_int(h->info, h->st);
   zero_int(h->err, h->st);

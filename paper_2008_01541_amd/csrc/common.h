@@ -16,7 +16,6 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // dense FP64
 void copy_lower_tiles(const double* S, int lds, double* H, int ldh, int n, hipStream_t st);
-void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStream_t st);
 // Single-launch dataflow Cholesky; flags: (nt + 2) * nt ints and ticket[2]
 // (task counter, launch epoch), all zero-initialised once; each call advances
 // the epoch on the device (safe under graph replay).  sbuf: nt * NB * NB
@@ -78,6 +77,15 @@ void equilibrate_convert(const double* H, int ld, int n, double* d, float* H32, 
 void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const double* d,
                     const double* r, double* b, double* y, double* x, int accumulate,
                     unsigned long long* tickets, int* flags, int* err, hipStream_t st);
+
+// conjugate-gradient steps on three independent columns [3][n] (scalars in
+// device memory): out[v] = a_v . b_v; with nq = -H p and pnq = p . nq,
+// u += alpha p, r += alpha nq for alpha = rz / (p^T H p); p = z + (rz_new / rz_old) p.
+void dot3(int n, const double* a, const double* b, double* out, hipStream_t st);
+void cg_update(int n, const double* rz, const double* pnq, const double* p, const double* nq,
+               double* u, double* r, hipStream_t st);
+void cg_direction(int n, const double* rz_new, const double* rz_old, const double* z, double* p,
+                  hipStream_t st);
 
 // condensation sweeps, one interior level at a time: sweep_symv writes the
 // tile parts of Z x for a level of width w (Z symmetric, only its lower tiles

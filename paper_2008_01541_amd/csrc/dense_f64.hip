@@ -101,54 +101,6 @@ __device__ void gemm_acc(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD],
   }
 }
 
-// Factor diagonal tile k in place (lower) and write its inverse (64x64, lower,
-// identity-padded past the matrix edge) to linv_ws + k*NB*NB.
-__global__ __launch_bounds__(256) void k_potrf_diag(double* A, int lda, int n, int k,
-                                                    double* linv_ws, int* info) {
-  __shared__ double T[NB][LDS_LD];
-  __shared__ double X[NB][LDS_LD];
-  const int t = threadIdx.x;
-  const int r0 = k * NB;
-  const int mr = min(NB, n - r0);
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    double v;
-    if (r < mr && c < mr) v = (r >= c) ? A[(long)(r0 + r) + (long)(r0 + c) * lda] : 0.0;
-    else v = (r == c) ? 1.0 : 0.0;
-    T[c][r] = v;
-  }
-  factor_tile_blocked(T, X, mr, r0, info);
-  double* Li = linv_ws + (long)k * NB * NB;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    Li[e] = X[c][r];
-    if (r < mr && c < mr && r >= c) A[(long)(r0 + r) + (long)(r0 + c) * lda] = T[c][r];
-  }
-}
-
-// Panel: L_ik = A_ik * Linv_kk^T for tiles i > k (one workgroup per tile).
-__global__ __launch_bounds__(256) void k_trsm_panel(double* A, int lda, int n, int k,
-                                                    const double* linv_ws) {
-  __shared__ double As[KC][LDS_LD];
-  __shared__ double Bs[KC][LDS_LD];
-  const int i = k + 1 + blockIdx.x;
-  const int r0 = i * NB, mr = min(NB, n - r0);
-  Acc acc;
-  acc_zero(acc);
-  gemm_acc<false, false>(acc, As, Bs, A, lda, r0, mr, k * NB,
-                         linv_ws + (long)k * NB * NB, NB, 0, NB, 0, NB);
-  __syncthreads();
-#pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = acc_row(mb), c = acc_col(nb, q);
-        if (r < mr) A[(long)(r0 + r) + (long)(k * NB + c) * lda] = acc.c[mb][nb][q];
-      }
-}
-
 __device__ inline void tri_index(int b, int& i, int& j) {
   // b -> (i, j) with 0 <= j <= i, b = i (i + 1) / 2 + j
   int ii = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
@@ -156,29 +108,6 @@ __device__ inline void tri_index(int b, int& i, int& j) {
   while (ii * (ii + 1) / 2 > b) --ii;
   i = ii;
   j = b - ii * (ii + 1) / 2;
-}
-
-// Trailing update of step k: A_ij -= L_ik L_jk^T for k < j <= i.
-__global__ __launch_bounds__(256) void k_syrk_update(double* A, int lda, int n, int k) {
-  __shared__ double As[KC][LDS_LD];
-  __shared__ double Bs[KC][LDS_LD];
-  int ii, jj;
-  tri_index(blockIdx.x, ii, jj);
-  const int i = k + 1 + ii, j = k + 1 + jj;
-  const int r0 = i * NB, c0 = j * NB;
-  const int mr = min(NB, n - r0), mc = min(NB, n - c0);
-  Acc acc;
-  acc_zero(acc);
-  gemm_acc<false, false>(acc, As, Bs, A, lda, r0, mr, k * NB, A, lda, c0, mc, k * NB, NB);
-#pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-    for (int nb = 0; nb < 2; ++nb)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = acc_row(mb), c = acc_col(nb, q);
-        if (r < mr && c < mc) A[(long)(r0 + r) + (long)(c0 + c) * lda] -= acc.c[mb][nb][q];
-      }
 }
 
 // ---------------------------------------------------------------------------
@@ -635,33 +564,6 @@ __global__ void k_zero_f64(long n, double* p) {
 }
 void zero_f64(long n, double* p, hipStream_t st) {
   if (n > 0) k_zero_f64<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, p);
-}
-
-// Upper triangle <- transpose of the strictly lower triangle (tiles (j, i), i > j,
-// and the strictly upper part of diagonal tiles).
-__global__ __launch_bounds__(256) void k_mirror_lower(double* A, int lda, int n) {
-  int i, j;
-  tri_index(blockIdx.x, i, j);
-  const int r0 = i * NB, c0 = j * NB;
-  const int mr = min(NB, n - r0), mc = min(NB, n - c0);
-  for (int e = threadIdx.x; e < NB * NB; e += 256) {
-    const int c = e & 63, r = e >> 6;        // write U(c0 + c, r0 + r) = L(r0 + r, c0 + c)
-    if (r < mr && c < mc && (i != j || r > c))
-      A[(long)(c0 + c) + (long)(r0 + r) * lda] = A[(long)(r0 + r) + (long)(c0 + c) * lda];
-  }
-}
-
-void potrf_tiled(double* A, int lda, int n, double* linv_ws, int* info, hipStream_t st) {
-  const int nt = (n + NB - 1) / NB;
-  for (int k = 0; k < nt; ++k) {
-    k_potrf_diag<<<1, 256, 0, st>>>(A, lda, n, k, linv_ws, info);
-    const int R = nt - k - 1;
-    if (R > 0) {
-      k_trsm_panel<<<R, 256, 0, st>>>(A, lda, n, k, linv_ws);
-      k_syrk_update<<<R * (R + 1) / 2, 256, 0, st>>>(A, lda, n, k);
-    }
-  }
-  k_mirror_lower<<<nt * (nt + 1) / 2, 256, 0, st>>>(A, lda, n);
 }
 
 // ---------------------------------------------------------------------------

@@ -522,4 +522,68 @@ void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const d
   k_unscale3<<<g, 256, 0, st>>>(n, d, b, x, accumulate);
 }
 
+// ---------------------------------------------------------------------------
+// Preconditioned conjugate gradients on H u = g (three independent columns),
+// the low-precision factor as preconditioner and H applied in FP64.
+// The scalars live in device memory so that no iteration waits for the host.
+
+// out[v] = sum_i a[v][i] b[v][i], one workgroup per column, fixed order.
+__global__ __launch_bounds__(256) void k_dot3(int n, const double* __restrict__ a,
+                                              const double* __restrict__ b,
+                                              double* __restrict__ out) {
+  __shared__ double part[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += a[(long)v * n + i] * b[(long)v * n + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = part[0];
+}
+
+// With nq = -H p and pnq[v] = p_v . nq_v (= -p_v^T H p_v):
+//   alpha_v = rz[v] / (p_v^T H p_v);  u_v += alpha_v p_v;  r_v += alpha_v nq_v.
+// A column whose curvature is not positive (converged to exactly zero, or
+// broken down) is left unchanged.
+__global__ void k_cg_update(int n, const double* __restrict__ rz, const double* __restrict__ pnq,
+                            const double* __restrict__ p, const double* __restrict__ nq,
+                            double* __restrict__ u, double* __restrict__ r) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const int v = e / n;
+  const double curv = -pnq[v];
+  if (!(curv > 0.0)) return;
+  const double alpha = rz[v] / curv;
+  u[e] += alpha * p[e];
+  r[e] += alpha * nq[e];
+}
+
+// beta_v = rz_new[v] / rz_old[v] (0 when rz_old is 0);  p_v = z_v + beta_v p_v.
+__global__ void k_cg_direction(int n, const double* __restrict__ rz_new,
+                               const double* __restrict__ rz_old, const double* __restrict__ z,
+                               double* __restrict__ p) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 3 * n) return;
+  const int v = e / n;
+  const double beta = rz_old[v] != 0.0 ? rz_new[v] / rz_old[v] : 0.0;
+  p[e] = z[e] + beta * p[e];
+}
+
+void dot3(int n, const double* a, const double* b, double* out, hipStream_t st) {
+  k_dot3<<<3, 256, 0, st>>>(n, a, b, out);
+}
+
+void cg_update(int n, const double* rz, const double* pnq, const double* p, const double* nq,
+               double* u, double* r, hipStream_t st) {
+  if (n > 0) k_cg_update<<<(3 * n + 255) / 256, 256, 0, st>>>(n, rz, pnq, p, nq, u, r);
+}
+
+void cg_direction(int n, const double* rz_new, const double* rz_old, const double* z, double* p,
+                  hipStream_t st) {
+  if (n > 0) k_cg_direction<<<(3 * n + 255) / 256, 256, 0, st>>>(n, rz_new, rz_old, z, p);
+}
+
 }  // namespace pdk

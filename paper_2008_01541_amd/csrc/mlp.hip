@@ -207,6 +207,43 @@ void mlp_adam(long n, float* w, const float* g, float* m, float* v, __bf16* wb, 
   k_adam<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, w, g, m, v, wb, lr, b1, b2, 1e-8f, c1, c2);
 }
 
+// dst[b][k] = src[rows[b]][k] * (k < n_scaled ? scale : 1), rows of n_cols floats.
+__global__ void k_gather_rows_scaled(int n_cols, const float* __restrict__ src,
+                                     const int32_t* __restrict__ rows, int n_scaled, float scale,
+                                     float* __restrict__ dst) {
+  const int b = blockIdx.y;
+  const long r = rows[b];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_cols; k += gridDim.x * blockDim.x) {
+    const float v = src[r * n_cols + k];
+    dst[(long)b * n_cols + k] = k < n_scaled ? v * scale : v;
+  }
+}
+
+void mlp_gather_rows_scaled(int B, int n_cols, const float* src, const int32_t* rows, int n_scaled,
+                            float scale, float* dst, hipStream_t st) {
+  const int gx = std::min((n_cols + 255) / 256, 64);
+  k_gather_rows_scaled<<<dim3(gx, B), 256, 0, st>>>(n_cols, src, rows, n_scaled, scale, dst);
+}
+
+// out = sum |a| / n over n floats, one workgroup, fixed order.
+__global__ __launch_bounds__(1024) void k_abs_mean(long n, const float* __restrict__ a,
+                                                   double* __restrict__ out) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (long e = threadIdx.x; e < n; e += 1024) s += fabs((double)a[e]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = n > 0 ? red[0] / (double)n : 0.0;
+}
+
+void mlp_abs_mean(long n, const float* a, double* out, hipStream_t st) {
+  k_abs_mean<<<1, 1024, 0, st>>>(n, a, out);
+}
+
 __global__ void k_to_bf16(long n, const float* __restrict__ w, __bf16* __restrict__ wb) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < n) wb[e] = (__bf16)w[e];

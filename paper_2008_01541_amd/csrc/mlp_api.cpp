@@ -23,6 +23,9 @@ void mlp_colsum(int M, int N, const float* dZ, float* gb, hipStream_t st);
 void mlp_adam(long n, float* w, const float* g, float* m, float* v, __bf16* wb, float lr, int step,
               hipStream_t st);
 void mlp_to_bf16(long n, const float* w, __bf16* wb, hipStream_t st);
+void mlp_gather_rows_scaled(int B, int n_cols, const float* src, const int32_t* rows, int n_scaled,
+                            float scale, float* dst, hipStream_t st);
+void mlp_abs_mean(long n, const float* a, double* out, hipStream_t st);
 }  // namespace pdk
 
 using namespace pdk;
@@ -200,6 +203,25 @@ pd_status pd_mlp_train_step(pd_mlp* h, const float* x, const float* target, int3
     if (hipStreamSynchronize(h->st) != hipSuccess) return PD_ERR_HIP;
   }
   return hipGetLastError() == hipSuccess ? PD_OK : PD_ERR_HIP;
+}
+
+pd_status pd_mlp_gather_rows(pd_mlp* h, const float* src, int32_t n_rows, int32_t n_cols,
+                             const int32_t* rows, int32_t B, int32_t n_scaled, float scale,
+                             float* dst) {
+  if (!h || !src || !rows || !dst || n_rows <= 0 || n_cols <= 0 || B <= 0 || B > 65535 ||
+      n_scaled < 0 || n_scaled > n_cols || !std::isfinite(scale))
+    return PD_ERR_INVALID;
+  mlp_gather_rows_scaled(B, n_cols, src, rows, n_scaled, scale, dst, h->st);
+  return hipGetLastError() == hipSuccess ? PD_OK : PD_ERR_HIP;
+}
+
+pd_status pd_mlp_abs_mean(pd_mlp* h, const float* a, int64_t n, double* out_host) {
+  if (!h || !a || n <= 0 || !out_host) return PD_ERR_INVALID;
+  mlp_abs_mean(n, a, h->loss, h->st);
+  if (hipMemcpyAsync(out_host, h->loss, sizeof(double), hipMemcpyDeviceToHost, h->st) != hipSuccess ||
+      hipStreamSynchronize(h->st) != hipSuccess)
+    return PD_ERR_HIP;
+  return PD_OK;
 }
 
 pd_status pd_mlp_destroy(pd_mlp* h) {

@@ -170,3 +170,14 @@ class Alg1Runner:
 
     def positions(self):
         return self.x.reshape(3, -1).cpu().numpy()
+
+    def close(self):
+        """Frees the library context (waits for its stream)."""
+        self.ctx.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False

@@ -66,6 +66,10 @@ def test_dense_cholesky_rejects_bad_arguments(torch_cuda):
         chol.factor(dA[: 100 * 100], 100, 100)      # lda not a multiple of 16
     with pytest.raises(PDError):
         chol.factor(dA, 128, 128)                   # n above n_max
+    with pytest.raises(PDError):
+        chol.factor(dA[1: 1 + 100 * 112], 100, 112)  # view not aligned to 128 bytes
+    with pytest.raises(PDError):
+        chol.factor(dA[8: 8 + 100 * 112], 100, 112)  # 64 bytes: still not a line
     chol.close()
 
 

@@ -312,6 +312,77 @@ def test_refined_solve(torch_cuda, name, prec):
     assert info["ir_iters"] >= 1
 
 
+def _penalised_system(torch_cuda, sc, om, ctx, seed, k=1e6, npen=20):
+    rng = np.random.default_rng(seed)
+    m = ctx.m
+    npen = min(npen, m)
+    sel = rng.choice(m, size=npen, replace=False)
+    idx = np.full((npen, 8), -1, dtype=np.int32)
+    idx[:, 0] = sel
+    w = np.zeros((npen, 8)); w[:, 0] = 1.0
+    c = np.full(npen, k)
+    t = rng.normal(size=(3, npen))
+    fcol = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), dev(sc.rest[:, om.i2]), fcol)
+    H = om.schur() + ocol.penalty_matrix(m, idx, w, c)
+    return H, rng.normal(size=(3, m))
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_refined_solve_stall_status_and_fp64_fallback(torch_cuda, prec):
+    """A stall forced from the host (no refinement step allowed): with the
+    fallback off the call returns PD_ERR_IR_STALLED with the last iterate (the
+    preconditioned first solve); with it on the call factors H in FP64 and
+    returns PD_OK, fell_back = 1 and the FP64 solution (residual recomputed by
+    the oracle).  A following refined call with steps allowed converges again
+    from the kept low-precision factor."""
+    import scipy.linalg as sla
+    from paper_2008_01541_amd import PD_ERR_IR_STALLED
+    sc = SMALL_SCENES["g16x15x8"]()
+    om = oracle_model(sc)
+    ctx = gpu_context(sc)
+    m = ctx.m
+    H, g = _penalised_system(torch_cuda, sc, om, ctx, seed=41)
+    u_or = sla.cho_solve(sla.cho_factor(H, lower=True), g.T).T
+
+    def relres(u):
+        r = g - (H @ u.T).T
+        return max(np.linalg.norm(r[v]) / np.linalg.norm(g[v]) for v in range(3))
+
+    u = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    ctx.set_refinement(max_steps=0, tol=1e-8, fallback=False)
+    info = ctx.global_solve(dev(g), u, prec=prec, want_info=True)
+    assert info["status"] == PD_ERR_IR_STALLED and info["fell_back"] == 0
+    assert info["ir_iters"] == 0
+    ug = host(u, (3, -1))
+    assert relres(ug) == pytest.approx(info["rel_residual"], rel=1e-6)
+    assert 1e-8 < relres(ug) < 0.5          # a real, if inaccurate, iterate
+
+    ctx.set_refinement(max_steps=0, tol=1e-8, fallback=True)
+    info = ctx.global_solve(dev(g), u, prec=prec, want_info=True)
+    assert info["status"] == 0 and info["fell_back"] == 1
+    ug = host(u, (3, -1))
+    assert relres(ug) <= 1e-12 and info["rel_residual"] <= 1e-12
+    assert np.abs(ug - u_or).max() <= 1e-10 * np.abs(u_or).max()
+    # the FP64 factor left by the fallback serves a plain FP64 solve bit for bit
+    u64 = torch_cuda.empty(3 * m, dtype=torch_cuda.float64, device="cuda")
+    ctx.global_solve(dev(g), u64, prec=0)
+    assert torch_cuda.equal(u64, u)
+
+    ctx.set_refinement()                   # defaults: 100 steps, 1e-8, fallback on
+    info = ctx.global_solve(dev(g), u, prec=prec, want_info=True)
+    assert info["status"] == 0 and info["fell_back"] == 0 and info["ir_iters"] >= 1
+    assert relres(host(u, (3, -1))) <= 1e-8
+
+
+def test_set_refinement_rejects_bad_settings(torch_cuda):
+    from paper_2008_01541_amd import PDError
+    ctx = gpu_context(SMALL_SCENES["g4x3x5"]())
+    for args in [(-1, 1e-8, 1), (10, 0.0, 1), (10, float("nan"), 1), (10, 1e-8, 2)]:
+        with pytest.raises(PDError):
+            ctx.set_refinement(*args)
+
+
 def test_slit_self_contact_alg1_matches_oracle(torch_cuda):
     """Self-contact of a slit closed by a prescribed jaw rotation: two-node
     penalties (off-diagonal W^T C W), both Dirichlet faces, E_beta non-empty;
