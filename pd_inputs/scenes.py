@@ -214,6 +214,9 @@ class SlitScene:
     k_pen: float
     mu: float
     h: float
+    meta_nx: int = 0
+    meta_zs: int = 0
+    meta_ys_end: int = 0
 
     @property
     def n_nodes(self):
@@ -267,4 +270,63 @@ def scene_slit(nx=64, ny=64, nz=40, zs=20, ys_end=46, h=1.0, seed=5, steps=10,
                       roll_max=np.deg2rad(rng.uniform(0.5, 1.5)), steps=steps)
     return SlitScene(name=f"slit{nx}x{ny}x{nz}", rest=rest, tets=tets, dirichlet=dirichlet,
                      region=region, pairs=twins, bottom=bottom, jaw=jaw, k_pen=k_pen,
-                     mu=lame_mu(), h=h)
+                     mu=lame_mu(), h=h, meta_nx=nx, meta_zs=zs, meta_ys_end=ys_end)
+
+
+def surface_points(rng, x_range, y_range, z, count):
+    """Seeded points uniform on the horizontal rectangle x_range x y_range at
+    height z: rest positions (3, count) of embedded collision proxies."""
+    x = rng.uniform(x_range[0], x_range[1], count)
+    y = rng.uniform(y_range[0], y_range[1], count)
+    return np.vstack([x, y, np.full(count, float(z))])
+
+
+def top_face_proxy_points(scene, count, seed=11):
+    """Embedded proxies on the top face of a grid scene: count seeded rest
+    positions, uniform over the face (z = nz h)."""
+    rng = np.random.default_rng(seed)
+    return surface_points(rng, (0.0, scene.nx * scene.h), (0.0, scene.ny * scene.h),
+                          scene.nz * scene.h, count)
+
+
+def region_tets(rest, tets, region, dirichlet):
+    """Indices of the tets whose four vertices are free region nodes (the set
+    that embeds the proxies)."""
+    ok = region & ~dirichlet
+    return np.nonzero(np.all(ok[tets], axis=0))[0]
+
+
+@dataclass
+class LevelSetBodies:
+    """Rest-pose level sets of the two lips of a slit and the embedded proxies
+    on both lip surfaces (all ids global; rest positions (3, *))."""
+    proxy_points: np.ndarray   # (3, n_prox) rest positions
+    proxy_body: np.ndarray     # (n_prox,) 0 = lower lip, 1 = upper lip
+    body_tets: np.ndarray      # (4, n_cand) global node ids
+    body_phi: np.ndarray       # (4, n_cand) signed distance to the lip plane (< 0 inside)
+    body_id: np.ndarray        # (n_cand,)
+
+
+def slit_levelset_bodies(sc, per_cell=1.0, seed=15):
+    """Lip bodies of a slit scene for rest-pose level-set self-collision: the
+    region tets below the slit plane (body 0) and above it (body 1); the signed
+    distance of each body's rest shape near the slit is the distance to the
+    plane z = zs (negative inside the body), given at each tet corner.  Proxies:
+    per_cell seeded points per lip cell face, uniform over the slit footprint
+    on each lip."""
+    zs = float(sc.meta_zs) * sc.h
+    sel = region_tets(sc.rest, sc.tets, sc.region, sc.dirichlet)
+    T = sc.tets[:, sel]
+    zc = sc.rest[2][T].mean(axis=0)
+    body = (zc > zs).astype(np.int32)
+    Z = sc.rest[2][T]
+    phi = np.where(body[None, :] == 1, zs - Z, Z - zs)
+    rng = np.random.default_rng(seed)
+    nfx, nfy = sc.meta_nx, sc.meta_ys_end
+    count = int(round(per_cell * nfx * nfy))
+    lo = surface_points(rng, (0.0, nfx * sc.h), (0.0, nfy * sc.h), zs, count)
+    up = surface_points(rng, (0.0, nfx * sc.h), (0.0, nfy * sc.h), zs, count)
+    pts = np.concatenate([lo, up], axis=1)
+    pb = np.concatenate([np.zeros(count, np.int32), np.ones(count, np.int32)])
+    return LevelSetBodies(proxy_points=pts, proxy_body=pb, body_tets=T.astype(np.int64),
+                          body_phi=phi, body_id=body)
