@@ -297,7 +297,7 @@ class PDContext(_Handle):
     def set_refinement(self, max_steps=100, tol=1e-8, fallback=True):
         """Settings of the refined solves (pd_set_refinement)."""
         self._chk(self._lib.pd_set_refinement(self._ctx, int(max_steps), float(tol),
-                                              1 if fallback else 0))
+                                              int(fallback)))
 
     def factor(self, n_workgroups=0, supply_rhs=False, overlap_forward=False):
         """FP64 factorization of H ahead of global_solve (pd_factor); with
