@@ -262,6 +262,21 @@ pd_status pd_chol_factor(pd_chol *h, double *A, int64_t lda, int64_t n, int32_t 
 /* Waits for the handle's stream and frees the workspace. */
 pd_status pd_chol_destroy(pd_chol *h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * factorization of pd_chol_factor without a handle.  Its workspace is a
+ * static device array of the library sized for n <= PD_CHOL_NOALLOC_MAX_N
+ * (about 8.1 MB), one copy per GPU, held until the process ends and shared by
+ * every call on that GPU: calls that overlap on one GPU (e.g. on two streams)
+ * race and must be serialized by the caller.  The first call on a GPU also
+ * enqueues a fill that zeroes the array's flags.  Enqueued on hip_stream
+ * (the current device's); arguments, layout, result and info_host as for
+ * pd_chol_factor.  n > PD_CHOL_NOALLOC_MAX_N -> PD_ERR_INVALID, nothing
+ * enqueued.  Calls no allocating routine. */
+#define PD_CHOL_NOALLOC_MAX_N 8192
+pd_status pd_chol_factor_noalloc(double *A, int64_t lda, int64_t n, int32_t n_workgroups,
+                                 void *hip_stream, int32_t *info_host);
+
 
 typedef struct pd_mlp pd_mlp;
 

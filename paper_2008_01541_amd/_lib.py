@@ -62,6 +62,7 @@ _SIGS = {
     "pd_chol_create": [C.c_int64, _P, C.POINTER(_P)],
     "pd_chol_factor": [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32)],
     "pd_chol_destroy": [_P],
+    "pd_chol_factor_noalloc": [_P, C.c_int64, C.c_int64, C.c_int32, _P, C.POINTER(C.c_int32)],
     "pd_displacement_change": [_P, _P, _P, _P],
     "pd_warmstart_input": [_P, _P, _P, C.c_float, C.c_int32, _P, _P, _P],
     "pd_region_add_f32": [_P, _P, C.c_double, _P],
@@ -408,6 +409,27 @@ class DenseCholesky(_Handle):
         if getattr(self, "_h", None):
             self._lib.pd_chol_destroy(self._h)
             self._h = None
+
+
+def chol_factor_noalloc(A, n, lda, n_workgroups=0, want_info=True, stream=None):
+    """pd_chol_factor_noalloc: the factorization of DenseCholesky.factor with
+    the library's static workspace (n <= PD_CHOL_NOALLOC_MAX_N), on `stream`
+    (default: torch's current stream).  Returns the pivot info when want_info."""
+    import torch
+    lib = load_library()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    ptr = _ptr(A, torch.float64, int(lda) * int(n), "A")
+    info = C.c_int32(0)
+    st = lib.pd_chol_factor_noalloc(ptr, int(lda), int(n), int(n_workgroups),
+                                    C.c_void_p(stream.cuda_stream),
+                                    C.byref(info) if want_info else None)
+    if st not in (PD_OK, PD_ERR_NOT_SPD) or (st == PD_ERR_NOT_SPD and not want_info):
+        raise PDError(st, "pd_chol_factor_noalloc failed")
+    return int(info.value) if want_info else None
+
+
+PD_CHOL_NOALLOC_MAX_N = 8192
 
 
 class MLP(_Handle):
