@@ -202,7 +202,7 @@ def plain_pd_iteration(model, x, detect):
     rhs = f[:, model.free].copy()
     fcol = collision.penalty_force(model.m, idx, w, c, t, x[:, model.i2])
     rhs[:, pos[model.i2]] += fcol
-    dx = spla.spsolve(A, rhs.T)
+    dx = schur.sparse_factor(A).solve(np.ascontiguousarray(rhs.T))
     x[:, model.free] += dx.T
     return x
 

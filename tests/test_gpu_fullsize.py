@@ -133,3 +133,57 @@ def test_slab_refined_solves_random_penalties(slab, oracle_slab, prec):
     r = g - Su - Pm_u
     rel = max(np.linalg.norm(r[v]) / np.linalg.norm(g[v]) for v in range(3))
     assert rel <= (1e-10 if prec == 0 else 1e-8), rel
+
+
+def _deformed_start(sc):
+    """Seeded smooth deformation of the free nodes (zero on the pinned bottom),
+    so that every tet has a non-trivial rotation."""
+    rng = np.random.default_rng(21)
+    X, Y, Z = sc.rest
+    amp = rng.uniform(0.05, 0.15, 3)
+    ph = rng.uniform(0.0, 2 * np.pi, 3)
+    s = (Z / Z.max()) ** 2
+    dx = np.vstack([amp[v] * s * np.sin(2 * np.pi * X / 56 + ph[v]) * np.cos(2 * np.pi * Y / 56)
+                    for v in range(3)])
+    x = sc.rest + dx
+    x[:, sc.dirichlet] = sc.rest[:, sc.dirichlet]
+    return x
+
+
+@pytest.fixture(scope="module")
+def slab_alg1_reference(oracle_slab):
+    """The oracle's plain full-mesh PD iteration from the deformed start with the
+    spheres of frame 40 (Alg. 1 with one inner iteration is this iterate)."""
+    from oracle import pd as opd
+    sc = P.scene_slab56()
+    om = oracle_slab
+    x0 = _deformed_start(sc)
+    cen, rad = sc.spheres.centers(40), sc.spheres.radii
+    det = opd.sphere_detector(om, sc.proxy_local(), cen, rad, sc.k_pen)
+    n_active = int((det(x0[:, om.i2])[2] > 0).sum())
+    return sc, x0, cen, rad, opd.plain_pd_iteration(om, x0, det), n_active
+
+
+@pytest.mark.parametrize("pipelined", [False, True])
+def test_slab_alg1_iteration_matches_oracle(slab, slab_alg1_reference, pipelined):
+    """One Alg. 1 outer iteration (one inner) at full size, on one stream and on
+    two streams (the benchmark's pipelined schedule, 384 factorization
+    workgroups), element-wise against the oracle's full sparse solve."""
+    import torch
+    from paper_2008_01541_amd.driver import Alg1Runner
+    sc, x0, cen, rad, x_or, n_active = slab_alg1_reference
+    assert n_active >= 20
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen)
+    run.set_positions(x0)
+    run.set_spheres(cen, rad)
+    if pipelined:
+        run.run_pipelined(1, n_workgroups=384, factor_stream=torch.cuda.Stream())
+    else:
+        run.outer_iteration(n_inner=1)
+    torch.cuda.synchronize()
+    assert int((run.c > 0).sum()) == n_active
+    xg = run.positions()
+    run.close()
+    scale = np.abs(x_or - x0).max()
+    assert scale > 0.05
+    assert np.abs(xg - x_or).max() <= 1e-9 * scale
