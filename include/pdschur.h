@@ -129,6 +129,55 @@ pd_status pd_detect_spheres(pd_ctx *ctx, int32_t n_prox, const int32_t *prox,
 pd_status pd_detect_pairs(pd_ctx *ctx, int32_t n_pairs, const int32_t *pairs, double k,
                           const double *x2, int32_t *idx, double *w, double *c, double *t);
 
+/* Embedded (non-conforming) proxies (Sec. 3.3, eq. p_j_v): a proxy moves
+ * with the tetrahedron that contains its rest position, p = sum_k w_k x_k
+ * over that tet's four nodes.  For each point pts[:, j] (dev [3][n_pts]) this
+ * finds the lowest-index candidate tet (cand: dev int32 [4][n_cand],
+ * region-local node ids; positions pos: dev [3][m], e.g. the region's rest
+ * positions) whose four barycentric coordinates are all >= -1e-12, and
+ * writes tet[j] (dev int32 [n_pts]), its nodes eidx[j][0..3] (dev int32
+ * [n_pts][4]) and the coordinates ew[j][0..3] (dev [n_pts][4]); a point in
+ * no candidate gets tet -1, nodes -1 and weights 0.  Candidates with a node
+ * outside 0..m-1 are skipped. */
+pd_status pd_embed_points(pd_ctx *ctx, int32_t n_pts, const double *pts, int32_t n_cand,
+                          const int32_t *cand, const double *pos, int32_t *tet, int32_t *eidx,
+                          double *ew);
+
+/* Sphere detection (the rule of pd_detect_spheres) for embedded proxies
+ * given by eidx/ew as written by pd_embed_points: p_j = sum_k ew[j][k]
+ * x2[eidx[j][k]]; penalty j's W row is the proxy's four weights (slots 0..3;
+ * slots 4..7 unused), target on the sphere, c = k when inside.  A proxy with
+ * a node outside 0..m-1 gives an unused row (c = 0).  Output layout as
+ * pd_detect_spheres. */
+pd_status pd_detect_embedded_spheres(pd_ctx *ctx, int32_t n_prox, const int32_t *eidx,
+                                     const double *ew, int32_t n_sph, const double *spheres,
+                                     double k, const double *x2, int32_t *idx, double *w,
+                                     double *c, double *t);
+
+/* Rest-pose level-set self-collision of embedded proxies (Sec. 5.1, with the
+ * penalty of Sec. 3.3).  Bodies: candidate tets cand (dev int32 [4][n_cand],
+ * region-local), the rest signed distance of their body at their corners
+ * cand_phi (dev [4][n_cand], linear over the tet, < 0 inside) and their body
+ * id cand_body (dev int32 [n_cand]); proxy j (eidx/ew as above) belongs to
+ * body prox_body[j] (dev int32 [n_prox]).  Per proxy: p = sum w x2; the
+ * lowest candidate of another body that contains p in the deformed
+ * positions x2 (dev [3][m]), skipping tets that share a node with the
+ * proxy's own tet; X = its rest point (rest2: dev [3][m]) with the same
+ * barycentric coordinates and phi(X); if phi(X) < 0, the rest surface point
+ * X - phi g / |g|^2 (g = grad phi on that tet) is located (same rule) in the
+ * rest candidates of the same body, and the penalty is a zero-rest-length
+ * spring between the proxy and that point: W row = the proxy's four weights,
+ * then minus the surface point's coordinates over its tet's nodes (a node
+ * already in the row carries the sum in its slot; at most 8 slots), target
+ * 0, c = k.  Otherwise the row holds the proxy's weights and c = 0.  One
+ * wavefront per proxy, candidates scanned in index order.  Output layout as
+ * pd_detect_spheres. */
+pd_status pd_detect_levelset(pd_ctx *ctx, int32_t n_prox, const int32_t *eidx, const double *ew,
+                             const int32_t *prox_body, int32_t n_cand, const int32_t *cand,
+                             const double *cand_phi, const int32_t *cand_body,
+                             const double *rest2, double k, const double *x2, int32_t *idx,
+                             double *w, double *c, double *t);
+
 /* Penalty update (Sec. 3.3 eq. E_col_C and Sec. 4.3 eq. k22): stores the
  * penalty set for the next pd_global_solve, whose matrix becomes
  * H = S + W^T C W, and writes f_col = -W^T C (W x2 - t) (dev [3][m]).

@@ -46,6 +46,11 @@ _SIGS = {
     "pd_detect_spheres": [_P, C.c_int32, _P, C.c_int32, _P, C.c_double, _P, _P, _P, _P, _P],
     "pd_collision_update": [_P, C.c_int32, _P, _P, _P, _P, _P, _P],
     "pd_detect_pairs": [_P, C.c_int32, _P, C.c_double, _P, _P, _P, _P, _P],
+    "pd_embed_points": [_P, C.c_int32, _P, C.c_int32, _P, _P, _P, _P, _P],
+    "pd_detect_embedded_spheres": [_P, C.c_int32, _P, _P, C.c_int32, _P, C.c_double, _P, _P, _P,
+                                   _P, _P],
+    "pd_detect_levelset": [_P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, _P, C.c_double, _P,
+                           _P, _P, _P, _P],
     "pd_local_step_region": [_P, _P, _P, _P, C.c_int],
     "pd_assemble_rhs": [_P, _P, _P, _P, _P],
     "pd_global_solve": [_P, _P, _P, C.c_int, C.POINTER(pd_solve_info)],
@@ -255,6 +260,45 @@ class PDContext(_Handle):
             _ptr(x2, torch.float64, 3 * self.m, "x2"), _ptr(idx, torch.int32, 8 * npr, "idx"),
             _ptr(w, torch.float64, 8 * npr, "w"), _ptr(c, torch.float64, npr, "c"),
             _ptr(t, torch.float64, 3 * npr, "t")))
+
+    def embed_points(self, pts, cand, pos, tet, eidx, ew):
+        """pd_embed_points: pts [3][n], cand [4][nc] region-local, pos [3][m]."""
+        import torch
+        n = pts.numel() // 3
+        nc = cand.numel() // 4
+        self._chk(self._lib.pd_embed_points(
+            self._ctx, n, _ptr(pts, torch.float64, 3 * n, "pts"), nc,
+            _ptr(cand, torch.int32, 4 * nc, "cand"), _ptr(pos, torch.float64, 3 * self.m, "pos"),
+            _ptr(tet, torch.int32, n, "tet"), _ptr(eidx, torch.int32, 4 * n, "eidx"),
+            _ptr(ew, torch.float64, 4 * n, "ew")))
+
+    def detect_embedded_spheres(self, eidx, ew, spheres, k, x2, idx, w, c, t):
+        import torch
+        npx = eidx.numel() // 4
+        nsph = spheres.numel() // 4
+        self._chk(self._lib.pd_detect_embedded_spheres(
+            self._ctx, npx, _ptr(eidx, torch.int32, 4 * npx, "eidx"),
+            _ptr(ew, torch.float64, 4 * npx, "ew"), nsph,
+            _ptr(spheres, torch.float64, 4 * nsph, "spheres"), float(k),
+            _ptr(x2, torch.float64, 3 * self.m, "x2"), _ptr(idx, torch.int32, 8 * npx, "idx"),
+            _ptr(w, torch.float64, 8 * npx, "w"), _ptr(c, torch.float64, npx, "c"),
+            _ptr(t, torch.float64, 3 * npx, "t")))
+
+    def detect_levelset(self, eidx, ew, prox_body, cand, cand_phi, cand_body, rest2, k, x2,
+                        idx, w, c, t):
+        import torch
+        npx = eidx.numel() // 4
+        nc = cand.numel() // 4
+        self._chk(self._lib.pd_detect_levelset(
+            self._ctx, npx, _ptr(eidx, torch.int32, 4 * npx, "eidx"),
+            _ptr(ew, torch.float64, 4 * npx, "ew"), _ptr(prox_body, torch.int32, npx, "prox_body"),
+            nc, _ptr(cand, torch.int32, 4 * nc, "cand"),
+            _ptr(cand_phi, torch.float64, 4 * nc, "cand_phi"),
+            _ptr(cand_body, torch.int32, nc, "cand_body"),
+            _ptr(rest2, torch.float64, 3 * self.m, "rest2"), float(k),
+            _ptr(x2, torch.float64, 3 * self.m, "x2"), _ptr(idx, torch.int32, 8 * npx, "idx"),
+            _ptr(w, torch.float64, 8 * npx, "w"), _ptr(c, torch.float64, npx, "c"),
+            _ptr(t, torch.float64, 3 * npx, "t")))
 
     def collision_update(self, idx, w, c, t, x2, f_col):
         import torch

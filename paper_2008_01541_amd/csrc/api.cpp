@@ -907,6 +907,47 @@ pd_status pd_detect_pairs(pd_ctx* c, int32_t n_pairs, const int32_t* pairs, doub
   return c->check("pd_detect_pairs");
 }
 
+pd_status pd_embed_points(pd_ctx* c, int32_t n_pts, const double* pts, int32_t n_cand,
+                          const int32_t* cand, const double* pos, int32_t* tet, int32_t* eidx,
+                          double* ew) {
+  if (bad_ctx(c) || n_pts < 0 || n_cand < 0 ||
+      (n_pts > 0 && (!pts || !pos || !tet || !eidx || !ew || (n_cand > 0 && !cand))))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  embed_points(n_pts, pts, n_cand, cand, pos, (int)c->m, tet, eidx, ew, c->st);
+  return c->check("pd_embed_points");
+}
+
+pd_status pd_detect_embedded_spheres(pd_ctx* c, int32_t n_prox, const int32_t* eidx,
+                                     const double* ew, int32_t n_sph, const double* spheres,
+                                     double k, const double* x2, int32_t* idx, double* w,
+                                     double* cc, double* t) {
+  if (bad_ctx(c) || n_prox < 0 || n_sph < 0 || !(k >= 0.0) ||
+      (n_prox > 0 && (!eidx || !ew || !x2 || !idx || !w || !cc || !t)) || (n_sph > 0 && !spheres))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  PhaseTimer tm(c, PD_PHASE_DETECT);
+  detect_embedded_spheres(n_prox, eidx, ew, n_sph, spheres, k, x2, (int)c->m, idx, w, cc, t,
+                          c->st);
+  return c->check("pd_detect_embedded_spheres");
+}
+
+pd_status pd_detect_levelset(pd_ctx* c, int32_t n_prox, const int32_t* eidx, const double* ew,
+                             const int32_t* prox_body, int32_t n_cand, const int32_t* cand,
+                             const double* cand_phi, const int32_t* cand_body,
+                             const double* rest2, double k, const double* x2, int32_t* idx,
+                             double* w, double* cc, double* t) {
+  if (bad_ctx(c) || n_prox < 0 || n_cand < 0 || !(k >= 0.0) ||
+      (n_prox > 0 && (!eidx || !ew || !prox_body || !rest2 || !x2 || !idx || !w || !cc || !t)) ||
+      (n_cand > 0 && (!cand || !cand_phi || !cand_body)))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  PhaseTimer tm(c, PD_PHASE_DETECT);
+  detect_levelset(n_prox, eidx, ew, prox_body, n_cand, cand, cand_phi, cand_body, rest2, k, x2,
+                  (int)c->m, idx, w, cc, t, c->st);
+  return c->check("pd_detect_levelset");
+}
+
 pd_status pd_collision_update(pd_ctx* c, int32_t n_pen, const int32_t* idx, const double* w,
                               const double* cc, const double* t, const double* x2, double* f_col) {
   if (bad_ctx(c) || n_pen < 0 || !x2 || !f_col || (n_pen > 0 && (!idx || !w || !cc || !t)))

@@ -129,6 +129,16 @@ void detect_spheres(int n_prox, const int32_t* prox, int n_sph, const double* sp
                     hipStream_t st);
 void detect_pairs(int n_pairs, const int32_t* pairs, double k, const double* x2, int m,
                   int32_t* idx, double* w, double* c, double* t, hipStream_t st);
+// embedded proxies and rest-pose level sets (embed.hip)
+void embed_points(int n, const double* pts, int nc, const int32_t* cand, const double* pos, int m,
+                  int32_t* tet, int32_t* eidx, double* ew, hipStream_t st);
+void detect_embedded_spheres(int n_prox, const int32_t* eidx, const double* ew, int n_sph,
+                             const double* sph, double k, const double* x2, int m, int32_t* idx,
+                             double* w, double* c, double* t, hipStream_t st);
+void detect_levelset(int n_prox, const int32_t* eidx, const double* ew, const int32_t* prox_body,
+                     int nc, const int32_t* cand, const double* cand_phi,
+                     const int32_t* cand_body, const double* rest2, double k, const double* x2,
+                     int m, int32_t* idx, double* w, double* c, double* t, hipStream_t st);
 // act[0..*cnt) <- indices j < n_pen with c[j] != 0, increasing (device count);
 // rowptr (m + 1) and ent (8 n_pen) <- for every region row a, the keys 8 q + s
 // of the active slots naming it (act[q], slot s), increasing; cursor: m ints

@@ -41,6 +41,7 @@ class Alg1Runner:
         self.k_pen = float(k_pen)
         self.spheres = None
         self.pairs = None
+        self.mode = "nodes"
 
     def set_spheres(self, centers, radii):
         sph = np.vstack([np.asarray(centers, dtype=np.float64),
@@ -63,15 +64,78 @@ class Alg1Runner:
         npr = loc.shape[1]
         dev = self.x.device
         self.pairs = torch.tensor(np.ascontiguousarray(loc, dtype=np.int32), device=dev).reshape(-1)
+        self.mode = "pairs"
         self.n_prox = npr
         self.idx = torch.empty(8 * npr, dtype=torch.int32, device=dev)
         self.w = torch.empty(8 * npr, dtype=torch.float64, device=dev)
         self.c = torch.empty(npr, dtype=torch.float64, device=dev)
         self.t = torch.empty(3 * npr, dtype=torch.float64, device=dev)
 
+    def _penalty_buffers(self, n):
+        import torch
+        dev = self.x.device
+        self.n_prox = n
+        self.idx = torch.empty(8 * n, dtype=torch.int32, device=dev)
+        self.w = torch.empty(8 * n, dtype=torch.float64, device=dev)
+        self.c = torch.empty(n, dtype=torch.float64, device=dev)
+        self.t = torch.empty(3 * n, dtype=torch.float64, device=dev)
+
+    def embed(self, pts, cand_local, pos=None):
+        """Embedding of rest points pts (3, n) in the region tets cand_local
+        (4, nc) (pd_embed_points, at the region's rest positions unless pos
+        is given).  Returns device tensors (tet, eidx [n][4], ew [n][4])."""
+        import torch
+        c = self.ctx
+        dev = self.x.device
+        n = np.asarray(pts).shape[1]
+        if pos is None:
+            pos = torch.empty(3 * c.m, dtype=torch.float64, device=dev)
+            c.region_gather(torch.tensor(self.rest_np, device=dev).reshape(-1), pos)
+        tet = torch.empty(n, dtype=torch.int32, device=dev)
+        eidx = torch.empty(4 * n, dtype=torch.int32, device=dev)
+        ew = torch.empty(4 * n, dtype=torch.float64, device=dev)
+        c.embed_points(torch.tensor(np.ascontiguousarray(pts, dtype=np.float64), device=dev).reshape(-1),
+                       torch.tensor(np.ascontiguousarray(cand_local, dtype=np.int32), device=dev).reshape(-1),
+                       pos, tet, eidx, ew)
+        return tet, eidx, ew
+
+    def use_embedded(self, eidx, ew):
+        """Switch detection to sphere contact of embedded proxies (device eidx
+        int32 [n][4], ew [n][4] from embed())."""
+        self.mode = "embedded"
+        self.eidx, self.ew = eidx, ew
+        self.pairs = None
+        self._penalty_buffers(eidx.numel() // 4)
+
+    def use_levelset(self, eidx, ew, prox_body, cand_local, cand_phi, cand_body):
+        """Switch detection to rest-pose level-set self-collision of embedded
+        proxies (pd_detect_levelset): proxies eidx/ew with body ids prox_body,
+        bodies given by candidate region tets cand_local (4, nc), their corner
+        signed distances cand_phi (4, nc) and body ids cand_body (nc,)."""
+        import torch
+        c = self.ctx
+        dev = self.x.device
+        self.mode = "levelset"
+        self.pairs = None
+        self.eidx, self.ew = eidx, ew
+        self.ls_body = torch.tensor(np.ascontiguousarray(prox_body, dtype=np.int32), device=dev)
+        self.ls_cand = torch.tensor(np.ascontiguousarray(cand_local, dtype=np.int32), device=dev).reshape(-1)
+        self.ls_phi = torch.tensor(np.ascontiguousarray(cand_phi, dtype=np.float64), device=dev).reshape(-1)
+        self.ls_cbody = torch.tensor(np.ascontiguousarray(cand_body, dtype=np.int32), device=dev)
+        self.rest2 = torch.empty(3 * c.m, dtype=torch.float64, device=dev)
+        c.region_gather(torch.tensor(self.rest_np, device=dev).reshape(-1), self.rest2)
+        self._penalty_buffers(eidx.numel() // 4)
+
     def detect(self):
         c = self.ctx
-        if self.pairs is not None:
+        if self.mode == "embedded":
+            c.detect_embedded_spheres(self.eidx, self.ew, self.spheres, self.k_pen, self.x2,
+                                      self.idx, self.w, self.c, self.t)
+        elif self.mode == "levelset":
+            c.detect_levelset(self.eidx, self.ew, self.ls_body, self.ls_cand, self.ls_phi,
+                              self.ls_cbody, self.rest2, self.k_pen, self.x2, self.idx, self.w,
+                              self.c, self.t)
+        elif self.pairs is not None:
             c.detect_pairs(self.pairs, self.k_pen, self.x2, self.idx, self.w, self.c, self.t)
         else:
             c.detect_spheres(self.prox, self.spheres, self.k_pen, self.x2, self.idx, self.w,
