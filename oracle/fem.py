@@ -97,3 +97,13 @@ def scalar_stiffness(n, tets, B, vol, mu, subset=None):
     rows = np.repeat(tets.T, 4, axis=1).ravel()       # tets.T[t, a] repeated over b
     cols = np.tile(tets.T, (1, 4)).ravel()
     return sp.csr_matrix((Ke.ravel(), (rows, cols)), shape=(n, n))
+
+
+def lumped_mass(n, tets, vol, density):
+    """Lumped nodal masses for backward-Euler dynamics (Sec. 3.2 notes that PD
+    applies to implicit backward Euler as well): each tet gives a quarter of
+    density * Vol_e to each of its four nodes.  -> (n,)"""
+    m = np.zeros(n)
+    for a in range(4):
+        np.add.at(m, tets[a], 0.25 * density * vol)
+    return m

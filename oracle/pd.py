@@ -32,9 +32,19 @@ from . import fem, schur, collision
 
 class PDModel:
     """Constant data of one mesh: shape operators, partition, K blocks,
-    sparse factor of A11 and (lazily) the dense Schur complement."""
+    sparse factor of A11 and (lazily) the dense Schur complement.
 
-    def __init__(self, rest, tets, mu, dirichlet, region, build_schur=True):
+    Backward-Euler dynamics (dt > 0): the step minimises the incremental
+    potential 1/(2 dt^2) (x - y)^T M (x - y) + E(x) with y = x_n + dt v_n and
+    lumped masses M, the quasistatic energy plus an inertia term that is
+    quadratic in x and independent of the rotations.  Its Hessian D = M/dt^2
+    (diagonal) joins the constant matrix (K + D), so the Schur complement is
+    built once as before; its force -D (x - y) joins the outer-loop force of
+    every free node, with the E_alpha terms (it does not depend on R, so the
+    inner loop's update of f~2 by Sigma_alpha u2 keeps it exact)."""
+
+    def __init__(self, rest, tets, mu, dirichlet, region, build_schur=True, density=0.0,
+                 dt=0.0):
         self.rest = np.asarray(rest, dtype=np.float64)
         self.tets = np.asarray(tets)
         self.mu = float(mu)
@@ -52,6 +62,10 @@ class PDModel:
         self.alpha = ~self.beta
         self.B, self.vol = fem.shape_matrices(self.rest, self.tets)
         self.K = fem.scalar_stiffness(n, self.tets, self.B, self.vol, self.mu)
+        self.D = None
+        if dt > 0.0:
+            self.D = fem.lumped_mass(n, self.tets, self.vol, density) / (dt * dt)
+            self.K = sp.csr_matrix(self.K + sp.diags(self.D))
         Kb = fem.scalar_stiffness(n, self.tets, self.B, self.vol, self.mu, subset=self.beta)
         self.A11, self.A12, self.A21, self.A22 = schur.blocks(self.K, self.i1, self.i2)
         self.Abeta22 = sp.csr_matrix(Kb)[self.i2][:, self.i2]
@@ -87,10 +101,22 @@ class PDModel:
         tet of the subset)."""
         return fem.nodal_forces(x, self.tets, self.B, self.vol, self.mu, R, subset)
 
-    def energy(self, x, R_alpha, R_beta, pen=None):
+    def inertia_force(self, x, y):
+        """-D (x - y) (3, n), zero on Dirichlet nodes; zero without dynamics."""
+        if self.D is None or y is None:
+            return np.zeros_like(x)
+        f = -self.D[None, :] * (x - y)
+        f[:, self.dirichlet] = 0.0
+        return f
+
+    def energy(self, x, R_alpha, R_beta, pen=None, y=None):
         """E_hat(x, R) + E_col (eq. energyHat + Sec. 3.3) with the given rotations
-        and frozen penalty set."""
+        and frozen penalty set, plus the inertia term 1/2 (x - y)^T D (x - y)
+        over the free nodes under backward Euler."""
         e = fem.pd_energy(x, self.tets, self.B, self.vol, self.mu, R_alpha, self.alpha)
+        if self.D is not None and y is not None:
+            d = (x - y)[:, self.free]
+            e += 0.5 * float(np.sum(self.D[self.free][None, :] * d * d))
         if self.beta.any():
             e += fem.pd_energy(x, self.tets, self.B, self.vol, self.mu, R_beta, self.beta)
         if pen is not None:
@@ -120,15 +146,16 @@ def _x1_completed(model, x, f1, delta2, x2):
     return xe
 
 
-def alg1_outer_iteration(model, x, detect, n_inner=1, log=None, check_energy=False):
+def alg1_outer_iteration(model, x, detect, n_inner=1, log=None, check_energy=False, y=None):
     """One outer iteration of Alg. 1.  `detect(x2) -> (idx, w, c, t)` returns the
-    penalty set for the current region positions.  Returns the new x (3, n)."""
+    penalty set for the current region positions.  Under backward Euler, y is
+    the inertial target x_n + dt v_n.  Returns the new x (3, n)."""
     x = x.copy()
     i1, i2 = model.i1, model.i2
     # 1. local step on E_alpha
     R_a = model.rotations(x, model.alpha)
-    # 2. forces from E_alpha only
-    f = model.forces(x, R_a, model.alpha)
+    # 2. forces from E_alpha only (plus inertia under backward Euler)
+    f = model.forces(x, R_a, model.alpha) + model.inertia_force(x, y)
     f1, f2 = f[:, i1], f[:, i2]
     # 3. forward substitution: w = A11^-1 f1, y2 = f2 - A21 w  (steps 3.1, 3.2)
     if i1.size:
@@ -156,7 +183,7 @@ def alg1_outer_iteration(model, x, detect, n_inner=1, log=None, check_energy=Fal
         g = ft + fb + collision.penalty_force(m, idx, wts, c, t, x2)
         if check_energy and log is not None:
             log.energies.append(model.energy(_x1_completed(model, x, f1, delta2, x2),
-                                             R_a, R_b, pen))
+                                             R_a, R_b, pen, y))
         # 4.5 dense Cholesky solve, three right-hand sides
         cf = sla.cho_factor(H, lower=True)
         u2 = sla.cho_solve(cf, g.T).T
@@ -168,7 +195,7 @@ def alg1_outer_iteration(model, x, detect, n_inner=1, log=None, check_energy=Fal
             log.u2_norms.append(float(np.linalg.norm(u2)))
             if check_energy:
                 log.energies.append(model.energy(_x1_completed(model, x, f1, delta2, x2),
-                                                 R_a, R_b, pen))
+                                                 R_a, R_b, pen, y))
     # 5. back substitution x1 += A11^-1 (f1 - A12 Delta2)
     if i1.size:
         x[:, i1] += _solve_cols(model.lu11, f1 - (model.A12 @ delta2.T).T)
@@ -189,13 +216,14 @@ def full_matrix_with_penalty(model, pen):
     return sp.csc_matrix(Kf + Pf), pos
 
 
-def plain_pd_iteration(model, x, detect):
+def plain_pd_iteration(model, x, detect, y=None):
     """Plain full-mesh PD iteration (Sec. 3.2-3.3): local step on every tet,
     detection, then one solve of (K + W^T C W) dx = f_el + f_col over all free
-    nodes.  Returns the new x."""
+    nodes (K including D and f_el the inertia force under backward Euler,
+    inertial target y).  Returns the new x."""
     x = x.copy()
     R = model.rotations(x, np.ones(model.tets.shape[1], dtype=bool))
-    f = model.forces(x, R, np.ones(model.tets.shape[1], dtype=bool))
+    f = model.forces(x, R, np.ones(model.tets.shape[1], dtype=bool)) + model.inertia_force(x, y)
     pen = detect(x[:, model.i2])
     idx, w, c, t = pen
     A, pos = full_matrix_with_penalty(model, pen)
@@ -234,3 +262,10 @@ def sphere_detector(model, proxy_local, centers, radii, k):
         c, t = collision.detect_spheres(x2[:, proxy_local], centers, radii, k)
         return collision.conforming_penalties(proxy_local, c, t)
     return detect
+
+
+def backward_euler_advance(x_new, x_old, dt):
+    """End of a backward-Euler step: v_{n+1} = (x_{n+1} - x_n) / dt and the
+    next step's inertial target y = x_{n+1} + dt v_{n+1}.  Returns (v, y)."""
+    v = (x_new - x_old) / dt
+    return v, x_new + dt * v
