@@ -52,20 +52,34 @@ def polar_rotation(F):
     return U @ D @ Vt
 
 
-def element_forces(F, R, B, vol, mu):
+def clamped_projection(F, sigma_min, sigma_max):
+    """Biphasic strain limit (Sec. 5.3): the closest matrix to F whose singular
+    values lie in [sigma_min, sigma_max], Q = U clamp(Sigma) V^T from the SVD
+    F = U Sigma V^T (singular values >= 0, no sign fix: the set is not limited
+    to rotations)."""
+    U, s, Vt = np.linalg.svd(F)
+    return U @ (np.clip(s, sigma_min, sigma_max)[..., :, None] * Vt)
+
+
+def element_forces(F, R, B, vol, mu, Q=None, mu_p=0.0):
     """Per-vertex elemental forces f_{e,a} = -Vol_e P (B_e)_a with P = 2 mu (F - R)
-    (Sec. 3.2: first Piola stress of the PD energy, R held fixed).  -> (T, 4, 3)"""
+    (Sec. 3.2: first Piola stress of the PD energy, R held fixed), plus
+    2 mu' (F - Q) for the biphasic material of Sec. 5.3 (Q held fixed).
+    -> (T, 4, 3)"""
     P = 2.0 * mu * (F - R)
+    if Q is not None and mu_p != 0.0:
+        P = P + 2.0 * mu_p * (F - Q)
     return -vol[:, None, None] * np.einsum("tij,taj->tai", P, B)
 
 
-def nodal_forces(x, tets, B, vol, mu, R, subset=None):
+def nodal_forces(x, tets, B, vol, mu, R, subset=None, Q=None, mu_p=0.0):
     """Sum elemental forces onto nodes.  subset: boolean tet mask or None (all);
-    R holds one rotation per tet of the subset.  Returns f (3, n)."""
+    R (and Q for the biphasic term) hold one matrix per tet of the subset.
+    Returns f (3, n)."""
     if subset is not None:
         tets, B, vol = tets[:, subset], B[subset], vol[subset]
     F = deformation_gradients(x, tets, B)
-    fe = element_forces(F, R, B, vol, mu)               # (T, 4, 3)
+    fe = element_forces(F, R, B, vol, mu, Q, mu_p)      # (T, 4, 3)
     f = np.zeros_like(x)
     for a in range(4):
         for i in range(3):
@@ -73,13 +87,17 @@ def nodal_forces(x, tets, B, vol, mu, R, subset=None):
     return f
 
 
-def pd_energy(x, tets, B, vol, mu, R, subset=None):
-    """E_hat(x, R) = sum_e Vol_e mu ||F_e(x) - R_e||_F^2  (eq. energyHat).
-    R holds one rotation per tet of the subset."""
+def pd_energy(x, tets, B, vol, mu, R, subset=None, Q=None, mu_p=0.0):
+    """E_hat(x, R) = sum_e Vol_e mu ||F_e(x) - R_e||_F^2  (eq. energyHat), plus
+    Vol_e mu' ||F_e - Q_e||^2 for the biphasic material (Sec. 5.3).
+    R (and Q) hold one matrix per tet of the subset."""
     if subset is not None:
         tets, B, vol = tets[:, subset], B[subset], vol[subset]
     F = deformation_gradients(x, tets, B)
-    return float(np.sum(vol * mu * np.sum((F - R) ** 2, axis=(1, 2))))
+    e = np.sum(vol * mu * np.sum((F - R) ** 2, axis=(1, 2)))
+    if Q is not None and mu_p != 0.0:
+        e += np.sum(vol * mu_p * np.sum((F - Q) ** 2, axis=(1, 2)))
+    return float(e)
 
 
 def corotated_energy(x, tets, B, vol, mu):

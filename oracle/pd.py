@@ -44,7 +44,7 @@ class PDModel:
     inner loop's update of f~2 by Sigma_alpha u2 keeps it exact)."""
 
     def __init__(self, rest, tets, mu, dirichlet, region, build_schur=True, density=0.0,
-                 dt=0.0):
+                 dt=0.0, mu_prime=0.0, sigma_min=0.0, sigma_max=np.inf):
         self.rest = np.asarray(rest, dtype=np.float64)
         self.tets = np.asarray(tets)
         self.mu = float(mu)
@@ -61,12 +61,18 @@ class PDModel:
         self.beta = np.all(in2[self.tets], axis=0)
         self.alpha = ~self.beta
         self.B, self.vol = fem.shape_matrices(self.rest, self.tets)
-        self.K = fem.scalar_stiffness(n, self.tets, self.B, self.vol, self.mu)
+        # biphasic material (Sec. 5.3): a second projective term mu' ||F - Q||^2
+        # with Q the strain-limited projection of F; its constant Hessian adds
+        # mu' to mu in K
+        self.mu_p = float(mu_prime)
+        self.sigma = (float(sigma_min), float(sigma_max))
+        self.K = fem.scalar_stiffness(n, self.tets, self.B, self.vol, self.mu + self.mu_p)
         self.D = None
         if dt > 0.0:
             self.D = fem.lumped_mass(n, self.tets, self.vol, density) / (dt * dt)
             self.K = sp.csr_matrix(self.K + sp.diags(self.D))
-        Kb = fem.scalar_stiffness(n, self.tets, self.B, self.vol, self.mu, subset=self.beta)
+        Kb = fem.scalar_stiffness(n, self.tets, self.B, self.vol, self.mu + self.mu_p,
+                                  subset=self.beta)
         self.A11, self.A12, self.A21, self.A22 = schur.blocks(self.K, self.i1, self.i2)
         self.Abeta22 = sp.csr_matrix(Kb)[self.i2][:, self.i2]
         self.lu11 = schur.sparse_factor(self.A11) if self.i1.size else None
@@ -96,10 +102,18 @@ class PDModel:
         F = fem.deformation_gradients(x, self.tets[:, subset], self.B[subset])
         return fem.polar_rotation(F)
 
-    def forces(self, x, R, subset):
-        """Elastic forces (3, n) from the tets in `subset` with rotations R (one per
-        tet of the subset)."""
-        return fem.nodal_forces(x, self.tets, self.B, self.vol, self.mu, R, subset)
+    def projections(self, x, subset):
+        """Biphasic local step (Sec. 5.3): Q_e = clamped-SVD projection of F_e for
+        the tets in `subset`; None for the plain corotated material."""
+        if self.mu_p == 0.0:
+            return None
+        F = fem.deformation_gradients(x, self.tets[:, subset], self.B[subset])
+        return fem.clamped_projection(F, *self.sigma)
+
+    def forces(self, x, R, subset, Q=None):
+        """Elastic forces (3, n) from the tets in `subset` with rotations R (and
+        biphasic projections Q), one per tet of the subset."""
+        return fem.nodal_forces(x, self.tets, self.B, self.vol, self.mu, R, subset, Q, self.mu_p)
 
     def inertia_force(self, x, y):
         """-D (x - y) (3, n), zero on Dirichlet nodes; zero without dynamics."""
@@ -109,16 +123,18 @@ class PDModel:
         f[:, self.dirichlet] = 0.0
         return f
 
-    def energy(self, x, R_alpha, R_beta, pen=None, y=None):
+    def energy(self, x, R_alpha, R_beta, pen=None, y=None, Q_alpha=None, Q_beta=None):
         """E_hat(x, R) + E_col (eq. energyHat + Sec. 3.3) with the given rotations
         and frozen penalty set, plus the inertia term 1/2 (x - y)^T D (x - y)
         over the free nodes under backward Euler."""
-        e = fem.pd_energy(x, self.tets, self.B, self.vol, self.mu, R_alpha, self.alpha)
+        e = fem.pd_energy(x, self.tets, self.B, self.vol, self.mu, R_alpha, self.alpha, Q_alpha,
+                          self.mu_p)
         if self.D is not None and y is not None:
             d = (x - y)[:, self.free]
             e += 0.5 * float(np.sum(self.D[self.free][None, :] * d * d))
         if self.beta.any():
-            e += fem.pd_energy(x, self.tets, self.B, self.vol, self.mu, R_beta, self.beta)
+            e += fem.pd_energy(x, self.tets, self.B, self.vol, self.mu, R_beta, self.beta, Q_beta,
+                               self.mu_p)
         if pen is not None:
             idx, w, c, t = pen
             e += collision.penalty_energy(idx, w, c, t, x[:, self.i2])
@@ -152,10 +168,12 @@ def alg1_outer_iteration(model, x, detect, n_inner=1, log=None, check_energy=Fal
     the inertial target x_n + dt v_n.  Returns the new x (3, n)."""
     x = x.copy()
     i1, i2 = model.i1, model.i2
-    # 1. local step on E_alpha
+    # 1. local step on E_alpha (rotations, and strain-limited projections for
+    #    the biphasic material)
     R_a = model.rotations(x, model.alpha)
+    Q_a = model.projections(x, model.alpha)
     # 2. forces from E_alpha only (plus inertia under backward Euler)
-    f = model.forces(x, R_a, model.alpha) + model.inertia_force(x, y)
+    f = model.forces(x, R_a, model.alpha, Q_a) + model.inertia_force(x, y)
     f1, f2 = f[:, i1], f[:, i2]
     # 3. forward substitution: w = A11^-1 f1, y2 = f2 - A21 w  (steps 3.1, 3.2)
     if i1.size:
@@ -175,15 +193,16 @@ def alg1_outer_iteration(model, x, detect, n_inner=1, log=None, check_energy=Fal
         xfull = x.copy()
         xfull[:, i2] = x2
         R_b = model.rotations(xfull, model.beta) if model.beta.any() else np.zeros((0, 3, 3))
+        Q_b = model.projections(xfull, model.beta) if model.beta.any() else None
         idx, wts, c, t = pen
         # 4.3 H = Sigma_alpha + A22^(beta) + C22 = Sigma + W^T C W
         H = S + collision.penalty_matrix(m, idx, wts, c)
         # 4.4 g = f~2 + f2^(beta) + f2^(col)
-        fb = model.forces(xfull, R_b, model.beta)[:, i2] if model.beta.any() else 0.0
+        fb = model.forces(xfull, R_b, model.beta, Q_b)[:, i2] if model.beta.any() else 0.0
         g = ft + fb + collision.penalty_force(m, idx, wts, c, t, x2)
         if check_energy and log is not None:
             log.energies.append(model.energy(_x1_completed(model, x, f1, delta2, x2),
-                                             R_a, R_b, pen, y))
+                                             R_a, R_b, pen, y, Q_a, Q_b))
         # 4.5 dense Cholesky solve, three right-hand sides
         cf = sla.cho_factor(H, lower=True)
         u2 = sla.cho_solve(cf, g.T).T
@@ -195,7 +214,7 @@ def alg1_outer_iteration(model, x, detect, n_inner=1, log=None, check_energy=Fal
             log.u2_norms.append(float(np.linalg.norm(u2)))
             if check_energy:
                 log.energies.append(model.energy(_x1_completed(model, x, f1, delta2, x2),
-                                                 R_a, R_b, pen, y))
+                                                 R_a, R_b, pen, y, Q_a, Q_b))
     # 5. back substitution x1 += A11^-1 (f1 - A12 Delta2)
     if i1.size:
         x[:, i1] += _solve_cols(model.lu11, f1 - (model.A12 @ delta2.T).T)
@@ -222,8 +241,10 @@ def plain_pd_iteration(model, x, detect, y=None):
     nodes (K including D and f_el the inertia force under backward Euler,
     inertial target y).  Returns the new x."""
     x = x.copy()
-    R = model.rotations(x, np.ones(model.tets.shape[1], dtype=bool))
-    f = model.forces(x, R, np.ones(model.tets.shape[1], dtype=bool)) + model.inertia_force(x, y)
+    every = np.ones(model.tets.shape[1], dtype=bool)
+    R = model.rotations(x, every)
+    Q = model.projections(x, every)
+    f = model.forces(x, R, every, Q) + model.inertia_force(x, y)
     pen = detect(x[:, model.i2])
     idx, w, c, t = pen
     A, pos = full_matrix_with_penalty(model, pen)
