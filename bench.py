@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6
+BIPHASIC = {"mu_prime_over_mu": 10.0, "sigma_min": 0.95, "sigma_max": 1.05}
+DYNAMICS = {"density": 1000.0, "dt": 1.0 / 30.0}
 # HBM bytes per launch of the Schur factorization, from the rocprofv3 counter
 # runs summarised in this file (FETCH_SIZE and WRITE_SIZE, each scaled by the
 # same counter on a plain copy of known size); valid only while the kernel
@@ -173,14 +175,20 @@ def warmstart_leg(run, args):
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t0
         tr = P.slab56_trajectory(999)
-        rows = evaluate(run, ws, tr.centers, tr.radii, n_frames=args.ws_eval + 1, tol=1e-8,
+        rows = evaluate(run, ws, tr.centers, tr.radii, n_frames=args.ws_eval + 2, tol=1e-8,
                         judge_tol=1e-9, accept=1e-6)
         print(f"warm start: evaluated {args.ws_eval} frames", file=sys.stderr, flush=True)
+        # the non-learned predictor on the same frames (previous increment repeated)
+        ex = summarize(evaluate(run, ws, tr.centers, tr.radii, n_frames=args.ws_eval + 2,
+                                tol=1e-8, judge_tol=1e-9, accept=1e-6, predictor="extrapolate"))
         return {"train_frames": int(X.shape[0]), "train_trajectories": args.ws_train,
                 "epochs": args.ws_epochs, "loss_first": hist[0], "loss_last": hist[-1],
                 "generate_s": round(gen_s, 2), "train_s": round(train_s, 2),
                 "run_tol": 1e-8, "judge_tol": 1e-9, "accept": 1e-6,
                 **summarize(rows),
+                "extrapolation": {k: ex[k] for k in ["charged_outer_iters_per_frame",
+                                                     "iters_saved_frac", "wall_saved_frac",
+                                                     "warm_start_err_mean", "fell_back"]},
                 "frames": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
                            for r in rows]}
     except Exception as e:              # report, do not hide, a failing leg
@@ -248,7 +256,26 @@ def bench_slit(args):
     t0 = time.perf_counter()
     run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, np.zeros(0, np.int64),
                      sc.k_pen)
-    run.use_pairs(sc.pairs)
+    n_proxies = int(sc.pairs.shape[1])
+    if args.contact == "levelset":
+        # rest-pose level sets of the two lips, proxies embedded in each lip
+        bd = P.slit_levelset_bodies(sc, per_cell=1.0, seed=15)
+        rid = sc.region_ids()
+        pos = np.full(sc.n_nodes, -1, dtype=np.int64)
+        pos[rid] = np.arange(rid.size)
+        cand = pos[bd.body_tets].astype(np.int32)
+        eidx = torch.empty(4 * bd.proxy_body.size, dtype=torch.int32, device="cuda")
+        ew = torch.empty(4 * bd.proxy_body.size, dtype=torch.float64, device="cuda")
+        for body in (0, 1):
+            sel = np.nonzero(bd.proxy_body == body)[0]
+            _, ei, wi = run.embed(bd.proxy_points[:, sel], cand[:, bd.body_id == body])
+            s0, s1 = int(sel[0]), int(sel[-1]) + 1           # each body's proxies are contiguous
+            eidx[4 * s0:4 * s1] = ei
+            ew[4 * s0:4 * s1] = wi
+        run.use_levelset(eidx, ew, bd.proxy_body, cand, bd.body_phi, bd.body_id)
+        n_proxies = int(bd.proxy_body.size)
+    else:
+        run.use_pairs(sc.pairs)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     ctx = run.ctx
@@ -298,11 +325,12 @@ def bench_slit(args):
         "value": max(eager_value, pipe_value or 0.0), "unit": "PD iterations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "slit64x64x40_kuhn", "tets": int(sc.n_tets),
-                   "nodes": int(sc.n_nodes), "region_nodes": int(m), "pairs": int(sc.pairs.shape[1]),
+                   "nodes": int(sc.n_nodes), "region_nodes": int(m), "contact": args.contact,
+                   "proxies": n_proxies,
                    "interior_levels": ctx.n_levels, "k_pen": sc.k_pen},
         "eager_pd_iters_per_s": eager_value, "pipelined_pd_iters_per_s": pipe_value,
         "pipelined_factor_workgroups": None if args.no_pipeline else args.factor_wg,
-        "active_pairs_last": act,
+        "active_penalties_last": act,
         "schur_cholesky_tflops": tf, "schur_cholesky_ms": fac,
         "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
         "schur_build_s": build_s}
@@ -330,6 +358,18 @@ def main():
     ap.add_argument("--workload", default="slab56", choices=["slab56", "slit64"],
                     help="slab56: the 602K-tet slab with spheres (default); slit64: the "
                          "983K-tet self-contact slit closed by a jaw rotation")
+    ap.add_argument("--material", default="corotated", choices=["corotated", "biphasic"],
+                    help="slab56 material: corotated (default) or the biphasic strain limit "
+                         "(mu' = 10 mu, singular values limited to [0.95, 1.05])")
+    ap.add_argument("--dynamics", action="store_true",
+                    help="slab56 with backward Euler (density 1000, dt 1/30; velocity and "
+                         "inertial target advance with each frame)")
+    ap.add_argument("--proxies", default="nodes", choices=["nodes", "embedded"],
+                    help="slab56 collision proxies: the top-face nodes (default) or four seeded "
+                         "points per top-face cell embedded in the region tets")
+    ap.add_argument("--contact", default="pairs", choices=["pairs", "levelset"],
+                    help="slit64 self-contact: lip node pairs (default) or rest-pose level sets "
+                         "of the two lips with embedded proxies")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before timing (counter calibration)")
     ap.add_argument("--no-overlap-forward", action="store_true",
@@ -371,7 +411,25 @@ def main():
     stream = torch.cuda.Stream()            # non-default stream: capturable
     torch.cuda.set_stream(stream)
     t0 = time.perf_counter()
-    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen)
+    extra = {}
+    if args.material == "biphasic":
+        extra.update(mu_prime=BIPHASIC["mu_prime_over_mu"] * sc.mu,
+                     sigma_min=BIPHASIC["sigma_min"], sigma_max=BIPHASIC["sigma_max"])
+    if args.dynamics:
+        extra.update(density=DYNAMICS["density"], dt=DYNAMICS["dt"])
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen,
+                     **extra)
+    n_proxies = int(sc.proxies.size)
+    if args.proxies == "embedded":
+        # four seeded proxies per top-face cell, embedded in the region tets
+        pts = P.top_face_proxy_points(sc, 4 * sc.nx * sc.ny, seed=11)
+        rid = sc.region_ids()
+        pos = np.full(sc.n_nodes, -1, dtype=np.int64)
+        pos[rid] = np.arange(rid.size)
+        T = pos[sc.tets[:, P.region_tets(sc.rest, sc.tets, sc.region, sc.dirichlet)]]
+        _, eidx, ew = run.embed(pts, T.astype(np.int32))
+        run.use_embedded(eidx, ew)
+        n_proxies = int(pts.shape[1])
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     ctx = run.ctx
@@ -382,7 +440,13 @@ def main():
     for fr in sorted(set(frames)):
         run.set_spheres(sc.spheres.centers(fr), sc.spheres.radii)
         sph[fr] = run.spheres
+    def new_frame(it):
+        # backward Euler: velocity and inertial target advance with the frame
+        if args.dynamics and it > 0 and frames[it] != frames[it - 1]:
+            run.advance_time_step()
+
     for it in range(args.warmup):
+        new_frame(it)
         run.spheres = sph[frames[it]]
         run.outer_iteration(n_inner=args.inner)
     torch.cuda.synchronize()
@@ -391,6 +455,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(args.warmup, nit):
+        new_frame(it)
         run.spheres = sph[frames[it]]
         run.outer_iteration(n_inner=args.inner)
     torch.cuda.synchronize()
@@ -406,19 +471,20 @@ def main():
         fac_stream = torch.cuda.Stream()
         run.run_pipelined(args.warmup, spheres_of=lambda k: sph[frames[k]],
                           n_workgroups=args.factor_wg, factor_stream=fac_stream,
-                          overlap_forward=not args.no_overlap_forward)
+                          overlap_forward=not args.no_overlap_forward, before_local=new_frame)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         run.run_pipelined(args.steps, spheres_of=lambda k: sph[frames[args.warmup + k]],
                           n_workgroups=args.factor_wg, factor_stream=fac_stream,
-                          overlap_forward=not args.no_overlap_forward)
+                          overlap_forward=not args.no_overlap_forward,
+                          before_local=lambda k: new_frame(args.warmup + k))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         pipe_value = args.steps / (t1 - t0)
         value = max(value, pipe_value)
     graph_value = None
     graph_error = None
-    if not args.no_graph:
+    if not args.no_graph and not args.dynamics:
         # one outer iteration captured into a HIP graph; frames change by
         # copying the next sphere positions into the captured input buffer
         try:
@@ -467,7 +533,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "slab56x56x32_kuhn", "tets": int(sc.n_tets),
                    "nodes": int(sc.n_nodes), "region_nodes": int(m), "interior_levels": ctx.n_levels,
-                   "spheres": 16, "k_pen": sc.k_pen, "outer_per_step": 1,
+                   "spheres": 16, "k_pen": sc.k_pen, "proxies": args.proxies,
+                   "n_proxies": n_proxies, "material": args.material,
+                   **({"biphasic": BIPHASIC} if args.material == "biphasic" else {}),
+                   "dynamics": DYNAMICS if args.dynamics else "quasistatic", "outer_per_step": 1,
                    "inner_per_outer": args.inner, "precision": "fp64"},
         "eager_pd_iters_per_s": eager_value,
         "pipelined_pd_iters_per_s": pipe_value,
@@ -489,7 +558,7 @@ def main():
     }
     if not args.no_precision_modes:
         out["precision_modes"] = precision_modes(run, sph[frames[-1]], args.inner)
-    if not args.no_warmstart:
+    if not args.no_warmstart and args.proxies == "nodes" and not args.dynamics:
         out["warm_start"] = warmstart_leg(run, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, frames[-1])

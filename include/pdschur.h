@@ -56,6 +56,11 @@ typedef struct {
   const uint8_t *region;    /* host [n_nodes] 1 = collision-prone node (x2) */
   const uint8_t *dirichlet; /* host [n_nodes] 1 = prescribed node (not an unknown) */
   double mu;                /* shear modulus; lambda is dropped (Sec. 3.2) */
+  double density;           /* backward Euler: mass per unit rest volume (dt > 0) */
+  double dt;                /* backward-Euler time step; 0 = quasistatic (Sec. 3.2) */
+  double mu_prime;          /* biphasic material (Sec. 5.3): stiffness of the strain */
+  double sigma_min;         /*   limit mu' ||F - Q||^2, Q = F with its singular values */
+  double sigma_max;         /*   clamped to [sigma_min, sigma_max]; mu_prime = 0: off */
 } pd_mesh;
 
 typedef struct {
@@ -97,9 +102,30 @@ pd_status pd_region_gather(pd_ctx *ctx, const double *x, double *x2);
 /* Local step and forces on E_alpha (Alg. 1 steps 1-2): R_e = polar(F_e(x))
  * (Sec. 3.2, orthogonal Procrustes, det R = +1), P = 2 mu (F - R) and
  * f = -sum_e Vol_e P B_e on every node.  x, f: dev [3][n_nodes]; R_alpha:
- * dev [9][n_alpha] row-major 3x3 per tet or NULL.  Forces on Dirichlet
- * nodes are written too (they are not used by the solve). */
-pd_status pd_local_step_full(pd_ctx *ctx, const double *x, double *R_alpha, double *f);
+ * dev [9][n_alpha] row-major 3x3 per tet (FP64, or FP32 with rot_fp32) or
+ * NULL.  rot_fp32 = 1: the polar decomposition (and the biphasic projection)
+ * in FP32 from the rounded F, forces accumulated in FP64.  Forces on
+ * Dirichlet nodes are written too (they are not used by the solve). */
+pd_status pd_local_step_full(pd_ctx *ctx, const double *x, void *R_alpha, double *f,
+                             int rot_fp32);
+
+/* Backward Euler (mesh.dt > 0; Sec. 3.2 states that PD applies to implicit
+ * backward Euler as it does to the quasistatic problem): each step minimises
+ * 1/(2 dt^2) (x - y)^T M (x - y) + E(x) with lumped masses M (a quarter of
+ * density * Vol_e to each node of tet e) and the inertial target
+ * y = x_n + dt v_n.  pd_schur_build then adds D = M / dt^2 to the constant
+ * matrix (so to S and the interior factor), and pd_local_step_full adds the
+ * inertia force -D (x - y) on every free node.  This call sets the target y
+ * (dev [3][n_nodes], caller-owned, read by every later pd_local_step_full;
+ * NULL clears it).  PD_ERR_STATE for a quasistatic context; with dynamics,
+ * pd_local_step_full returns PD_ERR_STATE while no target is set. */
+pd_status pd_set_inertia_target(pd_ctx *ctx, const double *y);
+
+/* End of a backward-Euler step (all dev [3][n_nodes]): v = (x - x_prev) / dt,
+ * then x_prev = x and y = x + dt v (the next step's target).  PD_ERR_STATE for
+ * a quasistatic context. */
+pd_status pd_time_step_advance(pd_ctx *ctx, const double *x, double *x_prev, double *v,
+                               double *y);
 
 /* Forward substitution through the interior factor (Alg. 1 step 3;
  * Sec. 4.4 Step 1): y2 = f2 - A21 A11^-1 f1, with f taken from f [3][n_nodes].
@@ -416,6 +442,26 @@ pd_status pd_warmstart_input(pd_ctx *ctx, const double *x2, const double *x2_pre
 /* x[:, region] += scale * d2 for a float32 region increment d2 (dev [3][m]),
  * x dev [3][n_nodes]: applies a predicted displacement to the region nodes. */
 pd_status pd_region_add_f32(pd_ctx *ctx, const float *d2, double scale, double *x);
+
+/* A predicted region increment applied with the static response of the
+ * interior (Sec. 4.4 Step 3 with a zero interior force): d = scale * d2
+ * (d2 float32 dev [3][m]), plus x2_prev1 - x2_prev2 when both are given (dev
+ * [3][m]: the previous frame's increment, so that d2 is a correction of it);
+ * then x2 += d and x1 -= A11^-1 A12 d, x dev [3][n_nodes].  The interior
+ * nodes then sit where the constant system puts them for the moved region,
+ * so the next local step sees the prediction everywhere.  Uses the interior
+ * factor's sweep; a following pd_backsub needs a new pd_condense_rhs
+ * (PD_ERR_STATE otherwise).  Only one of x2_prev1, x2_prev2 given ->
+ * PD_ERR_INVALID. */
+pd_status pd_warmstart_apply(pd_ctx *ctx, const float *d2, double scale, const double *x2_prev1,
+                             const double *x2_prev2, double *x);
+
+/* Training target of the warm-start network in its residual form: out =
+ * scale * ((x2 - x2_prev1) - (x2_prev1 - x2_prev2)) (float32 dev [3][m]; all
+ * x dev [3][m]), the change of the region increment from one frame to the
+ * next. */
+pd_status pd_warmstart_target(pd_ctx *ctx, const double *x2, const double *x2_prev1,
+                              const double *x2_prev2, float scale, float *out);
 
 /* Convergence measure of an outer iteration: out[0] = ||x - x_prev||_2 and
  * out[1] = ||x - X||_2 over all free nodes (X = rest positions), for the

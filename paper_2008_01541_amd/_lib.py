@@ -25,7 +25,8 @@ class PDError(RuntimeError):
 class pd_mesh(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("rest", C.c_void_p),
                 ("tets", C.c_void_p), ("region", C.c_void_p), ("dirichlet", C.c_void_p),
-                ("mu", C.c_double)]
+                ("mu", C.c_double), ("density", C.c_double), ("dt", C.c_double),
+                ("mu_prime", C.c_double), ("sigma_min", C.c_double), ("sigma_max", C.c_double)]
 
 
 class pd_solve_info(C.Structure):
@@ -41,7 +42,9 @@ _SIGS = {
     "pd_region_nodes": [_P, _P],
     "pd_get_schur": [_P, _P],
     "pd_region_gather": [_P, _P, _P],
-    "pd_local_step_full": [_P, _P, _P, _P],
+    "pd_local_step_full": [_P, _P, _P, _P, C.c_int],
+    "pd_set_inertia_target": [_P, _P],
+    "pd_time_step_advance": [_P, _P, _P, _P, _P],
     "pd_condense_rhs": [_P, _P, _P],
     "pd_detect_spheres": [_P, C.c_int32, _P, C.c_int32, _P, C.c_double, _P, _P, _P, _P, _P],
     "pd_collision_update": [_P, C.c_int32, _P, _P, _P, _P, _P, _P],
@@ -71,6 +74,8 @@ _SIGS = {
     "pd_displacement_change": [_P, _P, _P, _P],
     "pd_warmstart_input": [_P, _P, _P, C.c_float, C.c_int32, _P, _P, _P],
     "pd_region_add_f32": [_P, _P, C.c_double, _P],
+    "pd_warmstart_apply": [_P, _P, C.c_double, _P, _P, _P],
+    "pd_warmstart_target": [_P, _P, _P, _P, C.c_float, _P],
     "pd_set_stream": [_P, _P],
     "pd_use_stream": [_P, _P],
     "pd_factor": [_P, C.c_int32, C.c_int32],
@@ -176,7 +181,8 @@ def _ptr(t, dtype=None, numel=None, name="tensor"):
 class PDContext(_Handle):
     """One built mesh (pd_schur_build) and its per-iteration entry points."""
 
-    def __init__(self, rest, tets, region, dirichlet, mu, stream=None):
+    def __init__(self, rest, tets, region, dirichlet, mu, stream=None, density=0.0, dt=0.0,
+                 mu_prime=0.0, sigma_min=0.0, sigma_max=0.0):
         import torch
         lib = load_library()
         self._lib = lib
@@ -191,7 +197,8 @@ class PDContext(_Handle):
             raise ValueError("mesh arrays have inconsistent shapes")
         self._keep = (rest, tets, region, dirichlet)
         mesh = pd_mesh(n, T, rest.ctypes.data, tets.ctypes.data, region.ctypes.data,
-                       dirichlet.ctypes.data, float(mu))
+                       dirichlet.ctypes.data, float(mu), float(density), float(dt),
+                       float(mu_prime), float(sigma_min), float(sigma_max))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -229,12 +236,25 @@ class PDContext(_Handle):
         self._chk(self._lib.pd_region_gather(self._ctx, _ptr(x, torch.float64, 3 * self.n, "x"),
                                              _ptr(x2, torch.float64, 3 * self.m, "x2")))
 
-    def local_step_full(self, x, f, R_alpha=None):
+    def local_step_full(self, x, f, R_alpha=None, rot_fp32=False):
         import torch
+        rdt = torch.float32 if rot_fp32 else torch.float64
         self._chk(self._lib.pd_local_step_full(
             self._ctx, _ptr(x, torch.float64, 3 * self.n, "x"),
-            _ptr(R_alpha, torch.float64, 9 * self.n_alpha, "R_alpha"),
-            _ptr(f, torch.float64, 3 * self.n, "f")))
+            _ptr(R_alpha, rdt, 9 * self.n_alpha, "R_alpha"),
+            _ptr(f, torch.float64, 3 * self.n, "f"), 1 if rot_fp32 else 0))
+
+    def set_inertia_target(self, y):
+        import torch
+        self._chk(self._lib.pd_set_inertia_target(
+            self._ctx, None if y is None else _ptr(y, torch.float64, 3 * self.n, "y")))
+
+    def time_step_advance(self, x, x_prev, v, y):
+        import torch
+        self._chk(self._lib.pd_time_step_advance(
+            self._ctx, _ptr(x, torch.float64, 3 * self.n, "x"),
+            _ptr(x_prev, torch.float64, 3 * self.n, "x_prev"),
+            _ptr(v, torch.float64, 3 * self.n, "v"), _ptr(y, torch.float64, 3 * self.n, "y")))
 
     def condense_rhs(self, f, y2):
         import torch
@@ -382,6 +402,22 @@ class PDContext(_Handle):
             _ptr(x2_prev, torch.float64, 3 * self.m, "x2_prev"), float(scale), npx,
             _ptr(prox, torch.int32, npx, "prox"), _ptr(cpen, torch.float64, npx, "c"),
             _ptr(out, torch.float32, 4 * self.m, "out")))
+
+    def warmstart_apply(self, d2, scale, x, x2_prev1=None, x2_prev2=None):
+        import torch
+        self._chk(self._lib.pd_warmstart_apply(
+            self._ctx, _ptr(d2, torch.float32, 3 * self.m, "d2"), float(scale),
+            _ptr(x2_prev1, torch.float64, 3 * self.m, "x2_prev1"),
+            _ptr(x2_prev2, torch.float64, 3 * self.m, "x2_prev2"),
+            _ptr(x, torch.float64, 3 * self.n, "x")))
+
+    def warmstart_target(self, x2, x2_prev1, x2_prev2, scale, out):
+        import torch
+        self._chk(self._lib.pd_warmstart_target(
+            self._ctx, _ptr(x2, torch.float64, 3 * self.m, "x2"),
+            _ptr(x2_prev1, torch.float64, 3 * self.m, "x2_prev1"),
+            _ptr(x2_prev2, torch.float64, 3 * self.m, "x2_prev2"), float(scale),
+            _ptr(out, torch.float32, 3 * self.m, "out")))
 
     def region_add_f32(self, d2, scale, x):
         import torch

@@ -109,6 +109,12 @@ struct pd_ctx {
   double* d_cgs = nullptr;
   // sweeps
   double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
+  double* d_ext = nullptr;     // warm start: predicted region increment in FP64
+  double dt = 0.0;             // backward-Euler time step (0: quasistatic)
+  double mu_p = 0.0, smin = 0.0, smax = 0.0;   // biphasic material (mu_p = 0: corotated)
+  std::vector<double> h_D;     // inertia diagonal M / dt^2 per node (0 on prescribed nodes)
+  double* d_D = nullptr;
+  const double* d_target = nullptr;  // caller's inertial target x_n + dt v_n
   bool have_condense = false;
   double* d_P = nullptr;              // tile parts of a level's (or S's) dense product
   int* d_gflag = nullptr;             // right-hand side supplied to a running factorization
@@ -287,6 +293,18 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
         if (tets[a * T + e] == tets[b * T + e])
           return c->fail(PD_ERR_INVALID, "tet %lld repeats a vertex", (long long)e);
   if (!(M->mu > 0.0) || !std::isfinite(M->mu)) return c->fail(PD_ERR_INVALID, "mu must be positive");
+  if (!(M->dt >= 0.0) || !std::isfinite(M->dt) ||
+      (M->dt > 0.0 && (!(M->density > 0.0) || !std::isfinite(M->density))))
+    return c->fail(PD_ERR_INVALID, "backward Euler needs dt > 0 and density > 0 (dt = 0: quasistatic)");
+  c->dt = M->dt;
+  if (!(M->mu_prime >= 0.0) || !std::isfinite(M->mu_prime) ||
+      (M->mu_prime > 0.0 && !(M->sigma_min >= 0.0 && M->sigma_min <= M->sigma_max &&
+                              std::isfinite(M->sigma_max))))
+    return c->fail(PD_ERR_INVALID,
+                   "biphasic material needs mu_prime >= 0 and 0 <= sigma_min <= sigma_max");
+  c->mu_p = M->mu_prime;
+  c->smin = M->sigma_min;
+  c->smax = M->sigma_max;
 
   // ---- partition (Sec. 4.2): x2 = region & free, x1 = other free nodes
   std::vector<int8_t> cls(n);   // 0 dirichlet, 1 interior (x1), 2 region (x2)
@@ -414,7 +432,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&d_vol, T));
   CK(c->alloc(&d_Ke, 16 * T));
   tet_geometry(d_rest, n, d_tets, T, d_Bm, d_vol, c->st);
-  element_stiffness(d_Bm, d_vol, T, c->mu, d_Ke, c->st);
+  element_stiffness(d_Bm, d_vol, T, c->mu + c->mu_p, d_Ke, c->st);   // mu' joins K (Sec. 5.3)
   CK(c->check("geometry"));
   {
     std::vector<double> vol(T);
@@ -423,6 +441,17 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     for (int64_t e = 0; e < T; ++e)
       if (!(vol[e] > 0.0))
         return c->fail(PD_ERR_INVALID, "tet %lld has non-positive rest volume", (long long)e);
+    if (c->dt > 0.0) {
+      // lumped masses (a quarter of density * Vol_e per node), D = M / dt^2 on
+      // the free nodes (zero on prescribed ones)
+      std::vector<double> mass(n, 0.0);
+      for (int a = 0; a < 4; ++a)
+        for (int64_t e = 0; e < T; ++e) mass[tets[a * T + e]] += 0.25 * M->density * vol[e];
+      c->h_D.assign(n, 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        if (cls[i] != 0) c->h_D[i] = mass[i] / (c->dt * c->dt);
+      CK(c->upload(&c->d_D, c->h_D));
+    }
   }
 
   // ---- assembly plans: every K entry between free nodes, grouped by (row, col)
@@ -572,6 +601,34 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     CK(run_plan(c, pl_S, d_Ke, c->d_S));
     CK(run_plan(c, pl_B, d_Ke, c->d_Bval));
     CK(run_plan(c, pl_Bt, d_Ke, c->d_Btval));
+    if (c->dt > 0.0) {
+      // inertia diagonal into the diagonal blocks of the levels and of S
+      std::vector<int64_t> off_lev, off_S;
+      std::vector<double> val_lev, val_S;
+      for (int64_t u = 0; u < n; ++u) {
+        if (cls[u] == 0) continue;
+        const int lu = lvl[u];
+        const int64_t r = loc[u];
+        if (lu == K) {
+          off_S.push_back(r + r * m);
+          val_S.push_back(c->h_D[u]);
+        } else {
+          off_lev.push_back(c->lev_mat_off[lu] + r + r * c->ldw[lu]);
+          val_lev.push_back(c->h_D[u]);
+        }
+      }
+      int64_t *d_ol = nullptr, *d_os = nullptr;
+      double *d_vl = nullptr, *d_vs = nullptr;
+      CK(c->upload(&d_ol, off_lev));
+      CK(c->upload(&d_vl, val_lev));
+      CK(c->upload(&d_os, off_S));
+      CK(c->upload(&d_vs, val_S));
+      add_at((int64_t)off_lev.size(), d_ol, d_vl, c->d_levmat, c->st);
+      add_at((int64_t)off_S.size(), d_os, d_vs, c->d_S, c->st);
+      CK(c->check("inertia diagonal"));
+      HIPCK(c, hipStreamSynchronize(c->st));
+      for (void* p : {(void*)d_ol, (void*)d_vl, (void*)d_os, (void*)d_vs}) free_now(c, p);
+    }
   }
 
   // ---- A22^(beta): region-local CSR assembled from the E_beta tets only
@@ -821,14 +878,32 @@ pd_status pd_region_gather(pd_ctx* c, const double* x, double* x2) {
   return c->check("pd_region_gather");
 }
 
-pd_status pd_local_step_full(pd_ctx* c, const double* x, double* R_alpha, double* f) {
+pd_status pd_local_step_full(pd_ctx* c, const double* x, void* R_alpha, double* f, int rot_fp32) {
   if (bad_ctx(c) || !x || !f) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
+  if (c->dt > 0.0 && !c->d_target)
+    return c->fail(PD_ERR_STATE, "backward Euler: pd_set_inertia_target before pd_local_step_full");
   PhaseTimer tm(c, PD_PHASE_LOCAL_FULL);
   local_step(c->nalpha, c->d_tets_alpha, c->nalpha, c->d_Bm_alpha, c->d_vol_alpha, c->nalpha, x,
-             c->n, c->mu, c->d_fe, R_alpha, 0, c->st);
+             c->n, c->mu, c->mu_p, c->smin, c->smax, c->d_fe, R_alpha, rot_fp32 ? 1 : 0, c->st);
   node_gather3(c->n, c->d_inc_a_ptr, c->d_inc_a, c->d_fe, c->nalpha, nullptr, f, c->n, 0, c->st);
+  if (c->dt > 0.0) inertia_force(c->n, c->d_D, x, c->d_target, f, c->st);
   return c->check("pd_local_step_full");
+}
+
+pd_status pd_set_inertia_target(pd_ctx* c, const double* y) {
+  if (bad_ctx(c)) return PD_ERR_INVALID;
+  if (!(c->dt > 0.0)) return c->fail(PD_ERR_STATE, "quasistatic context: no inertia target");
+  c->d_target = y;
+  return PD_OK;
+}
+
+pd_status pd_time_step_advance(pd_ctx* c, const double* x, double* x_prev, double* v, double* y) {
+  if (bad_ctx(c) || !x || !x_prev || !v || !y) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  if (!(c->dt > 0.0)) return c->fail(PD_ERR_STATE, "quasistatic context: no time step");
+  time_step_advance(3 * c->n, c->dt, x, x_prev, v, y, c->st);
+  return c->check("pd_time_step_advance");
 }
 
 pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
@@ -858,12 +933,10 @@ pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
   return c->check("pd_condense_rhs");
 }
 
-pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
-  if (bad_ctx(c) || !delta2 || !x) return PD_ERR_INVALID;
-  if (c->broken) return PD_ERR_HIP;
-  if (!c->have_condense) return c->fail(PD_ERR_STATE, "pd_backsub needs a preceding pd_condense_rhs");
+// x1 += v - A11^-1 A12 delta2 level by level (v = A11^-1 f1 from the last
+// condensation, kept per level in d_v), then x2 += delta2.
+static void backsub_levels(pd_ctx* c, const double* delta2, double* x) {
   const int64_t n1 = c->n1, m = c->m;
-  PhaseTimer tm(c, PD_PHASE_BACKSUB);
   if (n1 > 0) {
     // level k: tmp = B_k^T x_{k+1} (x_K = delta2), then xs_k = v_k - Z_k tmp
     for (int k = c->K - 1; k >= 0; --k) {
@@ -881,7 +954,29 @@ pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
     scatter_add_rows3(n1, c->d_lev_nodes, c->d_xs, n1, x, c->n, c->st);
   }
   scatter_add_rows3(m, c->d_region_ids, delta2, m, x, c->n, c->st);
+}
+
+pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
+  if (bad_ctx(c) || !delta2 || !x) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  if (!c->have_condense) return c->fail(PD_ERR_STATE, "pd_backsub needs a preceding pd_condense_rhs");
+  PhaseTimer tm(c, PD_PHASE_BACKSUB);
+  backsub_levels(c, delta2, x);
   return c->check("pd_backsub");
+}
+
+pd_status pd_warmstart_apply(pd_ctx* c, const float* d2, double scale, const double* x2_prev1,
+                             const double* x2_prev2, double* x) {
+  if (bad_ctx(c) || !d2 || !x || !std::isfinite(scale) || (!x2_prev1 != !x2_prev2))
+    return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  if (!c->d_ext) CK(c->alloc(&c->d_ext, 3 * std::max<int64_t>(1, c->m)));
+  scale_f32_to_f64(3 * c->m, d2, scale, x2_prev1, x2_prev2, c->d_ext, c->st);
+  // the elastic response of the interior with f1 = 0: v = 0 on every level
+  zero_f64(3 * c->n1, c->d_v, c->st);
+  backsub_levels(c, c->d_ext, x);
+  c->have_condense = false;           // v no longer holds a condensation
+  return c->check("pd_warmstart_apply");
 }
 
 pd_status pd_detect_spheres(pd_ctx* c, int32_t n_prox, const int32_t* prox, int32_t n_sph,
@@ -981,7 +1076,7 @@ pd_status pd_local_step_region(pd_ctx* c, const double* x2, void* R_beta, double
   }
   PhaseTimer tm(c, PD_PHASE_LOCAL_REGION);
   local_step(c->nbeta, c->d_tets_beta, c->nbeta, c->d_Bm_beta, c->d_vol_beta, c->nbeta, x2, c->m,
-             c->mu, c->d_fe_b, R_beta, rot_fp32 ? 1 : 0, c->st);
+             c->mu, c->mu_p, c->smin, c->smax, c->d_fe_b, R_beta, rot_fp32 ? 1 : 0, c->st);
   node_gather3(c->m, c->d_inc_b_ptr, c->d_inc_b, c->d_fe_b, c->nbeta, nullptr, f_beta, c->m, 0,
                c->st);
   return c->check("pd_local_step_region");
@@ -1347,6 +1442,14 @@ pd_status pd_warmstart_input(pd_ctx* c, const double* x2, const double* x2_prev,
   if (c->broken) return PD_ERR_HIP;
   ws_input((int)c->m, x2, x2_prev, scale, n_prox, prox, cpen, out, c->st);
   return c->check("pd_warmstart_input");
+}
+
+pd_status pd_warmstart_target(pd_ctx* c, const double* x2, const double* x2_prev1,
+                              const double* x2_prev2, float scale, float* out) {
+  if (bad_ctx(c) || !x2 || !x2_prev1 || !x2_prev2 || !out) return PD_ERR_INVALID;
+  if (c->broken) return PD_ERR_HIP;
+  ws_target(3 * c->m, x2, x2_prev1, x2_prev2, scale, out, c->st);
+  return c->check("pd_warmstart_target");
 }
 
 pd_status pd_region_add_f32(pd_ctx* c, const float* d2, double scale, double* x) {

@@ -105,9 +105,11 @@ void element_stiffness(const double* Bm, const double* vol, int64_t T, double mu
                        double* Ke, hipStream_t st);
 void gather_assign(int64_t count, const int64_t* ptr, const int64_t* src, const double* vals,
                    const int64_t* dst_off, double* dst, hipStream_t st);
+// biphasic material when mu_p > 0 (strain limits smin, smax)
 void local_step(int64_t T, const int32_t* tets, int64_t ldt, const double* Bm,
                 const double* vol, int64_t ldb, const double* x, int64_t ldx, double mu,
-                double* fe, void* R, int rot_fp32, hipStream_t st);
+                double mu_p, double smin, double smax, double* fe, void* R, int rot_fp32,
+                hipStream_t st);
 void node_gather3(int64_t count, const int32_t* ptr, const int32_t* ent, const double* fe,
                   int64_t ldfe, const int32_t* node_of_row, double* f, int64_t ldf,
                   int accumulate, hipStream_t st);
@@ -159,6 +161,15 @@ void change_norms(int64_t cnt, const int32_t* ids, const double* x, const double
 void colnorm2_3(int m, const double* a, double* out, hipStream_t st);
 void ws_input(int m, const double* x2, const double* x2p, float scale, int n_prox,
               const int32_t* prox, const double* c, float* out, hipStream_t st);
+void add_at(int64_t count, const int64_t* dst, const double* val, double* base, hipStream_t st);
+void inertia_force(int64_t n, const double* D, const double* x, const double* y, double* f,
+                   hipStream_t st);
+void time_step_advance(int64_t len, double dt, const double* x, double* xp, double* v, double* y,
+                       hipStream_t st);
+void scale_f32_to_f64(int64_t n, const float* d, double scale, const double* a, const double* b,
+                      double* out, hipStream_t st);
+void ws_target(int64_t n, const double* x, const double* xp, const double* xpp, float scale,
+               float* out, hipStream_t st);
 void region_add_f32(int64_t count, const int32_t* ids, const float* d, double scale, double* x,
                     int64_t ldx, hipStream_t st);
 void axpy3_sum(int m, const double* a, const double* b, const double* c, double* out,

@@ -151,8 +151,14 @@ __device__ inline void givens_rows(T B[3][3], T U[3][3], int p, int q) {
   }
 }
 
+// With Q non-null also the strain-limited projection of the biphasic material
+// (Sec. 5.3): F V = U diag(b) with b_1, b_2 >= 0 and b_3 of either sign, so
+// the singular values are |b_i| with left vectors sign(b_i) U e_i, and the
+// closest matrix with singular values in [smin, smax] is
+// Q = U diag(sign(b_i) clamp(|b_i|)) V^T.
 template <typename T>
-__device__ void polar_rotation(const T F[3][3], T R[3][3]) {
+__device__ void polar_rotation(const T F[3][3], T R[3][3], T (*Q)[3] = nullptr, T smin = T(0),
+                               T smax = T(0)) {
   T A[3][3], V[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -205,6 +211,21 @@ __device__ void polar_rotation(const T F[3][3], T R[3][3]) {
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) R[i][j] = U[i][0] * V[j][0] + U[i][1] * V[j][1] + U[i][2] * V[j][2];
+  if (Q) {
+    T d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T b = B[k][k];
+      const T a = fabs(b);
+      const T c = a < smin ? smin : (a > smax ? smax : a);
+      d[k] = b < T(0) ? -c : c;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Q[i][j] = U[i][0] * d[0] * V[j][0] + U[i][1] * d[1] * V[j][1] + U[i][2] * d[2] * V[j][2];
+  }
 }
 
 // Local step and elemental forces for a list of tets:
@@ -212,9 +233,12 @@ __device__ void polar_rotation(const T F[3][3], T R[3][3]) {
 //   f_a = -vol P (D_m^-1)^T e_(a-1) for a = 1..3, f_0 = -(f_1 + f_2 + f_3).
 // tets [4][ldt] index positions in x ([3][ldx]); fe [12][T] (vertex-major);
 // R [9][T] (row-major 3x3 per tet) in FP64 or FP32, or NULL.
+//   biphasic material (mu_p > 0, Sec. 5.3): Q = strain-limited projection of F,
+//   P += 2 mu_p (F - Q).
 __global__ void k_local_step(int64_t T, const int32_t* __restrict__ tets, int64_t ldt,
                              const double* __restrict__ Bm, const double* __restrict__ vol,
                              int64_t ldb, const double* __restrict__ x, int64_t ldx, double mu,
+                             double mu_p, double smin, double smax,
                              double* __restrict__ fe, void* Rout, int rot_fp32) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= T) return;
@@ -237,26 +261,39 @@ __global__ void k_local_step(int64_t T, const int32_t* __restrict__ tets, int64_
     for (int j = 0; j < 3; ++j)
       F[i][j] = (X[1][i] - X[0][i]) * Dinv[0][j] + (X[2][i] - X[0][i]) * Dinv[1][j] +
                 (X[3][i] - X[0][i]) * Dinv[2][j];
-  double R[3][3];
+  double R[3][3], Q[3][3];
+  const bool biphasic = mu_p > 0.0;
   if (rot_fp32) {
-    float Ff[3][3], Rf[3][3];
+    float Ff[3][3], Rf[3][3], Qf[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Ff[i][j] = (float)F[i][j];
-    polar_rotation<float>(Ff, Rf);
+    polar_rotation<float>(Ff, Rf, biphasic ? Qf : nullptr, (float)smin, (float)smax);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) R[i][j] = (double)Rf[i][j];
+      for (int j = 0; j < 3; ++j) {
+        R[i][j] = (double)Rf[i][j];
+        Q[i][j] = biphasic ? (double)Qf[i][j] : F[i][j];
+      }
   } else {
-    polar_rotation<double>(F, R);
+    polar_rotation<double>(F, R, biphasic ? Q : nullptr, smin, smax);
+    if (!biphasic) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Q[i][j] = F[i][j];
+    }
   }
   const double s = -2.0 * mu * vol[e];
+  const double rp = biphasic ? mu_p / mu : 0.0;
   double f[4][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const double p0 = F[i][0] - R[i][0], p1 = F[i][1] - R[i][1], p2 = F[i][2] - R[i][2];
+    const double p0 = (F[i][0] - R[i][0]) + rp * (F[i][0] - Q[i][0]);
+    const double p1 = (F[i][1] - R[i][1]) + rp * (F[i][1] - Q[i][1]);
+    const double p2 = (F[i][2] - R[i][2]) + rp * (F[i][2] - Q[i][2]);
 #pragma unroll
     for (int a = 1; a < 4; ++a)
       f[a][i] = s * (p0 * Dinv[a - 1][0] + p1 * Dinv[a - 1][1] + p2 * Dinv[a - 1][2]);
@@ -280,11 +317,11 @@ __global__ void k_local_step(int64_t T, const int32_t* __restrict__ tets, int64_
 }
 
 void local_step(int64_t T, const int32_t* tets, int64_t ldt, const double* Bm, const double* vol,
-                int64_t ldb, const double* x, int64_t ldx, double mu, double* fe, void* R,
-                int rot_fp32, hipStream_t st) {
+                int64_t ldb, const double* x, int64_t ldx, double mu, double mu_p, double smin,
+                double smax, double* fe, void* R, int rot_fp32, hipStream_t st) {
   if (T > 0)
-    k_local_step<<<grid1(T, 128), 128, 0, st>>>(T, tets, ldt, Bm, vol, ldb, x, ldx, mu, fe, R,
-                                                rot_fp32);
+    k_local_step<<<grid1(T, 128), 128, 0, st>>>(T, tets, ldt, Bm, vol, ldb, x, ldx, mu, mu_p,
+                                                smin, smax, fe, R, rot_fp32);
 }
 
 // f[i][node_of_row[r]] (+)= sum over incidences e in [ptr[r], ptr[r+1]) of
@@ -796,6 +833,79 @@ __global__ void k_region_add_f32(int64_t count, const int32_t* __restrict__ ids,
 void region_add_f32(int64_t count, const int32_t* ids, const float* d, double scale, double* x,
                     int64_t ldx, hipStream_t st) {
   if (count > 0) k_region_add_f32<<<grid1(count), 256, 0, st>>>(count, ids, d, scale, x, ldx);
+}
+
+// base[dst[i]] += val[i] (distinct destinations).
+__global__ void k_add_at(int64_t count, const int64_t* __restrict__ dst,
+                         const double* __restrict__ val, double* __restrict__ base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) base[dst[i]] += val[i];
+}
+
+void add_at(int64_t count, const int64_t* dst, const double* val, double* base, hipStream_t st) {
+  if (count > 0) k_add_at<<<grid1(count), 256, 0, st>>>(count, dst, val, base);
+}
+
+// Backward-Euler inertia force: f[:, i] -= D_i (x[:, i] - y[:, i]).
+__global__ void k_inertia_force(int64_t n, const double* __restrict__ D,
+                                const double* __restrict__ x, const double* __restrict__ y,
+                                double* __restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double d = D[i];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) f[v * n + i] -= d * (x[v * n + i] - y[v * n + i]);
+}
+
+void inertia_force(int64_t n, const double* D, const double* x, const double* y, double* f,
+                   hipStream_t st) {
+  if (n > 0) k_inertia_force<<<grid1(n), 256, 0, st>>>(n, D, x, y, f);
+}
+
+// End of a backward-Euler step: v = (x - xp) / dt, xp = x, y = x + dt v.
+__global__ void k_time_step_advance(int64_t len, double dt, const double* __restrict__ x,
+                                    double* __restrict__ xp, double* __restrict__ v,
+                                    double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  const double xi = x[i];
+  const double vi = (xi - xp[i]) / dt;
+  v[i] = vi;
+  xp[i] = xi;
+  y[i] = xi + dt * vi;
+}
+
+void time_step_advance(int64_t len, double dt, const double* x, double* xp, double* v, double* y,
+                       hipStream_t st) {
+  if (len > 0) k_time_step_advance<<<grid1(len), 256, 0, st>>>(len, dt, x, xp, v, y);
+}
+
+// out = scale * d (+ a - b when a and b are given)
+__global__ void k_scale_f32_to_f64(int64_t n, const float* __restrict__ d, double scale,
+                                   const double* __restrict__ a, const double* __restrict__ b,
+                                   double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = scale * (double)d[i];
+  if (a) v += a[i] - b[i];
+  out[i] = v;
+}
+
+void scale_f32_to_f64(int64_t n, const float* d, double scale, const double* a, const double* b,
+                      double* out, hipStream_t st) {
+  if (n > 0) k_scale_f32_to_f64<<<grid1(n), 256, 0, st>>>(n, d, scale, a, b, out);
+}
+
+// out = scale * ((x - xp) - (xp - xpp)), float32
+__global__ void k_ws_target(int64_t n, const double* __restrict__ x, const double* __restrict__ xp,
+                            const double* __restrict__ xpp, float scale, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)(((x[i] - xp[i]) - (xp[i] - xpp[i])) * scale);
+}
+
+void ws_target(int64_t n, const double* x, const double* xp, const double* xpp, float scale,
+               float* out, hipStream_t st) {
+  if (n > 0) k_ws_target<<<grid1(n), 256, 0, st>>>(n, x, xp, xpp, scale, out);
 }
 
 __global__ void k_axpy3_sum(int64_t len, const double* __restrict__ a, const double* b,

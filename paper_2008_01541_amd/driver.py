@@ -14,10 +14,12 @@ class Alg1Runner:
     """Buffers and call sequence for outer/inner iterations with sphere
     obstacles and conforming proxies."""
 
-    def __init__(self, rest, tets, region, dirichlet, mu, proxies_global, k_pen, device="cuda"):
+    def __init__(self, rest, tets, region, dirichlet, mu, proxies_global, k_pen, device="cuda",
+                 density=0.0, dt=0.0, mu_prime=0.0, sigma_min=0.0, sigma_max=0.0):
         import torch
         self.torch = torch
-        self.ctx = PDContext(rest, tets, region, dirichlet, mu)
+        self.ctx = PDContext(rest, tets, region, dirichlet, mu, density=density, dt=dt,
+                             mu_prime=mu_prime, sigma_min=sigma_min, sigma_max=sigma_max)
         c = self.ctx
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
@@ -42,6 +44,13 @@ class Alg1Runner:
         self.spheres = None
         self.pairs = None
         self.mode = "nodes"
+        self.dt = float(dt)
+        if self.dt > 0.0:
+            # backward Euler: inertial target y = x_n + dt v_n (from rest at rest)
+            self.y = self.x.clone()
+            self.x_prev = self.x.clone()
+            self.v = torch.zeros_like(self.x)
+            c.set_inertia_target(self.y)
 
     def set_spheres(self, centers, radii):
         sph = np.vstack([np.asarray(centers, dtype=np.float64),
@@ -153,7 +162,7 @@ class Alg1Runner:
 
     def outer_iteration(self, n_inner=1, prec=PD_FP64, rot_fp32=False, want_info=False):
         c = self.ctx
-        c.local_step_full(self.x, self.f)
+        c.local_step_full(self.x, self.f, rot_fp32=rot_fp32)
         c.condense_rhs(self.f, self.ft)
         c.region_gather(self.x, self.x2)
         self.delta2.zero_()
@@ -231,6 +240,22 @@ class Alg1Runner:
             ev_upd = torch.cuda.Event()
             ev_upd.record(s_main)
         c.backsub(self.delta2, self.x)
+
+    def set_state(self, x, v):
+        """Backward Euler: positions x_n and velocities v_n at the start of a
+        step (host (3, n) arrays); sets x, x_prev = x_n and y = x_n + dt v_n
+        through pd_time_step_advance from x_n - dt v_n."""
+        torch = self.torch
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        self.set_positions(x)
+        self.x_prev.copy_(torch.as_tensor(x - self.dt * v).reshape(-1))
+        self.ctx.time_step_advance(self.x, self.x_prev, self.v, self.y)
+
+    def advance_time_step(self):
+        """Backward Euler, after the step's iterations: v = (x - x_prev) / dt,
+        x_prev = x, y = x + dt v for the next step."""
+        self.ctx.time_step_advance(self.x, self.x_prev, self.v, self.y)
 
     def positions(self):
         return self.x.reshape(3, -1).cpu().numpy()

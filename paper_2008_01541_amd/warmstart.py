@@ -30,16 +30,20 @@ def converge(run, tol=1e-6, max_outer=200, n_inner=1):
 
 
 def detect_at_start(run):
-    """Penalty set of the frame detected at the current positions (fills run.c)."""
+    """Penalty set of the frame detected at the current positions (fills run.c).
+    The network's mask input assumes the runner's node proxies (run.prox)."""
+    if run.mode != "nodes":
+        raise ValueError("the learned warm start takes node proxies (one mask entry per proxy node)")
     c = run.ctx
     c.region_gather(run.x, run.x2)
-    c.detect_spheres(run.prox, run.spheres, run.k_pen, run.x2, run.idx, run.w, run.c, run.t)
+    run.detect()
 
 
-def generate_trajectory(run, centers_fn, radii, n_frames, tol=1e-6, max_outer=200):
+def generate_trajectory(run, centers_fn, radii, n_frames, tol=1e-6, max_outer=200, residual=True):
     """Solve n_frames frames from rest (cold start from the previous frame).
-    Returns the network samples (inputs [du_{t-1}, mask_t], targets du_t,
-    unscaled) and the iteration counts."""
+    Returns the network samples (inputs [du_{t-1}, mask_t]; targets du_t, or
+    with residual the change du_t - du_{t-1}; unscaled) and the iteration
+    counts."""
     import torch
     c = run.ctx
     run.set_positions(run.rest_np)
@@ -57,8 +61,12 @@ def generate_trajectory(run, centers_fn, radii, n_frames, tol=1e-6, max_outer=20
         c.region_gather(run.x, run.x2)
         cur = run.x2.clone()
         if inp is not None:
-            tgt = torch.empty(4 * m, dtype=torch.float32, device=run.x.device)
-            c.warmstart_input(cur, prev1, 1.0, run.prox, run.c, tgt)   # first 3m = du_t
+            if residual:
+                tgt = torch.empty(3 * m, dtype=torch.float32, device=run.x.device)
+                c.warmstart_target(cur, prev1, prev2, 1.0, tgt)
+            else:
+                tgt = torch.empty(4 * m, dtype=torch.float32, device=run.x.device)
+                c.warmstart_input(cur, prev1, 1.0, run.prox, run.c, tgt)   # first 3m = du_t
             xs.append(inp)
             ys.append(tgt[:3 * m].clone())
         prev2, prev1 = prev1, cur
@@ -68,12 +76,18 @@ def generate_trajectory(run, centers_fn, radii, n_frames, tol=1e-6, max_outer=20
 
 
 class WarmStart:
-    def __init__(self, m, hidden=512, seed=4, max_batch=64):
+    """The network 4m -> hidden -> hidden -> 3m.  With residual (default) it
+    predicts the change of the region increment from the previous frame's
+    (the prediction is du_{t-1} + output), and its output layer starts at zero,
+    so before training it is the extrapolation du_t = du_{t-1}."""
+
+    def __init__(self, m, hidden=512, seed=4, max_batch=64, residual=True):
         from pd_inputs.mlp_init import mlp_init_params, pack
         from ._lib import MLP
         self.m = m
+        self.residual = residual
         n_in, n_out = 4 * m, 3 * m
-        p = mlp_init_params(n_in, hidden, hidden, n_out, seed)
+        p = mlp_init_params(n_in, hidden, hidden, n_out, seed, out_scale=0.0 if residual else 0.1)
         self.net = MLP(n_in, hidden, hidden, n_out, max_batch, pack(p))
         self.scale = 1.0
         self.max_batch = max_batch
@@ -108,8 +122,10 @@ class WarmStart:
             hist.append(tot / n)
         return hist
 
-    def predict_into(self, run, x2_prev1, x2_prev2):
-        """Predict du for the next frame and add it to the region nodes of run.x."""
+    def predict_into(self, run, x2_prev1, x2_prev2, extend=True):
+        """Predict du for the next frame and apply it to run.x: with extend
+        (default) to the region nodes together with the interior's static
+        response to it (pd_warmstart_apply), else to the region nodes alone."""
         import torch
         c = run.ctx
         m = self.m
@@ -117,18 +133,36 @@ class WarmStart:
         c.warmstart_input(x2_prev1, x2_prev2, self.scale, run.prox, run.c, inp)
         y = torch.empty((1, 3 * m), dtype=torch.float32, device=run.x.device)
         self.net.forward(inp, y)
-        c.region_add_f32(y, 1.0 / self.scale, run.x)
+        if self.residual:
+            c.warmstart_apply(y, 1.0 / self.scale, run.x, x2_prev1, x2_prev2)
+        elif extend:
+            c.warmstart_apply(y, 1.0 / self.scale, run.x)
+        else:
+            c.region_add_f32(y, 1.0 / self.scale, run.x)
+
+
+def extrapolate_into(run, x2_prev1, x2_prev2):
+    """The non-learned predictor for comparison: the previous frame's region
+    increment repeated (applied with the interior's static response)."""
+    import torch
+    c = run.ctx
+    zero = torch.zeros(3 * c.m, dtype=torch.float32, device=run.x.device)
+    c.warmstart_apply(zero, 1.0, run.x, x2_prev1, x2_prev2)
 
 
 def evaluate(run, ws, centers_fn, radii, n_frames, tol=1e-8, judge_tol=1e-9, accept=1e-6,
-             max_outer=2000):
+             max_outer=2000, extend=True, predictor="mlp"):
     """Per frame, from the previous frame's judged state: the judge (the plain
     iteration, no prediction, to ||x_k - x_{k-1}|| <= judge_tol ||x_k - X||),
     the cold start (the same iteration to tol) and the learned warm start
-    (prediction, then the same iteration to tol).  A warm result is accepted
+    (prediction, applied with the interior's static response when extend,
+    then the same iteration to tol).  A warm result is accepted
     when ||x_warm - x_judge|| <= accept ||x_judge - X||; otherwise the frame
     falls back to the cold solve and is charged both runs (iterations and
     wall time).  The judge's run is a measuring device and is not charged.
+    predictor="extrapolate" replaces the network by extrapolate_into.  Each
+    record also holds the distance of the cold and warm starting points from
+    the judged result (relative to its displacement from rest).
     Returns one record per frame."""
     import torch
     run.set_positions(run.rest_np)
@@ -148,14 +182,19 @@ def evaluate(run, ws, centers_fn, radii, n_frames, tol=1e-8, judge_tol=1e-9, acc
         torch.cuda.synchronize()
         t_cold = time.perf_counter() - t0
         d, s = c.displacement_change(run.x, x_judge)
+        d0, _ = c.displacement_change(start, x_judge)
         rec = {"frame": fr, "judge_iters": judge_it, "cold_iters": it_cold, "cold_s": t_cold,
-               "cold_rel_diff": d / max(s, 1e-300)}
+               "cold_rel_diff": d / max(s, 1e-300), "cold_start_err": d0 / max(s, 1e-300)}
         if prev2 is not None:
             run.x.copy_(start)
             detect_at_start(run)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ws.predict_into(run, prev1, prev2)
+            if predictor == "extrapolate":
+                extrapolate_into(run, prev1, prev2)
+            else:
+                ws.predict_into(run, prev1, prev2, extend=extend)
+            d0, _ = c.displacement_change(run.x, x_judge)
             it_warm = converge(run, tol, max_outer)
             torch.cuda.synchronize()
             t_warm = time.perf_counter() - t0
@@ -163,6 +202,7 @@ def evaluate(run, ws, centers_fn, radii, n_frames, tol=1e-8, judge_tol=1e-9, acc
             rel = d / max(s, 1e-300)
             ok = rel <= accept
             rec.update({"warm_iters": it_warm, "warm_s": t_warm, "rel_diff": rel,
+                        "warm_start_err": d0 / max(s, 1e-300),
                         "fell_back": not ok,
                         "charged_iters": it_warm if ok else it_warm + it_cold,
                         "charged_s": t_warm if ok else t_warm + t_cold})
@@ -191,5 +231,7 @@ def summarize(rows):
             "charged_s_per_frame": chg_s / len(warm),
             "wall_saved_frac": 1.0 - chg_s / cold_s if cold_s else None,
             "fell_back": sum(1 for r in warm if r["fell_back"]),
+            "cold_start_err_mean": float(np.mean([r["cold_start_err"] for r in warm])),
+            "warm_start_err_mean": float(np.mean([r["warm_start_err"] for r in warm])),
             "rel_diff_max": max(r["rel_diff"] for r in warm),
             "cold_rel_diff_max": max(r["cold_rel_diff"] for r in warm)}

@@ -50,6 +50,11 @@ def test_local_steps_match_oracle(torch_cuda, name):
     assert rel(host(f, (3, -1)), f_or) <= TOL
     Rg = host(Ra, (9, -1)).T.reshape(-1, 3, 3)
     assert np.abs(Rg - R_or).max() <= 1e-12
+    # FP32 rotations on E_alpha: rotations within 1e-6, forces from them
+    Ra32 = torch_cuda.empty(9 * ctx.n_alpha, dtype=torch_cuda.float32, device="cuda")
+    ctx.local_step_full(xd, f, Ra32, rot_fp32=True)
+    assert np.abs(host(Ra32, (9, -1)).T.reshape(-1, 3, 3) - R_or).max() <= 1e-6
+    assert rel(host(f, (3, -1)), f_or) <= 1e-5
     if ctx.n_beta:
         x2 = dev(x[:, om.i2])
         fb = torch_cuda.empty(3 * ctx.m, dtype=torch_cuda.float64, device="cuda")
@@ -477,3 +482,45 @@ def test_factor_modes(torch_cuda):
     ctx.global_solve(g, u_ovl)
     torch_cuda.cuda.synchronize()
     assert torch_cuda.equal(u_ref, u_ovl)
+
+
+@pytest.mark.parametrize("name", ["g9x7x6", "g16x15x8"])
+def test_warmstart_apply_matches_oracle(torch_cuda, name):
+    """pd_warmstart_apply: a float32 region increment d (times scale) moves the
+    region by d and the interior by its static response -A11^-1 A12 d; a
+    pd_backsub after it needs a new condensation."""
+    from oracle import schur as osch
+    from paper_2008_01541_amd import PDError
+    sc = SMALL_SCENES[name]()
+    om = oracle_model(sc, build_schur=False)
+    ctx = gpu_context(sc)
+    rng = np.random.default_rng(8)
+    d32 = rng.normal(size=(3, ctx.m)).astype(np.float32)
+    scale = 0.37
+    x0 = sc.rest + 0.01 * rng.normal(size=sc.rest.shape)
+    xd = dev(x0)
+    ctx.warmstart_apply(dev(d32), scale, xd)
+    d = scale * d32.astype(np.float64)
+    x1 = osch.back_sub(om.lu11, om.A12, np.zeros((om.i1.size, 3)), d.T).T
+    got = host(xd, (3, -1))
+    assert np.abs(got[:, om.i2] - (x0[:, om.i2] + d)).max() <= 1e-14
+    assert np.abs(got[:, om.i1] - (x0[:, om.i1] + x1)).max() <= 1e-10 * np.abs(x1).max()
+    assert np.array_equal(got[:, sc.dirichlet], x0[:, sc.dirichlet])
+    with pytest.raises(PDError):
+        ctx.backsub(dev(d), xd)
+    # residual form: d = scale * d2 + (x2_prev1 - x2_prev2)
+    p1 = rng.normal(size=(3, ctx.m))
+    p2 = rng.normal(size=(3, ctx.m))
+    xd = dev(x0)
+    ctx.warmstart_apply(dev(d32), scale, xd, dev(p1), dev(p2))
+    d = scale * d32.astype(np.float64) + (p1 - p2)
+    x1 = osch.back_sub(om.lu11, om.A12, np.zeros((om.i1.size, 3)), d.T).T
+    got = host(xd, (3, -1))
+    assert np.abs(got[:, om.i2] - (x0[:, om.i2] + d)).max() <= 1e-14 * max(1.0, np.abs(d).max())
+    assert np.abs(got[:, om.i1] - (x0[:, om.i1] + x1)).max() <= 1e-10 * np.abs(x1).max()
+    # and its training target, in float32
+    t32 = torch_cuda.empty(3 * ctx.m, dtype=torch_cuda.float32, device="cuda")
+    x2 = rng.normal(size=(3, ctx.m))
+    ctx.warmstart_target(dev(x2), dev(p1), dev(p2), 2.5, t32)
+    ref = ((x2 - p1) - (p1 - p2)) * 2.5
+    assert np.abs(host(t32, (3, -1)) - ref).max() <= 1e-6 * np.abs(ref).max()

@@ -37,9 +37,12 @@ def test_warm_start_gains_iterations():
     hist = ws.train(X, Y, epochs=60, lr=1e-3)
     assert hist[-1] < 0.5 * hist[0]
     fn, rad = traj(999)
+    sm_ex = summarize(evaluate(run, ws, fn, rad, n_frames=16, tol=1e-8, judge_tol=1e-9,
+                               accept=1e-6, predictor="extrapolate"))
+    print("extrapolation:", sm_ex)
     rows = evaluate(run, ws, fn, rad, n_frames=16, tol=1e-8, judge_tol=1e-9, accept=1e-6)
     sm = summarize(rows)
-    print(sm)
+    print("learned:", sm)
     warm = [r for r in rows if "warm_iters" in r]
     assert len(warm) == 14                     # frames 3..16 have two previous frames
     for r in rows:
@@ -50,5 +53,6 @@ def test_warm_start_gains_iterations():
     assert sm["fell_back"] <= 2
     # what the trained network gains over the method without it
     assert sm["charged_outer_iters_per_frame"] < sm["cold_outer_iters_per_frame"]
+    assert sm["warm_start_err_mean"] < sm["cold_start_err_mean"]
     run.close()
     ws.close()
