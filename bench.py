@@ -141,6 +141,38 @@ def precision_modes(run, spheres, inner, iters=6):
     return res
 
 
+def mlp_timing(net, X, Y, reps=20):
+    """Roofline figures of the network's kernels at the bench size: inference
+    at batch 1 (bound by reading the BF16 weights once, 2 B per parameter) and
+    a training step at batch 32 (forward, backward and Adam: 6 flop per
+    parameter and sample in the products), HIP events on the stream."""
+    import torch
+    n_in, h1, h2, n_out = net.shape
+    n_w = h1 * n_in + h2 * h1 + n_out * h2
+    st = torch.cuda.current_stream()
+    x1 = X[:1].contiguous()
+    y1 = torch.empty((1, n_out), dtype=torch.float32, device=X.device)
+    B = min(32, net.max_batch, X.shape[0])
+    xb, yb = X[:B].contiguous(), Y[:B].contiguous()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_fwd = timed(lambda: net.forward(x1, y1))
+    t_trn = timed(lambda: net.train_step(xb, yb, 0.0, want_loss=False))
+    return {"params": int(n_w + h1 + h2 + n_out), "forward_b1_ms": t_fwd,
+            "forward_b1_weight_gbps": 2.0 * n_w / (t_fwd * 1e-3) / 1e9,
+            "train_batch": int(B), "train_step_ms": t_trn,
+            "train_tflops": 6.0 * n_w * B / (t_trn * 1e-3) / 1e12}
+
+
 def warmstart_leg(run, args):
     """Learned warm start on the slab: the network (4m -> 512 -> 512 -> 3m) is
     trained on frames the plain FP64 solver generates along seeded sphere
@@ -178,6 +210,7 @@ def warmstart_leg(run, args):
         rows = evaluate(run, ws, tr.centers, tr.radii, n_frames=args.ws_eval + 2, tol=1e-8,
                         judge_tol=1e-9, accept=1e-6)
         print(f"warm start: evaluated {args.ws_eval} frames", file=sys.stderr, flush=True)
+        net_timing = mlp_timing(ws.net, X, Y)
         # the non-learned predictor on the same frames (previous increment repeated)
         ex = summarize(evaluate(run, ws, tr.centers, tr.radii, n_frames=args.ws_eval + 2,
                                 tol=1e-8, judge_tol=1e-9, accept=1e-6, predictor="extrapolate"))
@@ -186,6 +219,7 @@ def warmstart_leg(run, args):
                 "generate_s": round(gen_s, 2), "train_s": round(train_s, 2),
                 "run_tol": 1e-8, "judge_tol": 1e-9, "accept": 1e-6,
                 **summarize(rows),
+                "network_kernels": net_timing,
                 "extrapolation": {k: ex[k] for k in ["charged_outer_iters_per_frame",
                                                      "iters_saved_frac", "wall_saved_frac",
                                                      "warm_start_err_mean", "fell_back"]},
@@ -241,6 +275,59 @@ def bench_dense_chol(args):
         "config": {"workload": "dense_spd", "n": n, "lda": lda},
         "ms_mean": mean, "ms_best": best, "tflops_best": n ** 3 / 3.0 / (best * 1e-3) / 1e12,
         "frac_of_fp64_peak": tf / 78.6, "info": info, "rel_residual": float(res)}))
+
+
+def bench_local_step_column(args):
+    """E_alpha local step and force assembly (pd_local_step_full) on a mesh
+    whose per-launch working set exceeds the 256 MB Infinity Cache: a 28 x 28
+    x 768 Kuhn column (3,612,672 tets, 646,729 nodes), bottom pinned, region =
+    top two layers (its interior levels are 841 nodes wide, so the build
+    stays small).  HIP events around each call on the context stream; the
+    algorithmic bytes are those of the two kernels it launches: per tet 16 B
+    of vertex ids, 72 B of D_m^-1, 8 B of volume, 3 x 4 x 8 B of node
+    positions read once per node (counted per node), 96 B of element forces
+    written and read back once by the per-node gather with its 16 B of
+    incidence entries, and per node 24 B of positions, 24 B of forces
+    written and a 4 B list offset."""
+    import torch
+    import pd_inputs as P
+    from paper_2008_01541_amd import PDContext
+    nx = ny = 28
+    nz = 768
+    sc = P.scene_small(nx, ny, nz, h=1.0, region_top_layers=2, seed=7)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = PDContext(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, stream=stream)
+    rng = np.random.default_rng(5)
+    x = sc.rest + 0.05 * rng.normal(size=sc.rest.shape)
+    x[:, sc.dirichlet] = sc.rest[:, sc.dirichlet]
+    xd = torch.tensor(x.reshape(-1), device="cuda")
+    f = torch.empty_like(xd)
+    for _ in range(args.warmup):
+        ctx.local_step_full(xd, f)
+    ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.local_step_full(xd, f)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    T, n = ctx.n_alpha, ctx.n
+    per_tet = 16 + 72 + 8 + 96 + 96 + 16
+    per_node = 24 + 24 + 4
+    nbytes = T * per_tet + n * per_node
+    best, med = min(ms), float(np.median(ms))
+    print(json.dumps({
+        "metric": "E_alpha local step + force assembly GB/s (working set above the 256 MB cache)",
+        "value": nbytes / (med * 1e-3) / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"column{nx}x{ny}x{nz}_kuhn", "tets_alpha": int(T), "nodes": int(n),
+                   "algorithmic_bytes_per_call": int(nbytes), "bytes_per_tet": per_tet,
+                   "bytes_per_node": per_node},
+        "ms_median": med, "ms_best": best, "gbps_best": nbytes / (best * 1e-3) / 1e9,
+        "frac_of_hbm_peak": nbytes / (med * 1e-3) / 8e12}))
+    ctx.close()
 
 
 def bench_slit(args):
@@ -383,6 +470,9 @@ def main():
     ap.add_argument("--dense-chol", type=int, default=0,
                     help="time only the standalone dense FP64 Cholesky at this order "
                          "(e.g. 19494 = 3 x 6,498, the coupled form's size)")
+    ap.add_argument("--local-step-column", action="store_true",
+                    help="time only the E_alpha local step on a 28 x 28 x 768 column "
+                         "(3.6M tets, working set above the 256 MB Infinity Cache)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip timing replays of a HIP graph of one outer iteration")
     args = ap.parse_args()
@@ -405,6 +495,8 @@ def main():
         args.factor_wg = 448 if args.workload == "slit64" else 384
     if args.dense_chol > 0:
         return bench_dense_chol(args)
+    if args.local_step_column:
+        return bench_local_step_column(args)
     if args.workload == "slit64":
         return bench_slit(args)
     sc = P.scene_slab56()

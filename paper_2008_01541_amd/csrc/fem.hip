@@ -9,6 +9,18 @@ namespace pdk {
 
 static inline unsigned grid1(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+// Workgroup b of a launch is dispatched to XCD b % 8 (round robin over the
+// eight accelerator dies, each with its own L2).  For kernels whose
+// neighbouring blocks share data (node positions of adjacent tets, element
+// forces of adjacent nodes), map the dispatch index to a logical block so
+// that each XCD works through one contiguous eighth of the blocks and the
+// shared lines are fetched into one L2 instead of several.  A bijection on
+// [0, nb).
+__device__ inline int64_t xcd_contiguous_block(int64_t b, int64_t nb) {
+  const int64_t x = b & 7, q = b >> 3, base = nb >> 3, rem = nb & 7;
+  return x * base + (x < rem ? x : rem) + q;
+}
+
 // ---------------------------------------------------------------------------
 // Geometry: D_m = [X1-X0, X2-X0, X3-X0], Bm = D_m^-1 (row-major, SoA [9][T]),
 // vol = det(D_m) / 6.
@@ -240,7 +252,7 @@ __global__ void k_local_step(int64_t T, const int32_t* __restrict__ tets, int64_
                              int64_t ldb, const double* __restrict__ x, int64_t ldx, double mu,
                              double mu_p, double smin, double smax,
                              double* __restrict__ fe, void* Rout, int rot_fp32) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = xcd_contiguous_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (e >= T) return;
   double X[4][3];
 #pragma unroll
@@ -330,7 +342,7 @@ __global__ void k_node_gather3(int64_t count, const int32_t* __restrict__ ptr,
                                const int32_t* __restrict__ ent, const double* __restrict__ fe,
                                int64_t ldfe, const int32_t* __restrict__ node_of_row,
                                double* __restrict__ f, int64_t ldf, int accumulate) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = xcd_contiguous_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (r >= count) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int32_t e = ptr[r]; e < ptr[r + 1]; ++e) {
