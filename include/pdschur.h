@@ -328,8 +328,9 @@ pd_status pd_chol_create(int64_t n_max, void *hip_stream, pd_chol **out);
  * strictly upper triangle holds L^T.  n_workgroups > 0 caps the persistent
  * workgroups (default two per compute unit).  info_host == NULL: enqueue only.
  * Otherwise the call synchronizes and *info_host receives 0, or the 1-based
- * index of the first non-positive pivot (PD_ERR_NOT_SPD; that pivot is
- * replaced by 1 and the factorization runs to the end).  Calls on one handle
+ * index of the first non-positive pivot (PD_ERR_NOT_SPD; the reciprocal
+ * square root of that pivot is taken as 1 and the factorization runs to the
+ * end).  Calls on one handle
  * must not overlap.  Invalid arguments -> PD_ERR_INVALID, nothing enqueued. */
 pd_status pd_chol_factor(pd_chol *h, double *A, int64_t lda, int64_t n, int32_t n_workgroups,
                          int32_t *info_host);

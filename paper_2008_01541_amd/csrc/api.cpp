@@ -76,14 +76,14 @@ struct pd_ctx {
   double* d_H = nullptr;
   double* d_linv = nullptr;
   double* d_sbuf = nullptr;           // partial sums of the first sub-diagonal tiles (factor)
-  double* d_y = nullptr;
+  double* d_y = nullptr;               // scratch of the residual products
+  double* d_ys = nullptr;              // forward-solve result (holds the sentinel between solves)
   double* d_Yt = nullptr;             // 64 x m right-hand-side tile row of the fused solve
   double* d_res = nullptr;
   double* d_norms = nullptr;
   int* d_info = nullptr;
   int* d_err = nullptr;
   unsigned long long* d_ticket = nullptr;
-  int* d_flags = nullptr;
   int* d_tflags = nullptr;            // tile-ready flags of the dataflow Cholesky
   int* d_cumarks = nullptr;           // per-compute-unit marks of the dataflow Cholesky
   unsigned* d_tticket = nullptr;
@@ -96,7 +96,6 @@ struct pd_ctx {
   double* d_lpy = nullptr;
   double* d_dvec = nullptr;
   unsigned long long* d_lp_ticket = nullptr;
-  int* d_lp_flags = nullptr;
   int lp_prec = -1;                   // precision of the current low-precision factor
   bool lp_stale = true;
   int lp_info = -1;                   // its first non-positive pivot (0: none; -1: not read yet)
@@ -668,11 +667,9 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&c->d_info, 1));
   CK(c->alloc(&c->d_err, 1));
   CK(c->alloc(&c->d_ticket, 4));
-  CK(c->alloc(&c->d_flags, 4 * (int64_t)c->ntm));
   HIPCK(c, hipMemsetAsync(c->d_info, 0, sizeof(int), c->st));
   HIPCK(c, hipMemsetAsync(c->d_err, 0, sizeof(int), c->st));
   HIPCK(c, hipMemsetAsync(c->d_ticket, 0, 4 * sizeof(unsigned long long), c->st));
-  HIPCK(c, hipMemsetAsync(c->d_flags, 0, 4 * (int64_t)c->ntm * sizeof(int), c->st));
   {
     const int64_t nt2 = ntmax * (ntmax + 2);
     CK(c->alloc(&c->d_tflags, nt2));
@@ -780,6 +777,8 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   free_now(c, d_tets);
   CK(c->alloc(&c->d_H, (int64_t)c->ldH * m));
   CK(c->alloc(&c->d_y, 3 * m));
+  CK(c->alloc(&c->d_ys, 3 * m));
+  sentinel_fill(3 * m, c->d_ys, c->st);
   CK(c->alloc(&c->d_Yt, (int64_t)NB * m));
   CK(c->alloc(&c->d_res, 3 * m));
   CK(c->alloc(&c->d_norms, 8));
@@ -1139,7 +1138,7 @@ void neg_apply_H(pd_ctx* c, const double* p, double* nq) {
 // z = M^-1 r with M = D^-1 L L^T D^-1 from the low-precision factor.
 void lp_precondition(pd_ctx* c, const double* r, double* z) {
   trsv3_lp_solve(c->d_H32, c->ldH32, (int)c->m, c->d_linv32, c->d_dvec, r, c->d_lpb, c->d_lpy, z,
-                 0, c->d_lp_ticket, c->d_lp_flags, c->d_err, c->st);
+                 0, c->d_lp_ticket, c->d_err, c->st);
 }
 
 // max over columns of ||r_v|| / ||g_v|| from squared norms computed on the
@@ -1216,9 +1215,8 @@ pd_status ensure_lp_buffers(pd_ctx* c) {
   CK(c->alloc(&c->d_cgz, 3 * m));
   CK(c->alloc(&c->d_cgs, 16));
   CK(c->alloc(&c->d_lp_ticket, 2));
-  CK(c->alloc(&c->d_lp_flags, 2 * (int64_t)c->ntm));
   HIPCK(c, hipMemsetAsync(c->d_lp_ticket, 0, 2 * sizeof(unsigned long long), c->st));
-  HIPCK(c, hipMemsetAsync(c->d_lp_flags, 0, 2 * (int64_t)c->ntm * sizeof(int), c->st));
+  sentinel_fill(3 * m, c->d_lpy, c->st);
   return PD_OK;
 }
 
@@ -1250,23 +1248,24 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
         // deferred right-hand side: the one given to pd_supply_rhs)
         if (c->deferred && !c->rhs_supplied)
           return c->fail(PD_ERR_STATE, "pd_factor(supply_rhs) needs pd_supply_rhs before the solve");
-        rhs_unpack(m, c->d_Yt, c->d_y, m, c->st);
+        rhs_unpack(m, c->d_Yt, c->d_ys, m, c->st);
+        sentinel_fill(3 * m, u, c->st);     // the backward solve publishes u by value
         c->deferred = false;
         c->rhs_supplied = false;
       } else if (c->overlap) {
         // the factorization may still run on another stream: the forward
         // solve follows its tile flags, the backward one waits for its end
         HIPCK(c, hipStreamWaitEvent(c->st, c->ev_fstart, 0));
-        trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
-                      c->d_err, c->st, c->d_tflags, c->d_tticket);
+        trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_ys, m, c->d_ticket, c->d_err, u, m,
+                      c->st, c->d_tflags, c->d_tticket);
         HIPCK(c, hipStreamWaitEvent(c->st, c->ev_fdone, 0));
         c->overlap = false;
       } else {
-        trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
-                      c->d_err, c->st);
+        trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_ys, m, c->d_ticket, c->d_err, u, m,
+                      c->st);
       }
-      trsv3_backward(c->d_H, c->ldH, m, c->d_linv, c->d_y, m, u, m, c->d_ticket + 1,
-                     c->d_flags + c->ntm, c->d_err, c->st);
+      trsv3_backward(c->d_H, c->ldH, m, c->d_linv, c->d_ys, m, u, m, c->d_ticket + 1, c->d_err,
+                     c->st);
     }
     CK(c->check("pd_global_solve"));
     if (info) {
@@ -1333,10 +1332,10 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
     c->stale = false;
     {
       PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
-      trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_y, m, c->d_ticket, c->d_flags,
-                    c->d_err, c->st);
-      trsv3_backward(c->d_H, c->ldH, m, c->d_linv, c->d_y, m, u, m, c->d_ticket + 1,
-                     c->d_flags + c->ntm, c->d_err, c->st);
+      trsv3_forward(c->d_H, c->ldH, m, c->d_linv, g, m, c->d_ys, m, c->d_ticket, c->d_err, u, m,
+                    c->st);
+      trsv3_backward(c->d_H, c->ldH, m, c->d_linv, c->d_ys, m, u, m, c->d_ticket + 1, c->d_err,
+                     c->st);
     }
     CK(c->check("pd_global_solve"));
     CK(residual(c, g, u, &rr));

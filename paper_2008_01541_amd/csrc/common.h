@@ -45,22 +45,26 @@ void copy_i32(long n, const int32_t* src, int32_t* dst, hipStream_t st);
 void trtri_from_factor(const double* L, int ldl, int n, const double* linv_ws, double* M,
                        double* X, int ldx, hipStream_t st);
 void lauum_full(const double* X, int ldx, int n, double* Z, int ldz, hipStream_t st);
+// Triangular solves with the tiled factor, three right-hand sides.  The
+// output vector publishes each value as it is stored: before the forward
+// solve y must hold the sentinel everywhere (sentinel_fill once; the backward
+// solve refills y as it reads it), and the forward solve writes the sentinel
+// into xfill (the backward solve's output; may alias g) as it reads g.
 // fflags/fticket: the tile flags and ticket of a dataflow Cholesky of L still
 // running on another stream (forward solve overlapped with it), or null.
+void sentinel_fill(long n, double* p, hipStream_t st);
 void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const double* g,
-                   int ldg, double* y, int ldy, unsigned long long* ticket, int* flags,
-                   int* err, hipStream_t st, const int* fflags = nullptr,
+                   int ldg, double* y, int ldy, unsigned long long* ticket, int* err,
+                   double* xfill, int ldxf, hipStream_t st, const int* fflags = nullptr,
                    const unsigned* fticket = nullptr);
-void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
-                    int ldy, double* x, int ldx, unsigned long long* ticket, int* flags,
-                    int* err, hipStream_t st);
+void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, double* y, int ldy,
+                    double* x, int ldx, unsigned long long* ticket, int* err, hipStream_t st);
 // the same solves with a float factor (FP64 vectors and arithmetic)
 void trsv3_forward(const float* L, int ld, int n, const float* linv_ws, const double* g, int ldg,
-                   double* y, int ldy, unsigned long long* ticket, int* flags, int* err,
-                   hipStream_t st);
-void trsv3_backward(const float* L, int ld, int n, const float* linv_ws, const double* y, int ldy,
-                    double* x, int ldx, unsigned long long* ticket, int* flags, int* err,
-                    hipStream_t st);
+                   double* y, int ldy, unsigned long long* ticket, int* err, double* xfill,
+                   int ldxf, hipStream_t st);
+void trsv3_backward(const float* L, int ld, int n, const float* linv_ws, double* y, int ldy,
+                    double* x, int ldx, unsigned long long* ticket, int* err, hipStream_t st);
 // y = alpha * A v + beta * y for symmetric A (full storage), 3 right-hand sides.
 void symv3(const double* A, int lda, int n, const double* v, int ldv, double alpha,
            double beta, double* y, int ldy, hipStream_t st);
@@ -73,10 +77,11 @@ void potrf_dataflow_lp(float* A, int lda, int n, float* linv_ws, float* sbuf, in
 void equilibrate_convert(const double* H, int ld, int n, double* d, float* H32, int ld32,
                          hipStream_t st);
 // x (+)= D L^-T L^-1 D r with L the FP32 factor of D H D (three right-hand
-// sides); b, y: 3 n doubles of workspace; flags: 2 nt ints, tickets[2].
+// sides); b, y: 3 n doubles of workspace, y holding the sentinel
+// (sentinel_fill once; each call leaves it so); tickets[2].
 void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const double* d,
                     const double* r, double* b, double* y, double* x, int accumulate,
-                    unsigned long long* tickets, int* flags, int* err, hipStream_t st);
+                    unsigned long long* tickets, int* err, hipStream_t st);
 
 // conjugate-gradient steps on three independent columns [3][n] (scalars in
 // device memory): out[v] = a_v . b_v; with nq = -H p and pnq = p . nq,

@@ -104,6 +104,16 @@ __device__ inline void tri_index(int b, int& i, int& j) {
   j = b - ii * (ii + 1) / 2;
 }
 
+// An empty asm that takes all sixteen values: every load feeding them is
+// issued before it and they are waited for once, instead of the compiler
+// turning each select of a loaded value into a branch with its own wait.
+__device__ inline void regs_ready(double (&v)[16]) {
+  asm volatile(""
+               : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),
+                 "+v"(v[6]), "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]),
+                 "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15]));
+}
+
 // ---------------------------------------------------------------------------
 // Single-launch tiled Cholesky.  Persistent workgroups claim lower tiles in
 // column-major order from a ticket counter; the workgroup that owns tile
@@ -360,10 +370,10 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
         double v[16];
 #pragma unroll
         for (int qq = 0; qq < 16; ++qq)
-          v[qq] = (r < mr) ? coherent_load(&A[(long)(r0 + r) + (long)(cs + (t >> 6) + 4 * qq) * lda])
-                           : 0.0;
+          v[qq] = coherent_load(&A[(long)(r0 + min(r, mr - 1)) + (long)(cs + (t >> 6) + 4 * qq) * lda]);
+        regs_ready(v);
 #pragma unroll
-        for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][r] = v[qq];
+        for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][r] = (r < mr) ? v[qq] : 0.0;
       }
       if (t == 0 && (!df_wait(&sflags[j], epoch, err) ||
                      !df_wait(&flags[(j - 1) * nt + (j - 1)], epoch, err)))
@@ -425,10 +435,10 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
           double v[16];
 #pragma unroll
           for (int qq = 0; qq < 16; ++qq)
-            v[qq] = (r < mr) ? coherent_load(&A[(long)(r0 + r) + (long)(cs + (t >> 6) + 4 * qq) * lda])
-                             : 0.0;
+            v[qq] = coherent_load(&A[(long)(r0 + min(r, mr - 1)) + (long)(cs + (t >> 6) + 4 * qq) * lda]);
+          regs_ready(v);
 #pragma unroll
-          for (int qq = 0; qq < 16; ++qq) buf1[(t >> 6) + 4 * qq][r] = v[qq];
+          for (int qq = 0; qq < 16; ++qq) buf1[(t >> 6) + 4 * qq][r] = (r < mr) ? v[qq] : 0.0;
         }
         __syncthreads();
         for (int e = t; e < NB * NB; e += 256) {

@@ -513,12 +513,12 @@ __global__ void k_unscale3(int n, const double* __restrict__ d, const double* __
 
 void trsv3_lp_solve(const float* L, int ld, int n, const float* linv_ws, const double* d,
                     const double* r, double* b, double* y, double* x, int accumulate,
-                    unsigned long long* tickets, int* flags, int* err, hipStream_t st) {
-  const int nt = (n + NB - 1) / NB;
+                    unsigned long long* tickets, int* err, hipStream_t st) {
   const int g = (3 * n + 255) / 256;
   k_scale3<<<g, 256, 0, st>>>(n, d, r, b);
-  trsv3_forward(L, ld, n, linv_ws, b, n, y, n, tickets, flags, err, st);
-  trsv3_backward(L, ld, n, linv_ws, y, n, b, n, tickets + 1, flags + nt, err, st);   // z into b
+  // the forward solve puts the sentinel into b as it reads it; z into b
+  trsv3_forward(L, ld, n, linv_ws, b, n, y, n, tickets, err, b, n, st);
+  trsv3_backward(L, ld, n, linv_ws, y, n, b, n, tickets + 1, err, st);
   k_unscale3<<<g, 256, 0, st>>>(n, d, b, x, accumulate);
 }
 

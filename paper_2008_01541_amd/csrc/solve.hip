@@ -9,23 +9,77 @@ namespace pdk {
 
 // ---------------------------------------------------------------------------
 // Three-right-hand-side triangular solves with the tiled factor.  One
-// workgroup per block row; rows are claimed in dependency order through a
-// ticket counter, so every claimed row only waits on rows claimed earlier by
-// running workgroups.  Row completion is published with a per-call epoch.
+// workgroup per pair of block rows; rows are claimed in dependency order
+// through a ticket counter, so every claimed row only waits on rows claimed
+// earlier by running workgroups.
+//
+// Publication by value: the vector a solve produces (y of the forward solve,
+// x of the backward one) holds a sentinel before the solve (a signalling NaN
+// bit pattern, which no arithmetic produces: every NaN an operation returns
+// is quiet); each value is published by its own agent-coherent 8-byte store,
+// and a consumer polls the values of a block row with coherent loads until
+// none is the sentinel.  This takes one round trip per hand-off instead of a
+// flag (stores drained, flag stored, flag polled, data loaded).  The
+// sentinels are written by the solve that consumes the previous content:
+// the forward solve puts them into x as it reads each value of its right-hand
+// side (so x may alias the right-hand side), the backward solve puts them
+// back into y as it reads y, and sentinel_fill() prepares a vector once.
 
 constexpr long SPIN_LIMIT = 1L << 24;
+constexpr unsigned long long SENTINEL = 0x7FF0DEAD00000001ull;   // signalling NaN
 
-__device__ inline bool wait_flag(int* f, int epoch, int* err) {
+__device__ inline bool is_sentinel(double v) {
+  return __builtin_bit_cast(unsigned long long, v) == SENTINEL;
+}
+
+__global__ void k_sentinel_fill(long n, double* p) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = __builtin_bit_cast(double, SENTINEL);
+}
+void sentinel_fill(long n, double* p, hipStream_t st) {
+  if (n > 0) k_sentinel_fill<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, p);
+}
+
+// Workgroup barrier for data exchanged through LDS only: waits for this
+// wave's LDS operations, not for its global loads and stores in flight (the
+// barrier of __syncthreads also waits for those, which puts the latency of
+// every write-through store of a published value on the chain).
+__device__ inline void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Polls the cnt values v[0 .. cnt - 1] of the three columns (v[c * ldv + e])
+// into out[c][e] until none is the sentinel; false (and *err set) after the
+// spin limit or when another workgroup has set *err.  Uniform over the block.
+template <int CAP>
+__device__ inline bool poll_block(const double* v, int ldv, int cnt, double (*out)[CAP],
+                                  int (*s_miss)[4], int* err) {
+  const int t = threadIdx.x;
   long spins = 0;
-  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    __builtin_amdgcn_s_sleep(1);
-    if (++spins > SPIN_LIMIT) {
-      atomicExch(err, 1);
+  for (int it = 0;; it ^= 1) {
+    int miss = 0;
+    for (int e = t; e < 3 * CAP; e += 256) {
+      const int c = e / CAP, cc = e - c * CAP;
+      double val = 0.0;
+      if (cc < cnt) {
+        val = coherent_load(&v[(long)c * ldv + cc]);
+        miss |= is_sentinel(val) ? 1 : 0;
+      }
+      out[c][cc] = val;
+    }
+    // one slot per wave, two sets used alternately so that a slot is not
+    // rewritten before every wave has read it
+    const bool wmiss = __ballot(miss) != 0;
+    if ((t & 63) == 0) s_miss[it][t >> 6] = wmiss ? 1 : 0;
+    lds_barrier();
+    if (!(s_miss[it][0] | s_miss[it][1] | s_miss[it][2] | s_miss[it][3])) return true;
+    if (++spins > SPIN_LIMIT ||
+        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      if (t == 0) atomicExch(err, 1);
       return false;
     }
+    __builtin_amdgcn_s_sleep(1);
   }
-  return true;
 }
 
 // Two tile rows per workgroup ("super-row" s: tile rows TR s and TR s + 1), so
@@ -36,14 +90,37 @@ constexpr int TR = 2;
 
 // sums the four column-group partials of part (3 x 64 per group) into out[v][rr]
 // = base[v][rr] - sum; base may be null (then out = sum).
-__device__ inline void trsv_reduce(double (*part)[3][NB], const double* base, int ldb, int r0,
-                                   int mr, double (*out)[NB], bool negate) {
+// out[v][rr] = b - (sum of the four column-group partials of part) for
+// thread t = 64 v + rr < 192, b = this thread's right-hand-side value.
+__device__ inline void trsv_reduce(double (*part)[3][NB], double b, double (*out)[NB]) {
   const int t = threadIdx.x;
   if (t < 3 * NB) {
     const int v = t >> 6, rr = t & 63;
     const double sum = part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr];
-    const double b = (base && rr < mr) ? base[(long)v * ldb + r0 + rr] : 0.0;
-    out[v][rr] = negate ? b - sum : sum;
+    out[v][rr] = b - sum;
+  }
+}
+
+// The right-hand-side values of the TR tile rows from i0 on, one per thread
+// t = 64 v + rr < 192 (rows past n: 0), read at the start so that their
+// latency is off the chain; fill (may alias base) gets the sentinel at each
+// value once it is read, by the thread that read it.
+template <int R>
+__device__ inline void load_rhs(const double* base, int ldb, int i0, int nu, int n, double* fill,
+                                int ldf, double (&b)[R]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < R; ++u) b[u] = 0.0;
+  if (t < 3 * NB) {
+    const int v = t >> 6, rr = t & 63;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int row = (i0 + u) * NB + rr;
+      if (u < nu && row < n) {
+        b[u] = base[(long)v * ldb + row];
+        if (fill) fill[(long)v * ldf + row] = __builtin_bit_cast(double, SENTINEL);
+      }
+    }
   }
 }
 
@@ -81,14 +158,15 @@ __device__ inline float panel_load<float>(__amdgpu_buffer_rsrc_t rs, int voff, i
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, int ld, int n,
                                                    int nt, const T* __restrict__ linv,
-                                                   const double* __restrict__ g, int ldg,
+                                                   const double* g, int ldg,
                                                    double* y, int ldy,
-                                                   unsigned long long* ticket, int* flags,
-                                                   int* err, const int* fflags,
-                                                   const unsigned* fticket) {
-  __shared__ int s_row, s_epoch, s_ok;
+                                                   unsigned long long* ticket, int* err,
+                                                   const int* fflags, const unsigned* fticket,
+                                                   double* xfill, int ldxf) {
+  __shared__ int s_row, s_ok;
   __shared__ double Ls[TR][NB][NB + 1];     // Ls[u][c][r] = Linv_{i_u}(r, c)
   __shared__ double ys[3][TR * NB];         // y of a finished super-row / of this one
+  __shared__ int s_miss[2][4];
   __shared__ double part[4][3][NB];
   __shared__ double zs[3][NB];
   const int t = threadIdx.x;
@@ -96,21 +174,22 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, i
   if (t == 0) {
     const unsigned long long tk = atomicAdd(ticket, 1ull);
     s_row = (int)(tk % (unsigned long long)ns);
-    s_epoch = (int)(tk / (unsigned long long)ns) + 1;
     s_ok = 1;
   }
-  __syncthreads();
-  const int sr = s_row, epoch = s_epoch;
+  lds_barrier();
+  const int sr = s_row;
   const int r = t & 63, cg = t >> 6;
   const int cgs = __builtin_amdgcn_readfirstlane(cg);    // cg is uniform per wave
   const int i0 = TR * sr, nu = min(TR, nt - i0);
+  double rhs[TR];
+  load_rhs<TR>(g, ldg, i0, nu, n, xfill, ldxf, rhs);
   if (fflags) {
     if (t == 0) {
       const int fe = (int)__hip_atomic_load(&fticket[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const int il = i0 + nu - 1;
       if (!df_wait(&fflags[il * nt + il], fe, err)) s_ok = 0;
     }
-    __syncthreads();
+    lds_barrier();
     if (!s_ok) return;
   }
   for (int u = 0; u < nu; ++u) {
@@ -156,14 +235,7 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, i
           lv[u][w][c] = panel_load<T>(prs, voff, (w * NB + cgs * 16 + c) * ld * (int)sizeof(T)) *
                         (ok ? T(1) : T(0));
     }
-    if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
-    __syncthreads();
-    if (!s_ok) return;
-    for (int e = t; e < 3 * TR * NB; e += 256) {
-      const int v = e / (TR * NB), cc = e - v * TR * NB;
-      ys[v][cc] = coherent_load(&y[(long)v * ldy + TR * q * NB + cc]);
-    }
-    __syncthreads();
+    if (!poll_block<TR * NB>(y + (long)TR * q * NB, ldy, TR * NB, ys, s_miss, err)) return;
     // each operand of ys is read once and used for every tile row; four
     // columns at a time, so that the operands are not all held at once
 #pragma unroll
@@ -180,10 +252,14 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, i
         }
         if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
-    __syncthreads();
+    lds_barrier();
   }
-  // finish the tile rows of this super-row in order
-  for (int u = 0; u < nu; ++u) {
+  // finish the tile rows of this super-row in order (unrolled, so that the
+  // accumulators acc[u] are indexed at compile time, not through register
+  // indexing)
+#pragma unroll
+  for (int u = 0; u < TR; ++u) {
+    if (u >= nu) break;
     const int i = i0 + u, r0 = i * NB, mr = min(NB, n - r0);
     if (u > 0) {           // coupling to the row finished above in this super-row
 #pragma unroll
@@ -198,9 +274,9 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, i
     part[cg][0][r] = acc[u][0];
     part[cg][1][r] = acc[u][1];
     part[cg][2][r] = acc[u][2];
-    __syncthreads();
-    trsv_reduce(part, g, ldg, r0, mr, zs, true);        // zs = g_i - sum
-    __syncthreads();
+    lds_barrier();
+    trsv_reduce(part, rhs[u], zs);                      // zs = g_i - sum
+    lds_barrier();
     // y_i = Linv_ii zs: column group cg adds columns 16 cg .. 16 cg + 15
     {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -216,16 +292,15 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, i
       part[cg][1][r] = s1;
       part[cg][2][r] = s2;
     }
-    __syncthreads();
+    lds_barrier();
     if (t < 3 * NB) {
       const int v = t >> 6, rr = t & 63;
       const double yv = part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr];
       ys[v][u * NB + rr] = yv;
-      if (rr < mr) coherent_store(&y[(long)v * ldy + r0 + rr], yv);
+      if (rr < mr) coherent_store(&y[(long)v * ldy + r0 + rr], yv);   // published
     }
-    __syncthreads();
+    lds_barrier();
   }
-  publish_flag(&flags[sr], epoch);
 }
 
 // L^T x = y, reading L^T from the upper triangle (U(r, c) = L(c, r) for c > r):
@@ -233,13 +308,13 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_fwd(const T* __restrict__ L, i
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_trsv3_bwd(const T* __restrict__ L, int ld, int n,
                                                    int nt, const T* __restrict__ linv,
-                                                   const double* __restrict__ y, int ldy,
+                                                   double* y, int ldy,
                                                    double* x, int ldx,
-                                                   unsigned long long* ticket, int* flags,
-                                                   int* err) {
-  __shared__ int s_row, s_epoch, s_ok;
+                                                   unsigned long long* ticket, int* err) {
+  __shared__ int s_row, s_ok;
   __shared__ double Ls[TR][NB][NB + 1];     // Ls[u][c][r] = Linv_{i_u}(r, c)
   __shared__ double xs[3][TR * NB];
+  __shared__ int s_miss[2][4];
   __shared__ double part[4][3][NB];
   __shared__ double zs[3][NB];
   const int t = threadIdx.x;
@@ -247,14 +322,15 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_bwd(const T* __restrict__ L, i
   if (t == 0) {
     const unsigned long long tk = atomicAdd(ticket, 1ull);
     s_row = ns - 1 - (int)(tk % (unsigned long long)ns);
-    s_epoch = (int)(tk / (unsigned long long)ns) + 1;
     s_ok = 1;
   }
-  __syncthreads();
-  const int sr = s_row, epoch = s_epoch;
+  lds_barrier();
+  const int sr = s_row;
   const int r = t & 63, cg = t >> 6;
   const int cgs = __builtin_amdgcn_readfirstlane(cg);    // cg is uniform per wave
   const int i0 = TR * sr, nu = min(TR, nt - i0);
+  double rhs[TR];
+  load_rhs<TR>(y, ldy, i0, nu, n, y, ldy, rhs);        // y refilled with the sentinel
   for (int u = 0; u < nu; ++u) {
     const T* Li = linv + (long)(i0 + u) * NB * NB;
     double v16[16];
@@ -301,15 +377,8 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_bwd(const T* __restrict__ L, i
                         ((okr && col < n) ? T(1) : T(0));
         }
     }
-    if (t == 0 && !wait_flag(&flags[q], epoch, err)) s_ok = 0;
-    __syncthreads();
-    if (!s_ok) return;
     const int qn = min(TR * NB, n - TR * q * NB);
-    for (int e = t; e < 3 * TR * NB; e += 256) {
-      const int v = e / (TR * NB), cc = e - v * TR * NB;
-      xs[v][cc] = (cc < qn) ? coherent_load(&x[(long)v * ldx + TR * q * NB + cc]) : 0.0;
-    }
-    __syncthreads();
+    if (!poll_block<TR * NB>(x + (long)TR * q * NB, ldx, qn, xs, s_miss, err)) return;
     // each operand of xs is read once and used for every tile row; four
     // columns at a time, so that the operands are not all held at once
 #pragma unroll
@@ -326,9 +395,13 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_bwd(const T* __restrict__ L, i
         }
         if ((c & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }
-    __syncthreads();
+    lds_barrier();
   }
-  for (int u = nu - 1; u >= 0; --u) {
+  // (unrolled, so that the accumulators acc[u] are indexed at compile time)
+#pragma unroll
+  for (int uu = 0; uu < TR; ++uu) {
+    const int u = TR - 1 - uu;
+    if (u >= nu) continue;
     const int i = i0 + u, r0 = i * NB, mr = min(NB, n - r0);
     if (u + 1 < nu) {      // coupling to the row finished below in this super-row
 #pragma unroll
@@ -343,9 +416,9 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_bwd(const T* __restrict__ L, i
     part[cg][0][r] = acc[u][0];
     part[cg][1][r] = acc[u][1];
     part[cg][2][r] = acc[u][2];
-    __syncthreads();
-    trsv_reduce(part, y, ldy, r0, mr, zs, true);        // zs = y_i - sum
-    __syncthreads();
+    lds_barrier();
+    trsv_reduce(part, rhs[u], zs);                      // zs = y_i - sum
+    lds_barrier();
     // x_i = Linv_ii^T zs: (Linv^T z)(rr) = sum_c Linv(c, rr) z(c) = sum_c Ls[rr][c] z(c);
     // thread (r, cg) adds c = 16 cg .. 16 cg + 15 for output row r
     {
@@ -362,46 +435,44 @@ __global__ __launch_bounds__(256, 2) void k_trsv3_bwd(const T* __restrict__ L, i
       part[cg][1][r] = s1;
       part[cg][2][r] = s2;
     }
-    __syncthreads();
+    lds_barrier();
     if (t < 3 * NB) {
       const int v = t >> 6, rr = t & 63;
       const double xv = part[0][v][rr] + part[1][v][rr] + part[2][v][rr] + part[3][v][rr];
       xs[v][u * NB + rr] = xv;
-      if (rr < mr) coherent_store(&x[(long)v * ldx + r0 + rr], xv);
+      if (rr < mr) coherent_store(&x[(long)v * ldx + r0 + rr], xv);   // published
     }
-    __syncthreads();
+    lds_barrier();
   }
-  publish_flag(&flags[sr], epoch);
 }
 
 void trsv3_forward(const double* L, int ld, int n, const double* linv_ws, const double* g,
-                   int ldg, double* y, int ldy, unsigned long long* ticket, int* flags,
-                   int* err, hipStream_t st, const int* fflags, const unsigned* fticket) {
+                   int ldg, double* y, int ldy, unsigned long long* ticket, int* err,
+                   double* xfill, int ldxf, hipStream_t st, const int* fflags,
+                   const unsigned* fticket) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_fwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err,
-                                          fflags, fticket);
+  k_trsv3_fwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, err,
+                                          fflags, fticket, xfill, ldxf);
 }
 
-void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, const double* y,
-                    int ldy, double* x, int ldx, unsigned long long* ticket, int* flags,
-                    int* err, hipStream_t st) {
+void trsv3_backward(const double* L, int ld, int n, const double* linv_ws, double* y, int ldy,
+                    double* x, int ldx, unsigned long long* ticket, int* err, hipStream_t st) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_bwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, flags, err);
+  k_trsv3_bwd<double><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, err);
 }
 
 // The same solves with a float factor (FP64 vectors and arithmetic).
 void trsv3_forward(const float* L, int ld, int n, const float* linv_ws, const double* g, int ldg,
-                   double* y, int ldy, unsigned long long* ticket, int* flags, int* err,
-                   hipStream_t st) {
+                   double* y, int ldy, unsigned long long* ticket, int* err, double* xfill,
+                   int ldxf, hipStream_t st) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_fwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, flags, err,
-                                         nullptr, nullptr);
+  k_trsv3_fwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, g, ldg, y, ldy, ticket, err,
+                                         nullptr, nullptr, xfill, ldxf);
 }
-void trsv3_backward(const float* L, int ld, int n, const float* linv_ws, const double* y, int ldy,
-                    double* x, int ldx, unsigned long long* ticket, int* flags, int* err,
-                    hipStream_t st) {
+void trsv3_backward(const float* L, int ld, int n, const float* linv_ws, double* y, int ldy,
+                    double* x, int ldx, unsigned long long* ticket, int* err, hipStream_t st) {
   const int nt = (n + NB - 1) / NB, ns = (nt + TR - 1) / TR;
-  k_trsv3_bwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, flags, err);
+  k_trsv3_bwd<float><<<ns, 256, 0, st>>>(L, ld, n, nt, linv_ws, y, ldy, x, ldx, ticket, err);
 }
 
 }  // namespace pdk

@@ -47,11 +47,11 @@ __device__ __forceinline__ void chol16_step(double (&a)[16], double (&x)[16], do
   if constexpr (C < 16) {
     const bool ok = d > 0.0;
     bad = (!ok && bad == 0) ? C + 1 : bad;
-    d = ok ? d : 1.0;
-    const double y = rsqrt_newton(d);
-    // column C of L: d y on the diagonal, a y below, 0 above (branch-free)
-    const double sc = (r > C) ? y : 0.0;
-    a[C] = fma(a[C], sc, (r == C) ? d * y : 0.0);
+    const double y = ok ? rsqrt_newton(d) : 1.0;
+    // column C of L, d y on the diagonal and a y below; the lanes above the
+    // diagonal (r < C) only carry values of the upper part, which no later
+    // step reads into the lower part, and are cleared after the last step
+    a[C] *= y;
     x[C] *= y;
     double dn = 0.0;
     if constexpr (C + 1 < 16) {
@@ -66,8 +66,8 @@ __device__ __forceinline__ void chol16_step(double (&a)[16], double (&x)[16], do
 // LDS tile T, by one wave (the four rows of 16 lanes work redundantly).  L
 // replaces the lower part of the block (zeros above), its inverse goes to the
 // same block of X (zeros above).  The first non-positive pivot j of the block
-// (inside the first mr rows) is reported in *info as gbase + b0 + j + 1 and
-// replaced by 1.
+// (inside the first mr rows) is reported in *info as gbase + b0 + j + 1, and
+// its reciprocal square root is taken as 1.
 __device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[LDS_LD], int b0,
                                                int mr, int gbase, int* info) {
   const int lane = threadIdx.x & 63, r = lane & 15;
@@ -80,6 +80,8 @@ __device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[
   int bad = 0;          // first non-positive pivot of the block, 1-based; 0: none
   chol16_step<0>(a, x, row_bcast<0>(a[0]), r, bad);
   if (lane == 0 && bad > 0 && b0 + bad - 1 < mr) atomicCAS(info, 0, gbase + b0 + bad);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = (r >= c) ? a[c] : 0.0;
   if (lane < 16) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) T[b0 + c][b0 + r] = a[c];
@@ -116,8 +118,8 @@ __device__ inline void mma16(double4_t& acc, double (*As)[LDS_LD], int am, int a
 // diagonal block (the staged Y_ij waits in the X_ij slot until X_ii exists),
 // so only the last block row is left after the final diagonal block.  A
 // non-positive pivot stores its 1-based global index gbase + j + 1 in *info
-// (first one wins) and is replaced by 1 so that the factorization stays
-// finite.  Only the lower triangle of T is meaningful on return.
+// (first one wins) and its reciprocal square root is taken as 1 so that the
+// factorization stays finite.  Only the lower triangle of T is meaningful on return.
 __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
                                     int* info) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
