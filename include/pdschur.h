@@ -354,6 +354,20 @@ pd_status pd_chol_factor_noalloc(double *A, int64_t lda, int64_t n, int32_t n_wo
                                  void *hip_stream, int32_t *info_host);
 
 
+/* Schedule of the single-launch dataflow Cholesky (pd_chol_factor, the
+ * factorization of H = S + P in pd_global_solve / pd_factor), for checking
+ * its index ranges on the host (no GPU work; the kernels decode their
+ * tickets with the same code).  For order n (tiles of 64, nt = ceil(n/64)),
+ * rhs = 1 when the three right-hand sides ride along as an extra tile row,
+ * supplied = 1 when that row is given during the factorization (its tasks
+ * then come after all tiles): *ntask receives the number of tasks, and for
+ * 0 <= q < *ntask the tile (*i, *j) of ticket q (*i == nt: the right-hand-side
+ * row) and *kend, the number of 64-column steps the task accumulates.
+ * n < 1, rhs or supplied not 0/1, supplied without rhs, or q outside
+ * [0, *ntask) (q < 0 only queries the count) -> PD_ERR_INVALID. */
+pd_status pd_dataflow_task(int64_t n, int32_t rhs, int32_t supplied, int64_t q, int32_t *i,
+                           int32_t *j, int32_t *kend, int64_t *ntask);
+
 typedef struct pd_mlp pd_mlp;
 
 /* Creates the network with the given initial parameters (host, packed as

@@ -70,6 +70,8 @@ _SIGS = {
     "pd_chol_create": [C.c_int64, _P, C.POINTER(_P)],
     "pd_chol_factor": [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32)],
     "pd_chol_destroy": [_P],
+    "pd_dataflow_task": [C.c_int64, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
+                         C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
     "pd_chol_factor_noalloc": [_P, C.c_int64, C.c_int64, C.c_int32, _P, C.POINTER(C.c_int32)],
     "pd_displacement_change": [_P, _P, _P, _P],
     "pd_warmstart_input": [_P, _P, _P, C.c_float, C.c_int32, _P, _P, _P],

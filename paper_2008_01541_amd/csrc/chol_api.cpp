@@ -6,6 +6,7 @@
 
 #include "../../include/pdschur.h"
 #include "common.h"
+#include "df_schedule.h"
 
 using namespace pdk;
 
@@ -186,6 +187,23 @@ pd_status pd_chol_destroy(pd_chol* h) {
   if (!h) return PD_ERR_INVALID;
   (void)hipStreamSynchronize(h->st);
   delete h;
+  return PD_OK;
+}
+
+pd_status pd_dataflow_task(int64_t n, int32_t rhs, int32_t supplied, int64_t q, int32_t* i,
+                           int32_t* j, int32_t* kend, int64_t* ntask) {
+  if (n < 1 || n > 46340 || (rhs != 0 && rhs != 1) || (supplied != 0 && supplied != 1) ||
+      (supplied && !rhs) || !ntask)
+    return PD_ERR_INVALID;
+  const int nt = (int)((n + NB - 1) / NB);
+  *ntask = df_task_count(nt, rhs);
+  if (q < 0) return PD_OK;
+  if (q >= *ntask || !i || !j || !kend) return PD_ERR_INVALID;
+  int ti, tj;
+  df_task_of_ticket((int)q, nt, rhs, supplied != 0, ti, tj);
+  *i = ti;
+  *j = tj;
+  *kend = df_task_kend(ti, tj);
   return PD_OK;
 }
 

@@ -8,6 +8,7 @@
 #include "common.h"
 #include "tile_factor_f64.h"
 #include "publish.h"
+#include "df_schedule.h"
 
 namespace pdk {
 
@@ -272,7 +273,6 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
                                                            int gepoch, int* cu_marks) {
   const int epoch = (int)ticket[1];
   const int rhs = Yt != nullptr ? 1 : 0;
-  const int ntile = nt * (nt + 1) / 2;
   int* const mark = cu_marks ? cu_marks + cu_slot() : nullptr;
   int* sflags = flags + (nt + 1) * nt;
   // two 64 x 68 double tiles (69,632 bytes): operands of the accumulation,
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
   __shared__ double buf1[NB][LDS_LD];
   __shared__ int s_task, s_ok;
   const int t = threadIdx.x;
-  const int ntask = nt * (nt + 1) / 2 + rhs * nt;
+  const int ntask = df_task_count(nt, rhs);
   for (;;) {
     __syncthreads();
     if (t == 0) {
@@ -292,29 +292,13 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     const int q = s_task;
     if (q >= ntask) return;
     int i, j;
-    if (gflag) {
+    df_task_of_ticket(q, nt, rhs, gflag != nullptr, i, j);
+    if (gflag && i == nt) {
       // right-hand side supplied during the factorization: its row comes
       // after all tiles, and each of its tasks first waits for it
-      if (q < ntile) {
-        j = 0;
-        int start = 0;
-        while (start + (nt - j) <= q) start += nt - j++;
-        i = j + (q - start);
-      } else {
-        i = nt;
-        j = q - ntile;
-        if (t == 0 && !df_wait(gflag, gepoch, err)) s_ok = 0;
-        __syncthreads();
-        if (!s_ok) return;
-      }
-    } else {
-      j = 0;
-      int start = 0;
-      while (start + (nt - j + rhs) <= q) {
-        start += nt - j + rhs;
-        ++j;
-      }
-      i = j + (q - start);                 // i == nt: the right-hand-side row
+      if (t == 0 && !df_wait(gflag, gepoch, err)) s_ok = 0;
+      __syncthreads();
+      if (!s_ok) return;
     }
     const bool rrow = (i == nt);
     const bool diag = (i == j), sub = !rrow && i == j + 1;
@@ -340,7 +324,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
                                 ? -coherent_load(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai])
                                 : ((diag && r == c) ? -1.0 : 0.0);
         }
-    const int kend = diag ? max(j - 1, 0) : j;
+    const int kend = df_task_kend(i, j);
     if (!df_accumulate(acc, buf0, buf1, Ai, ldai, r0, mr, A, lda, c0, mc, i, j, kend, nt, flags,
                        epoch, err, &s_ok, critical ? nullptr : mark))
       return;
@@ -480,7 +464,7 @@ void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, in
                     unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
                     const int* gflag, int gepoch, int* cu_marks, hipEvent_t after_reset) {
   const int nt = (n + NB - 1) / NB;
-  const int ntask = nt * (nt + 1) / 2 + (Yt ? nt : 0);
+  const int ntask = df_task_count(nt, Yt ? 1 : 0);
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
   if (after_reset) (void)hipEventRecord(after_reset, st);
   k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, sbuf, flags,

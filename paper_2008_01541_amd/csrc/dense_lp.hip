@@ -7,6 +7,7 @@
 #include <algorithm>
 #include "common.h"
 #include "tile_factor_f64.h"
+#include "df_schedule.h"
 
 namespace pdk {
 
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
   float (*buf0)[LP_LD] = reinterpret_cast<float (*)[LP_LD]>(&Tf[0][0]);
   float (*buf1)[LP_LD] = reinterpret_cast<float (*)[LP_LD]>(&Xf[0][0]);
   const int t = threadIdx.x;
-  const int ntask = nt * (nt + 1) / 2;
+  const int ntask = df_task_count(nt, 0);
   for (;;) {
     __syncthreads();
     if (t == 0) {
@@ -306,12 +307,8 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
     __syncthreads();
     const int q = s_task;
     if (q >= ntask) return;
-    int j = 0, start = 0;
-    while (start + (nt - j) <= q) {
-      start += nt - j;
-      ++j;
-    }
-    const int i = j + (q - start);
+    int i, j;
+    df_task_of_ticket(q, nt, 0, false, i, j);
     const bool diag = (i == j), sub = (i == j + 1);
     const bool critical = diag || sub;
     const int r0 = i * NB, c0 = j * NB;
@@ -330,7 +327,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
                             : (r < mr && c < mc) ? -cload(&A[(long)(r0 + r) + (long)(c0 + c) * lda])
                                                  : ((diag && r == c) ? -1.f : 0.f);
         }
-    const int kend = diag ? max(j - 1, 0) : j;
+    const int kend = df_task_kend(i, j);
     if (!lp_accumulate<BF16>(acc, buf0, buf1, A, lda, r0, mr, c0, mc, i, j, kend, nt, flags, epoch,
                              err, &s_ok, critical ? nullptr : mark))
       return;

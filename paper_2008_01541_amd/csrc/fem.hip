@@ -163,14 +163,15 @@ __device__ inline void givens_rows(T B[3][3], T U[3][3], int p, int q) {
   }
 }
 
-// With Q non-null also the strain-limited projection of the biphasic material
+// Q: the strain-limited projection of the biphasic material
 // (Sec. 5.3): F V = U diag(b) with b_1, b_2 >= 0 and b_3 of either sign, so
 // the singular values are |b_i| with left vectors sign(b_i) U e_i, and the
 // closest matrix with singular values in [smin, smax] is
-// Q = U diag(sign(b_i) clamp(|b_i|)) V^T.
+// Q = U diag(sign(b_i) clamp(|b_i|)) V^T (computed always: a pointer chosen
+// at run time would keep the arrays in private memory; callers that do not
+// need Q ignore it).
 template <typename T>
-__device__ void polar_rotation(const T F[3][3], T R[3][3], T (*Q)[3] = nullptr, T smin = T(0),
-                               T smax = T(0)) {
+__device__ void polar_rotation(const T F[3][3], T R[3][3], T Q[3][3], T smin, T smax) {
   T A[3][3], V[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -223,7 +224,7 @@ __device__ void polar_rotation(const T F[3][3], T R[3][3], T (*Q)[3] = nullptr, 
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) R[i][j] = U[i][0] * V[j][0] + U[i][1] * V[j][1] + U[i][2] * V[j][2];
-  if (Q) {
+  {
     T d[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -281,7 +282,7 @@ __global__ void k_local_step(int64_t T, const int32_t* __restrict__ tets, int64_
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) Ff[i][j] = (float)F[i][j];
-    polar_rotation<float>(Ff, Rf, biphasic ? Qf : nullptr, (float)smin, (float)smax);
+    polar_rotation<float>(Ff, Rf, Qf, (float)smin, (float)smax);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -290,7 +291,7 @@ __global__ void k_local_step(int64_t T, const int32_t* __restrict__ tets, int64_
         Q[i][j] = biphasic ? (double)Qf[i][j] : F[i][j];
       }
   } else {
-    polar_rotation<double>(F, R, biphasic ? Q : nullptr, smin, smax);
+    polar_rotation<double>(F, R, Q, smin, smax);
     if (!biphasic) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)

@@ -127,6 +127,14 @@ def test_penalty_solve_matches_oracle(torch_cuda, name):
     ctx.global_solve(dev(g2), u)
     u2_or = sla.cho_solve(sla.cho_factor(H, lower=True), g2.T).T
     assert rel(host(u, (3, -1)), u2_or) <= TOL
+    # the solution written over the right-hand side (u and g the same buffer:
+    # the solves mark u as unpublished only where g has been read), bit for
+    # bit the solve into a separate buffer
+    g3 = rng.normal(size=(3, m))
+    ctx.global_solve(dev(g3), u)
+    ug = dev(g3)
+    ctx.global_solve(ug, ug)
+    assert np.array_equal(host(ug, (3, -1)), host(u, (3, -1)))
 
 
 def test_penalty_incidence_many(torch_cuda):
