@@ -359,13 +359,11 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 #pragma unroll
         for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][r] = (r < mr) ? v[qq] : 0.0;
       }
-      if (t == 0 && (!df_wait(&sflags[j], epoch, err) ||
-                     !df_wait(&flags[(j - 1) * nt + (j - 1)], epoch, err)))
-        s_ok = 0;
+      // the partial sum is usually published well before Linv_{j-1}: take it
+      // (each thread the elements it loaded above) while Linv is awaited
+      if (t == 0 && !df_wait(&sflags[j], epoch, err)) s_ok = 0;
       __syncthreads();
       if (!s_ok) return;
-      mark_unit();
-      stage_tile(buf1, linv_ws + (long)(j - 1) * NB * NB);   // buf1[kk][c] = Linv(c, kk)
       {
         const double* Sb = sbuf + (long)j * NB * NB;
         double v[16];
@@ -374,17 +372,29 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 #pragma unroll
         for (int qq = 0; qq < 16; ++qq) buf0[(t >> 6) + 4 * qq][t & 63] -= v[qq];   // S(r, c)
       }
+      if (t == 0 && !df_wait(&flags[(j - 1) * nt + (j - 1)], epoch, err)) s_ok = 0;
+      __syncthreads();
+      if (!s_ok) return;
+      mark_unit();
+      stage_tile(buf1, linv_ws + (long)(j - 1) * NB * NB);   // buf1[kk][c] = Linv(c, kk)
       __syncthreads();
       Acc l;
       acc_zero(l);
       lds_product(l, buf0, buf1);                  // L = S Linv^T
       __syncthreads();
       acc_to_lds(l, buf0, 1.0);
+      // the tile goes to memory straight from the registers (each lane's
+      // sixteen rows of 16-lane runs), while the LDS copy feeds the product
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int r = acc_row(mb), c = acc_col(nb, qq);
+            if (r < mr) coherent_store(&A[(long)(r0 + r) + (long)(cs + c) * lda], l.c[mb][nb][qq]);
+          }
       __syncthreads();
-      for (int e = t; e < NB * NB; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        if (r < mr) coherent_store(&A[(long)(r0 + r) + (long)(cs + c) * lda], buf0[c][r]);
-      }
       lds_product(acc, buf0, buf0);                // acc += L L^T, while the stores drain
       publish_flag(&flags[j * nt + (j - 1)], epoch);
       // (its transposed copy is written after the tile, off the critical path)
@@ -438,14 +448,21 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
       __syncthreads();
       acc_zero(acc);
       lds_product(acc, buf0, buf1);
+      // stored straight from the registers (the right-hand-side row also runs
+      // over the last, ragged, column block); the LDS copy is for the
+      // transposed copy below
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) {
+            const int r = acc_row(mb), c = acc_col(nb, qq);
+            if (r < mr && c < mc)
+              coherent_store(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai], acc.c[mb][nb][qq]);
+          }
       __syncthreads();
       acc_to_lds(acc, buf0, 1.0);
-      __syncthreads();
-      for (int e = t; e < NB * NB; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        // the right-hand-side row also runs over the last (ragged) column block
-        if (r < mr && c < mc) coherent_store(&Ai[(long)(r0 + r) + (long)(c0 + c) * ldai], buf0[c][r]);
-      }
       publish_flag(&flags[i * nt + j], epoch);
       // transposed copy, read only by the backward solve after this launch:
       // U(c0 + r', r0 + c') = L(r0 + c', c0 + r') with r' = e & 63, c' = e >> 6
