@@ -61,6 +61,11 @@ typedef struct {
   double mu_prime;          /* biphasic material (Sec. 5.3): stiffness of the strain */
   double sigma_min;         /*   limit mu' ||F - Q||^2, Q = F with its singular values */
   double sigma_max;         /*   clamped to [sigma_min, sigma_max]; mu_prime = 0: off */
+  int32_t interior_order;   /* interior factor (Sec. 4.3): 0 = breadth-first levels from
+                               x2, eliminated level by level; 1 = nested dissection,
+                               factored supernode by supernode (multifrontal) */
+  int32_t nd_leaf;          /* nested dissection: largest part not bisected further
+                               (0: 256); ignored for interior_order = 0 */
 } pd_mesh;
 
 typedef struct {
@@ -77,16 +82,22 @@ typedef struct {
  *    (one of the three identical coordinate blocks, Sec. 3.2);
  *  - the partition: x2 = region & !dirichlet, x1 = other free nodes,
  *    E_beta = tets with all four vertices in x2, E_alpha = the rest (Sec. 4.5);
- *  - the interior factor: x1 is ordered by breadth-first distance from x2 and
- *    eliminated level by level (dense FP64 on the GPU);
+ *  - the interior factor (dense FP64 on the GPU): with interior_order = 0, x1
+ *    is ordered by breadth-first distance from x2 and eliminated level by
+ *    level (Z_k = S_k^-1 kept per level); with interior_order = 1, by
+ *    geometric nested dissection (pd_nd_analyse) and factored supernode by
+ *    supernode, keeping X_s = L_ss^-1 and L_Bs per supernode;
  *  - the dense Schur complement S = K22 - K21 K11^-1 K12 (m x m, FP64).
  * Synchronous.  *out receives a context freed by pd_destroy.
  * Errors: PD_ERR_INVALID for out-of-range vertex ids, an empty region or a
- * non-positive rest volume; PD_ERR_NOT_SPD if an interior level block is not
+ * non-positive rest volume, interior_order outside {0, 1} or nd_leaf outside
+ * [0, 8192]; PD_ERR_NOT_SPD if an interior level block or supernode is not
  * positive definite (e.g. an interior component with no Dirichlet node). */
 pd_status pd_schur_build(const pd_mesh *mesh, void *hip_stream, pd_ctx **out);
 
-/* Sizes: m = |x2|, n1 = |x1|, E_beta and E_alpha tet counts, interior levels. */
+/* Sizes: m = |x2|, n1 = |x1|, E_beta and E_alpha tet counts, interior levels
+ * (nested dissection: the height of the supernode tree, the number of
+ * batched steps of each sweep). */
 pd_status pd_query(const pd_ctx *ctx, int64_t *m, int64_t *n1, int64_t *n_beta,
                    int64_t *n_alpha, int64_t *n_levels);
 
@@ -367,6 +378,31 @@ pd_status pd_chol_factor_noalloc(double *A, int64_t lda, int64_t n, int32_t n_wo
  * [0, *ntask) (q < 0 only queries the count) -> PD_ERR_INVALID. */
 pd_status pd_dataflow_task(int64_t n, int32_t rhs, int32_t supplied, int64_t q, int32_t *i,
                            int32_t *j, int32_t *kend, int64_t *ntask);
+
+/* The nested-dissection ordering and symbolic factorization that
+ * pd_schur_build uses for interior_order = 1 (host only, no GPU work;
+ * mesh->interior_order is ignored here).  The interior nodes x1 are bisected
+ * recursively along the longest side of their bounding box of rest positions
+ * at the coordinate change nearest the median; the nodes of one half (the
+ * smaller choice) adjacent to the other half form the separator.  Parts of at
+ * most leaf nodes, and the separators, are the supernodes, numbered so that
+ * every child precedes its parent.
+ * sizes (host [3]) <- n1, ns (supernodes), nb (boundary entries).  The
+ * arrays, each host memory owned by the caller, are filled when non-NULL:
+ *   elim [n1]     node id at each elimination position;
+ *   first [ns+1]  supernode s holds positions first[s] .. first[s+1]-1;
+ *   parent [ns]   the supernode holding the first key of s's boundary (the
+ *                 elimination tree), -1 when that boundary is empty or lies
+ *                 in x2 (a root: its update goes to S);
+ *   bptr [ns+1], bkey [nb]: boundary of s, ascending keys bkey[bptr[s]..
+ *                 bptr[s+1]-1]; a key k < n1 is the elimination position k,
+ *                 k >= n1 the region node k - n1 (region-local order).
+ * The boundary of s is the set of later nodes coupled to s after the
+ * elimination of its subtree: x2 nodes and later x1 nodes adjacent to s, and
+ * the boundaries of its children minus s.  Errors: PD_ERR_INVALID for NULL
+ * mesh arrays or sizes, out-of-range vertex ids or leaf < 1. */
+pd_status pd_nd_analyse(const pd_mesh *mesh, int32_t leaf, int64_t *sizes, int32_t *elim,
+                        int32_t *first, int32_t *parent, int64_t *bptr, int32_t *bkey);
 
 typedef struct pd_mlp pd_mlp;
 

@@ -26,7 +26,8 @@ class pd_mesh(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("n_tets", C.c_int64), ("rest", C.c_void_p),
                 ("tets", C.c_void_p), ("region", C.c_void_p), ("dirichlet", C.c_void_p),
                 ("mu", C.c_double), ("density", C.c_double), ("dt", C.c_double),
-                ("mu_prime", C.c_double), ("sigma_min", C.c_double), ("sigma_max", C.c_double)]
+                ("mu_prime", C.c_double), ("sigma_min", C.c_double), ("sigma_max", C.c_double),
+                ("interior_order", C.c_int32), ("nd_leaf", C.c_int32)]
 
 
 class pd_solve_info(C.Structure):
@@ -70,6 +71,7 @@ _SIGS = {
     "pd_chol_create": [C.c_int64, _P, C.POINTER(_P)],
     "pd_chol_factor": [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32)],
     "pd_chol_destroy": [_P],
+    "pd_nd_analyse": [C.POINTER(pd_mesh), C.c_int32, _P, _P, _P, _P, _P, _P],
     "pd_dataflow_task": [C.c_int64, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
     "pd_chol_factor_noalloc": [_P, C.c_int64, C.c_int64, C.c_int32, _P, C.POINTER(C.c_int32)],
@@ -180,11 +182,41 @@ def _ptr(t, dtype=None, numel=None, name="tensor"):
     return t.data_ptr()
 
 
+def nd_analyse(rest, tets, region, dirichlet, leaf=256):
+    """pd_nd_analyse: nested-dissection ordering and boundary sets of the
+    interior nodes (host only).  Returns a dict with n1, elim [n1], first
+    [ns+1], parent [ns], bptr [ns+1] and bkey [nb] (numpy arrays)."""
+    lib = load_library()
+    rest = np.ascontiguousarray(rest, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    region = np.ascontiguousarray(region, dtype=np.uint8)
+    dirichlet = np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    mesh = pd_mesh(rest.shape[1], tets.shape[1], rest.ctypes.data, tets.ctypes.data,
+                   region.ctypes.data, dirichlet.ctypes.data, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1,
+                   int(leaf))
+    sizes = np.zeros(3, dtype=np.int64)
+    st = lib.pd_nd_analyse(C.byref(mesh), int(leaf), sizes.ctypes.data, None, None, None, None,
+                           None)
+    if st != PD_OK:
+        raise PDError(st, "pd_nd_analyse failed")
+    n1, ns, nb = (int(v) for v in sizes)
+    out = dict(n1=n1, elim=np.zeros(n1, np.int32), first=np.zeros(ns + 1, np.int32),
+               parent=np.zeros(ns, np.int32), bptr=np.zeros(ns + 1, np.int64),
+               bkey=np.zeros(max(nb, 1), np.int32))
+    st = lib.pd_nd_analyse(C.byref(mesh), int(leaf), sizes.ctypes.data, out["elim"].ctypes.data,
+                           out["first"].ctypes.data, out["parent"].ctypes.data,
+                           out["bptr"].ctypes.data, out["bkey"].ctypes.data)
+    if st != PD_OK:
+        raise PDError(st, "pd_nd_analyse failed")
+    out["bkey"] = out["bkey"][:nb]
+    return out
+
+
 class PDContext(_Handle):
     """One built mesh (pd_schur_build) and its per-iteration entry points."""
 
     def __init__(self, rest, tets, region, dirichlet, mu, stream=None, density=0.0, dt=0.0,
-                 mu_prime=0.0, sigma_min=0.0, sigma_max=0.0):
+                 mu_prime=0.0, sigma_min=0.0, sigma_max=0.0, interior="levels", nd_leaf=0):
         import torch
         lib = load_library()
         self._lib = lib
@@ -198,9 +230,12 @@ class PDContext(_Handle):
                 dirichlet.shape != (n,):
             raise ValueError("mesh arrays have inconsistent shapes")
         self._keep = (rest, tets, region, dirichlet)
+        if interior not in ("levels", "nd"):
+            raise ValueError("interior must be 'levels' or 'nd'")
         mesh = pd_mesh(n, T, rest.ctypes.data, tets.ctypes.data, region.ctypes.data,
                        dirichlet.ctypes.data, float(mu), float(density), float(dt),
-                       float(mu_prime), float(sigma_min), float(sigma_max))
+                       float(mu_prime), float(sigma_min), float(sigma_max),
+                       1 if interior == "nd" else 0, int(nd_leaf))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

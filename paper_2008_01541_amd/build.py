@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdschur.so")
 SOURCES = ["dense_f64.hip", "dense_lp.hip", "fem.hip", "sweeps.hip", "mlp.hip", "embed.hip", "solve.hip", "api.cpp", "mlp_api.cpp",
-           "chol_api.cpp"]
+           "chol_api.cpp", "nd.hip", "nd_factor.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

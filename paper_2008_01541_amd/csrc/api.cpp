@@ -13,193 +13,9 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pdschur.h"
-#include "common.h"
+#include "ctx.h"
 
 using namespace pdk;
-
-namespace {
-
-struct DevAlloc {
-  std::vector<void*> ptrs;
-  ~DevAlloc() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-};
-
-}  // namespace
-
-struct pd_ctx {
-  hipStream_t st = nullptr;
-  std::string err;
-  bool broken = false;
-
-  int64_t n = 0, T = 0, m = 0, n1 = 0, nbeta = 0, nalpha = 0;
-  int K = 0;
-  double mu = 0.0;
-
-  std::vector<int32_t> region_ids;   // global ids of x2, ascending
-  std::vector<int64_t> lev_off;      // [K+1] offsets into the interior ordering
-  std::vector<int64_t> lev_mat_off;  // [K] offsets (doubles) of Z_k in levmat
-  std::vector<int64_t> B_ptr_off, B_nnz_off, Bt_ptr_off, Bt_nnz_off, Brows_off, Brows_cnt;
-  int64_t maxw = 0;
-  int64_t maxldw = 0;
-  int ntm = 0;                        // tiles of the m x m system
-  int ldH = 0, ldH32 = 0;             // padded leading dimensions of the work matrices
-  std::vector<int> ldw;               // padded leading dimension of each level block
-
-  DevAlloc mem;
-  // mesh subsets
-  int32_t* d_tets_alpha = nullptr;   // [4][nalpha] global ids
-  double* d_Bm_alpha = nullptr;      // [9][nalpha]
-  double* d_vol_alpha = nullptr;
-  int32_t* d_tets_beta = nullptr;    // [4][nbeta] region-local ids
-  double* d_Bm_beta = nullptr;
-  double* d_vol_beta = nullptr;
-  double* d_fe = nullptr;            // [12][nalpha]: element forces of the full local step
-  double* d_fe_b = nullptr;          // [12][nbeta]: element forces of the region local step
-  int32_t *d_inc_a_ptr = nullptr, *d_inc_a = nullptr;
-  int32_t *d_inc_b_ptr = nullptr, *d_inc_b = nullptr;
-  int32_t* d_region_ids = nullptr;
-  int32_t* d_free_ids = nullptr;      // every free node (x1 and x2)
-  double* d_rest = nullptr;           // rest positions [3][n]
-  int64_t n_free = 0;
-  int32_t* d_lev_nodes = nullptr;    // [n1] global ids in level order
-  double* d_levmat = nullptr;        // Z_k = S_k^-1, full symmetric, per level
-  int32_t *d_Bptr = nullptr, *d_Bcol = nullptr, *d_Btptr = nullptr, *d_Btcol = nullptr;
-  double *d_Bval = nullptr, *d_Btval = nullptr;
-  int32_t* d_Brows = nullptr;
-  int32_t *d_Abptr = nullptr, *d_Abcol = nullptr;
-  double* d_Abval = nullptr;
-  // dense system
-  double* d_S = nullptr;
-  double* d_H = nullptr;
-  double* d_linv = nullptr;
-  double* d_sbuf = nullptr;           // partial sums of the first sub-diagonal tiles (factor)
-  double* d_y = nullptr;               // scratch of the residual products
-  double* d_ys = nullptr;              // forward-solve result (holds the sentinel between solves)
-  double* d_Yt = nullptr;             // 64 x m right-hand-side tile row of the fused solve
-  double* d_res = nullptr;
-  double* d_norms = nullptr;
-  int* d_info = nullptr;
-  int* d_err = nullptr;
-  unsigned long long* d_ticket = nullptr;
-  int* d_tflags = nullptr;            // tile-ready flags of the dataflow Cholesky
-  int* d_cumarks = nullptr;           // per-compute-unit marks of the dataflow Cholesky
-  unsigned* d_tticket = nullptr;
-  int chol_epoch = 0;
-  int n_wg = 512;
-  // low-precision factor for the refined solves
-  float* d_H32 = nullptr;
-  float* d_linv32 = nullptr;
-  double* d_lpb = nullptr;            // workspaces of the float-factor solves (3 m each)
-  double* d_lpy = nullptr;
-  double* d_dvec = nullptr;
-  unsigned long long* d_lp_ticket = nullptr;
-  int lp_prec = -1;                   // precision of the current low-precision factor
-  bool lp_stale = true;
-  int lp_info = -1;                   // its first non-positive pivot (0: none; -1: not read yet)
-  int max_ir = 100;
-  double ir_tol = 1e-8;
-  int ir_fallback = 1;                // refactor in FP64 when the refinement stalls
-  double* d_cgp = nullptr;            // conjugate-gradient vectors (3 m each) and scalars
-  double* d_cgq = nullptr;
-  double* d_cgz = nullptr;
-  double* d_cgs = nullptr;
-  // sweeps
-  double *d_fhat = nullptr, *d_v = nullptr, *d_xs = nullptr, *d_tmp = nullptr;
-  double* d_ext = nullptr;     // warm start: predicted region increment in FP64
-  double dt = 0.0;             // backward-Euler time step (0: quasistatic)
-  double mu_p = 0.0, smin = 0.0, smax = 0.0;   // biphasic material (mu_p = 0: corotated)
-  std::vector<double> h_D;     // inertia diagonal M / dt^2 per node (0 on prescribed nodes)
-  double* d_D = nullptr;
-  const double* d_target = nullptr;  // caller's inertial target x_n + dt v_n
-  bool have_condense = false;
-  double* d_P = nullptr;              // tile parts of a level's (or S's) dense product
-  int* d_gflag = nullptr;             // right-hand side supplied to a running factorization
-  int g_epoch = 0;                    // last value stored to d_gflag
-  bool deferred = false;              // the current factor awaits / holds a supplied RHS
-  bool rhs_supplied = false;          // pd_supply_rhs was called for it
-  bool overlap = false;               // the forward solve may overlap the running factorization
-  hipEvent_t ev_fstart = nullptr;     // factorization epoch advanced (its flags may be polled)
-  hipEvent_t ev_fdone = nullptr;      // factorization finished
-  // penalties
-  int32_t n_pen = 0, pen_cap = 0;
-  int32_t* d_pidx = nullptr;
-  double *d_pw = nullptr, *d_pc = nullptr, *d_pt = nullptr;
-  int32_t* d_pact = nullptr;          // active penalties (c != 0), increasing
-  int32_t* d_pnact = nullptr;         // their count (device)
-  int32_t* d_prow = nullptr;          // incidence of the active slots on region rows: row pointers
-  int32_t* d_pcur = nullptr;          // (m + 1), cursors (m), keys (8 per penalty)
-  int32_t* d_pent = nullptr;
-  bool stale = true;
-
-  // optional per-phase timing with HIP events recorded on the stream
-  bool timing = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<std::pair<int, std::pair<size_t, size_t>>> ev_pairs;   // (phase, (start, end))
-  hipEvent_t next_event() {
-    if (ev_used == ev_pool.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      ev_pool.push_back(e);
-    }
-    return ev_pool[ev_used++];
-  }
-  ~pd_ctx() {
-    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    if (ev_fstart) (void)hipEventDestroy(ev_fstart);
-    if (ev_fdone) (void)hipEventDestroy(ev_fdone);
-  }
-
-  pd_status fail(pd_status s, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    err = buf;
-    if (s == PD_ERR_HIP) broken = true;
-    return s;
-  }
-  template <typename TT>
-  pd_status alloc(TT** p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    if (hipMalloc((void**)p, count * sizeof(TT)) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(PD_ERR_OOM, "device allocation of %zu bytes failed", count * sizeof(TT));
-    }
-    mem.ptrs.push_back((void*)*p);
-    return PD_OK;
-  }
-  template <typename TT>
-  pd_status upload(TT** p, const std::vector<TT>& h) {
-    pd_status s = alloc(p, h.size());
-    if (s != PD_OK) return s;
-    if (!h.empty() && hipMemcpy(*p, h.data(), h.size() * sizeof(TT), hipMemcpyHostToDevice) != hipSuccess)
-      return fail(PD_ERR_HIP, "host-to-device copy failed");
-    return PD_OK;
-  }
-  pd_status check(const char* what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(PD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-    return PD_OK;
-  }
-};
-
-#define CK(expr)                             \
-  do {                                       \
-    pd_status _s = (expr);                   \
-    if (_s != PD_OK) return _s;              \
-  } while (0)
-
-#define HIPCK(ctx, expr)                                                                 \
-  do {                                                                                   \
-    hipError_t _e = (expr);                                                              \
-    if (_e != hipSuccess) return (ctx)->fail(PD_ERR_HIP, "%s: %s", #expr, hipGetErrorString(_e)); \
-  } while (0)
 
 namespace {
 
@@ -226,15 +42,7 @@ struct PhaseTimer {
   }
 };
 
-// Gather plan: dst[dst_off[i]] = sum of vals[src[e]] for e in [ptr[i], ptr[i+1]).
-struct Plan {
-  std::vector<int64_t> ptr{0}, src, dst;
-  void add_group(const int64_t* s, int64_t cnt, int64_t d) {
-    for (int64_t i = 0; i < cnt; ++i) src.push_back(s[i]);
-    ptr.push_back((int64_t)src.size());
-    dst.push_back(d);
-  }
-};
+}  // namespace
 
 pd_status run_plan(pd_ctx* c, const Plan& P, const double* vals, double* dst) {
   if (P.dst.empty()) return PD_OK;
@@ -259,6 +67,8 @@ void free_now(pd_ctx* c, void* p) {
   if (it != c->mem.ptrs.end()) c->mem.ptrs.erase(it);
   (void)hipFree(p);
 }
+
+namespace {
 
 // In-place lower Cholesky of the n x n matrix A (leading dimension lda, a
 // multiple of 16 so tiles start on 128-byte lines); tile inverses to d_linv,
@@ -304,6 +114,11 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   c->mu_p = M->mu_prime;
   c->smin = M->sigma_min;
   c->smax = M->sigma_max;
+  if (M->interior_order != 0 && M->interior_order != 1)
+    return c->fail(PD_ERR_INVALID, "interior_order must be 0 (levels) or 1 (nested dissection)");
+  if (M->nd_leaf < 0 || M->nd_leaf > 8192)
+    return c->fail(PD_ERR_INVALID, "nd_leaf must lie in [0, 8192] (0: default)");
+  const bool use_nd = M->interior_order == 1;
 
   // ---- partition (Sec. 4.2): x2 = region & free, x1 = other free nodes
   std::vector<int8_t> cls(n);   // 0 dirichlet, 1 interior (x1), 2 region (x2)
@@ -326,26 +141,16 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   c->nalpha = (int64_t)alpha.size();
   c->nbeta = (int64_t)beta.size();
 
-  // ---- free-node adjacency and breadth-first levels of x1 from x2
-  std::vector<int64_t> adj_ptr(n + 1, 0);
-  {
-    std::vector<std::pair<int32_t, int32_t>> pairs;
-    pairs.reserve((size_t)T * 12);
-    for (int64_t e = 0; e < T; ++e)
-      for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) {
-          if (a == b) continue;
-          const int32_t u = tets[a * T + e], v = tets[b * T + e];
-          if (cls[u] != 0 && cls[v] != 0) pairs.emplace_back(u, v);
-        }
-    std::sort(pairs.begin(), pairs.end());
-    pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
-    std::vector<int32_t> adj(pairs.size());
-    for (size_t i = 0; i < pairs.size(); ++i) {
-      adj_ptr[pairs[i].first + 1]++;
-      adj[i] = pairs[i].second;
-    }
-    for (int64_t i = 0; i < n; ++i) adj_ptr[i + 1] += adj_ptr[i];
+  // ---- free-node adjacency; interior ordering: breadth-first levels of x1
+  // from x2, or nested dissection
+  std::vector<int64_t> adj_ptr;
+  std::vector<int32_t> adj;
+  free_adjacency(n, T, tets, cls, adj_ptr, adj);
+  if (use_nd) {
+    CK(nd_prepare(c, M->rest, cls, rloc, adj_ptr, adj, M->nd_leaf > 0 ? M->nd_leaf : 256));
+    c->K = 0;
+    c->lev_off.assign(1, c->n1);
+  } else {
     std::vector<int32_t> dist(n, -1), frontier, next;
     for (int32_t r : c->region_ids) {
       for (int64_t k = adj_ptr[r]; k < adj_ptr[r + 1]; ++k) {
@@ -397,7 +202,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   const int64_t m = c->m;
   // level id and local index of every free node; region = level K
   std::vector<int32_t> lvl(n, -1), loc(n, -1);
-  {
+  if (!use_nd) {
     std::vector<int32_t> h(c->n1);
     HIPCK(c, hipMemcpy(h.data(), c->d_lev_nodes, c->n1 * sizeof(int32_t), hipMemcpyDeviceToHost));
     for (int k = 0; k < K; ++k)
@@ -470,7 +275,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&c->d_S, m * m));
   HIPCK(c, hipMemsetAsync(c->d_levmat, 0, lev_mat_total * sizeof(double), c->st));
   HIPCK(c, hipMemsetAsync(c->d_S, 0, m * m * sizeof(double), c->st));
-  {
+  if (!use_nd) {
     // node-major bucketing of contributions
     std::vector<int64_t> cnt(n + 1, 0);
     for (int64_t e = 0; e < T; ++e)
@@ -716,6 +521,7 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
     if (info != 0)
       return c->fail(PD_ERR_NOT_SPD, "interior level block not positive definite (pivot %d)", info);
   }
+  if (use_nd) CK(nd_factor(c, tets, T, cls, rloc, d_Ke));
 
   // ---- per-iteration data: E_alpha / E_beta tets, incidence lists, buffers
   {
@@ -853,7 +659,7 @@ pd_status pd_query(const pd_ctx* c, int64_t* m, int64_t* n1, int64_t* n_beta, in
   if (n1) *n1 = c->n1;
   if (n_beta) *n_beta = c->nbeta;
   if (n_alpha) *n_alpha = c->nalpha;
-  if (n_levels) *n_levels = c->K;
+  if (n_levels) *n_levels = c->nd ? nd_height(c) : c->K;
   return PD_OK;
 }
 
@@ -910,6 +716,11 @@ pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
   if (c->broken) return PD_ERR_HIP;
   const int64_t n1 = c->n1, m = c->m;
   PhaseTimer tm(c, PD_PHASE_CONDENSE);
+  if (c->nd) {
+    nd_condense(c, f, y2);
+    c->have_condense = true;
+    return c->check("pd_condense_rhs");
+  }
   gather_rows3(n1, c->d_lev_nodes, f, c->n, c->d_fhat, n1, c->st);
   gather_rows3(m, c->d_region_ids, f, c->n, y2, m, c->st);
   for (int k = 0; k < c->K; ++k) {
@@ -933,10 +744,14 @@ pd_status pd_condense_rhs(pd_ctx* c, const double* f, double* y2) {
 }
 
 // x1 += v - A11^-1 A12 delta2 level by level (v = A11^-1 f1 from the last
-// condensation, kept per level in d_v), then x2 += delta2.
-static void backsub_levels(pd_ctx* c, const double* delta2, double* x) {
+// condensation, kept per level in d_v; zero_w: v = 0), then x2 += delta2.
+// With the nested-dissection factor the interior part runs its sweep instead.
+static void backsub_levels(pd_ctx* c, const double* delta2, double* x, bool zero_w) {
   const int64_t n1 = c->n1, m = c->m;
-  if (n1 > 0) {
+  if (c->nd) {
+    nd_backsub(c, delta2, x, zero_w);
+  } else if (n1 > 0) {
+    if (zero_w) zero_f64(3 * n1, c->d_v, c->st);
     // level k: tmp = B_k^T x_{k+1} (x_K = delta2), then xs_k = v_k - Z_k tmp
     for (int k = c->K - 1; k >= 0; --k) {
       const int64_t off = c->lev_off[k], w = c->lev_off[k + 1] - off;
@@ -960,7 +775,7 @@ pd_status pd_backsub(pd_ctx* c, const double* delta2, double* x) {
   if (c->broken) return PD_ERR_HIP;
   if (!c->have_condense) return c->fail(PD_ERR_STATE, "pd_backsub needs a preceding pd_condense_rhs");
   PhaseTimer tm(c, PD_PHASE_BACKSUB);
-  backsub_levels(c, delta2, x);
+  backsub_levels(c, delta2, x, false);
   return c->check("pd_backsub");
 }
 
@@ -971,9 +786,8 @@ pd_status pd_warmstart_apply(pd_ctx* c, const float* d2, double scale, const dou
   if (c->broken) return PD_ERR_HIP;
   if (!c->d_ext) CK(c->alloc(&c->d_ext, 3 * std::max<int64_t>(1, c->m)));
   scale_f32_to_f64(3 * c->m, d2, scale, x2_prev1, x2_prev2, c->d_ext, c->st);
-  // the elastic response of the interior with f1 = 0: v = 0 on every level
-  zero_f64(3 * c->n1, c->d_v, c->st);
-  backsub_levels(c, c->d_ext, x);
+  // the elastic response of the interior with f1 = 0
+  backsub_levels(c, c->d_ext, x, true);
   c->have_condense = false;           // v no longer holds a condensation
   return c->check("pd_warmstart_apply");
 }

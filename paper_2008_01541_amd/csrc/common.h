@@ -181,4 +181,42 @@ void axpy3_sum(int m, const double* a, const double* b, const double* c, double*
                hipStream_t st);
 void inner_update(int m, const double* u, double* x2, double* d2, hipStream_t st);
 
+// C(r, c) = beta C(r, c) + alpha sum_{k < K} A(r, k) B(c, k) for r < m, c < nc
+// (column-major; beta = 0: C is not read).  lower: C is square and only its
+// tiles on or below the diagonal are formed.  blower: B is lower triangular
+// and only its tiles on or below the diagonal are read (X = L^-1 from
+// trtri_from_factor, whose tiles above the diagonal are never written).
+void gemm_nt(const double* A, long lda, const double* B, long ldb, double* C, long ldc, int m,
+             int nc, int K, double alpha, double beta, int lower, int blower, hipStream_t st);
+
+// ---- nested-dissection interior factor (nd.hip) ----------------------------
+
+// One work item of the supernodal sweeps: the matrix block at moff (leading
+// dimension ldm, rows x cols), the chunk that starts at row (gemv_n) or
+// column (gemv_t) row0, and the offsets of its input and output vectors.
+struct NdItem {
+  int64_t moff;
+  int32_t ldm, rows, cols, row0, xoff, yoff;
+};
+// Adds the lower entries (r >= c) of the b x b update matrix U of a child
+// into its parent's front: i = map[r], j = map[c]; j < ns: into the front's
+// first ns columns P (F_ss entries mirrored to the upper triangle), else into
+// the trailing update block Uo at (i - ns, j - ns) (mirrored when mirror).
+void nd_extend_add(const double* U, long ldu, int b, const int32_t* map, int ns, double* P,
+                   long ldp, double* Uo, long lduo, int mirror, hipStream_t st);
+// dst[v][t or t - n1] = f[v][node_of[t]] - sum_{e in [ptr[t], ptr[t+1])} contrib[v][slot[e]]
+// for the cnt targets t of tlist (t < n1: elimination position; t >= n1: region index t - n1).
+void nd_gather_rhs(int cnt, const int32_t* tlist, int n1, const int32_t* node_of, const double* f,
+                   long ldf, const int32_t* ptr, const int32_t* slot, const double* contrib,
+                   long ldc, double* dst, long ldd, hipStream_t st);
+// y = M x per item (64 rows each; lower: M lower triangular), three columns.
+void nd_gemv_n(int nitems, const NdItem* items, const double* M, const double* x, long ldx,
+               double* y, long ldy, int lower, hipStream_t st);
+// y = M^T (xa - xb) per item (4 columns each; xb may be null; lower: M lower triangular).
+void nd_gemv_t(int nitems, const NdItem* items, const double* M, const double* xa, const double* xb,
+               long ldx, double* y, long ldy, int lower, hipStream_t st);
+// zb[v][e] = key[e] < n1 ? z[v][key[e]] : d2[v][key[e] - n1] for the cnt entries of elist.
+void nd_gather_zb(int cnt, const int32_t* elist, const int32_t* key, int n1, const double* z,
+                  long ldz, const double* d2, long ldd2, double* zb, long ldzb, hipStream_t st);
+
 }  // namespace pdk

@@ -643,6 +643,53 @@ void lauum_full(const double* X, int ldx, int n, double* Z, int ldz, hipStream_t
   k_lauum_full<<<nt * (nt + 1) / 2, 256, 0, st>>>(X, ldx, n, Z, ldz);
 }
 
+// C = beta C + alpha A B^T, one 64 x 64 tile of C per workgroup (tiles on or
+// below the diagonal only when lower; B lower triangular when blower, so the
+// sum for a column tile j stops at the end of B's diagonal tile j).
+__global__ __launch_bounds__(256) void k_gemm_nt(const double* A, long lda, const double* B,
+                                                 long ldb, double* C, long ldc, int m, int nc,
+                                                 int K, double alpha, double beta, int lower,
+                                                 int blower) {
+  __shared__ double As[KC][LDS_LD];
+  __shared__ double Bs[KC][LDS_LD];
+  int i, j;
+  if (lower) {
+    tri_index(blockIdx.x, i, j);
+  } else {
+    const int mt = (m + NB - 1) / NB;
+    i = blockIdx.x % mt;
+    j = blockIdx.x / mt;
+  }
+  const int r0 = i * NB, c0 = j * NB;
+  const int mr = min(NB, m - r0), mc = min(NB, nc - c0);
+  const int kend = blower ? min(K, c0 + NB) : K;
+  Acc acc;
+  acc_zero(acc);
+  gemm_acc<false, false>(acc, As, Bs, A, lda, r0, mr, 0, B, ldb, c0, mc, 0, kend);
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = acc_row(mb), c = acc_col(nb, q);
+        if (r < mr && c < mc) {
+          double* p = C + (long)(r0 + r) + (long)(c0 + c) * ldc;
+          const double v = alpha * acc.c[mb][nb][q];
+          *p = beta == 0.0 ? v : beta * *p + v;
+        }
+      }
+}
+
+void gemm_nt(const double* A, long lda, const double* B, long ldb, double* C, long ldc, int m,
+             int nc, int K, double alpha, double beta, int lower, int blower, hipStream_t st) {
+  if (m <= 0 || nc <= 0) return;
+  const long mt = (m + NB - 1) / NB, ntc = (nc + NB - 1) / NB;
+  const long cnt = lower ? mt * (mt + 1) / 2 : mt * ntc;
+  k_gemm_nt<<<(unsigned)cnt, 256, 0, st>>>(A, lda, B, ldb, C, ldc, m, nc, K, alpha, beta, lower,
+                                           blower);
+}
+
 __global__ __launch_bounds__(256) void k_copy_lower_tiles(const double* S, int lds, double* H,
                                                           int ldh, int n) {
   int i, j;

@@ -15,11 +15,13 @@ class Alg1Runner:
     obstacles and conforming proxies."""
 
     def __init__(self, rest, tets, region, dirichlet, mu, proxies_global, k_pen, device="cuda",
-                 density=0.0, dt=0.0, mu_prime=0.0, sigma_min=0.0, sigma_max=0.0):
+                 density=0.0, dt=0.0, mu_prime=0.0, sigma_min=0.0, sigma_max=0.0,
+                 interior="levels", nd_leaf=0):
         import torch
         self.torch = torch
         self.ctx = PDContext(rest, tets, region, dirichlet, mu, density=density, dt=dt,
-                             mu_prime=mu_prime, sigma_min=sigma_min, sigma_max=sigma_max)
+                             mu_prime=mu_prime, sigma_min=sigma_min, sigma_max=sigma_max,
+                             interior=interior, nd_leaf=nd_leaf)
         c = self.ctx
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)

@@ -155,6 +155,32 @@ def scene_small(nx, ny, nz, h=1.0, region_top_layers=2, seed=7, n_spheres=2,
                        spheres=sph, outer_iters=3, inner_iters=1, steps=3)
 
 
+def scene_irregular(nx=12, ny=10, nz=9, h=1.0, jitter=0.1, region_radius=None, seed=9,
+                    k_pen=1.0e6):
+    """Irregular stand-in for an anatomical mesh: a Kuhn grid whose node
+    positions are jittered by U[-jitter, jitter] h per coordinate (seeded),
+    bottom layer pinned, and a collision-prone region shaped as a cap, the
+    nodes within region_radius (default 0.35 min(nx, ny) h) of a seeded point
+    of the top face, so the breadth-first levels of the interior from the
+    region have uneven widths.  Proxies = top-face nodes of the region; one
+    sphere above the cap centre."""
+    rng = np.random.default_rng(seed)
+    rest, tets = kuhn_grid(nx, ny, nz, h)
+    rest = rest + rng.uniform(-jitter, jitter, size=rest.shape) * h
+    dirichlet = layer_mask(nx, ny, nz, [0])
+    if region_radius is None:
+        region_radius = 0.35 * min(nx, ny) * h
+    c = np.array([rng.uniform(0.3, 0.7) * nx * h, rng.uniform(0.3, 0.7) * ny * h, nz * h])
+    region = np.linalg.norm(rest - c[:, None], axis=0) <= region_radius
+    top = layer_mask(nx, ny, nz, [nz])
+    proxies = np.nonzero(top & region)[0].astype(np.int64)
+    sph = SphereSchedule(base_xy=c[:2, None].copy(), radii=np.array([0.3 * region_radius]),
+                         top_z=nz * h, depth_rate=np.array([0.05 * h]))
+    return Scene(name=f"irregular{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, h=h, mu=lame_mu(),
+                 rest=rest, tets=tets, dirichlet=dirichlet, region=region, proxies=proxies,
+                 k_pen=k_pen, spheres=sph, outer_iters=3, inner_iters=1, steps=3, seed=seed)
+
+
 def random_penalty_set(rng, n_proxy, m_region, lo=0.01, hi=0.05):
     """Solver-benchmark penalty set: a random subset of proxies (between lo*m
     and hi*m of them) with target offsets drawn U[0, 0.5] downward along z.

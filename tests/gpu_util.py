@@ -10,9 +10,9 @@ def oracle_model(scene, build_schur=True):
                        build_schur=build_schur)
 
 
-def gpu_context(scene):
+def gpu_context(scene, **kw):
     from paper_2008_01541_amd import PDContext
-    return PDContext(scene.rest, scene.tets, scene.region, scene.dirichlet, scene.mu)
+    return PDContext(scene.rest, scene.tets, scene.region, scene.dirichlet, scene.mu, **kw)
 
 
 def dev(a, dtype=None):

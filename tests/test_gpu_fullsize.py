@@ -187,3 +187,72 @@ def test_slab_alg1_iteration_matches_oracle(slab, slab_alg1_reference, pipelined
     scale = np.abs(x_or - x0).max()
     assert scale > 0.05
     assert np.abs(xg - x_or).max() <= 1e-9 * scale
+
+
+@pytest.fixture(scope="module")
+def slab_nd():
+    """The same slab with the nested-dissection interior factor."""
+    import torch
+    assert torch.cuda.is_available()
+    sc = P.scene_slab56()
+    ctx = gpu_context(sc, interior="nd")
+    S = torch.empty(ctx.m * ctx.m, dtype=torch.float64, device="cuda")
+    ctx.get_schur(S)
+    return sc, ctx, S
+
+
+def test_slab_nd_schur_probes_and_closed_form(slab_nd, oracle_slab):
+    import torch
+    from oracle import schur as osch
+    sc, ctx, S = slab_nd
+    assert (ctx.m, ctx.n1) == (6498, 97470) and 1 < ctx.n_levels <= 16
+    om = oracle_slab
+    Sm = S.reshape(ctx.m, ctx.m)
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        v = rng.normal(size=ctx.m)
+        ref = osch.schur_apply(om.lu11, om.A12, om.A21, om.A22, v)
+        got = host(Sm @ torch.tensor(v, device="cuda"))
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+    z = sc.rest[2, ctx.region_ids]
+    vd = torch.tensor(z / 32.0, device="cuda")
+    assert float(vd @ (Sm @ vd)) == pytest.approx(2 * sc.mu * 98.0, rel=1e-10)
+
+
+def test_slab_nd_condense_and_backsub_match_oracle(slab_nd, oracle_slab):
+    import torch
+    from oracle import schur as osch
+    sc, ctx, S = slab_nd
+    om = oracle_slab
+    rng = np.random.default_rng(4)
+    f = rng.normal(size=(3, sc.n_nodes))
+    y2 = torch.empty(3 * ctx.m, dtype=torch.float64, device="cuda")
+    ctx.condense_rhs(dev(f), y2)
+    w1, y2_or = osch.forward_sub(om.lu11, om.A21, f[:, om.i1].T, f[:, om.i2].T)
+    assert np.abs(host(y2, (3, -1)) - y2_or.T).max() <= 1e-10 * np.abs(y2_or).max()
+    d2 = rng.normal(size=(3, ctx.m))
+    xd = dev(np.zeros((3, sc.n_nodes)))
+    ctx.backsub(dev(d2), xd)
+    x1_or = osch.back_sub(om.lu11, om.A12, f[:, om.i1].T, d2.T).T
+    got = host(xd, (3, -1))
+    assert np.abs(got[:, om.i1] - x1_or).max() <= 1e-10 * np.abs(x1_or).max()
+    assert np.array_equal(got[:, om.i2], d2)
+
+
+def test_slab_nd_alg1_iteration_matches_oracle(slab_alg1_reference):
+    """One Alg. 1 outer iteration at full size with the nested-dissection
+    interior factor, element-wise against the oracle's full sparse solve."""
+    import torch
+    from paper_2008_01541_amd.driver import Alg1Runner
+    sc, x0, cen, rad, x_or, n_active = slab_alg1_reference
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen,
+                     interior="nd")
+    run.set_positions(x0)
+    run.set_spheres(cen, rad)
+    run.outer_iteration(n_inner=1)
+    torch.cuda.synchronize()
+    assert int((run.c > 0).sum()) == n_active
+    xg = run.positions()
+    run.close()
+    scale = np.abs(x_or - x0).max()
+    assert np.abs(xg - x_or).max() <= 1e-9 * scale
