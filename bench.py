@@ -342,7 +342,7 @@ def bench_slit(args):
     torch.cuda.set_stream(stream)           # stream must not serialise with it
     t0 = time.perf_counter()
     run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, np.zeros(0, np.int64),
-                     sc.k_pen)
+                     sc.k_pen, interior=args.interior, nd_leaf=args.nd_leaf)
     n_proxies = int(sc.pairs.shape[1])
     if args.contact == "levelset":
         # rest-pose level sets of the two lips, proxies embedded in each lip
@@ -414,7 +414,8 @@ def bench_slit(args):
         "config": {"workload": "slit64x64x40_kuhn", "tets": int(sc.n_tets),
                    "nodes": int(sc.n_nodes), "region_nodes": int(m), "contact": args.contact,
                    "proxies": n_proxies,
-                   "interior_levels": ctx.n_levels, "k_pen": sc.k_pen},
+                   "interior": args.interior, "interior_levels": ctx.n_levels,
+                   "k_pen": sc.k_pen},
         "eager_pd_iters_per_s": eager_value, "pipelined_pd_iters_per_s": pipe_value,
         "pipelined_factor_workgroups": None if args.no_pipeline else args.factor_wg,
         "active_penalties_last": act,
@@ -473,6 +474,10 @@ def main():
     ap.add_argument("--local-step-column", action="store_true",
                     help="time only the E_alpha local step on a 28 x 28 x 768 column "
                          "(3.6M tets, working set above the 256 MB Infinity Cache)")
+    ap.add_argument("--interior", default="levels", choices=["levels", "nd"],
+                    help="interior factor: breadth-first levels or nested dissection")
+    ap.add_argument("--nd-leaf", type=int, default=0,
+                    help="nested dissection: largest part not bisected further (0: default)")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip timing replays of a HIP graph of one outer iteration")
     args = ap.parse_args()
@@ -510,7 +515,7 @@ def main():
     if args.dynamics:
         extra.update(density=DYNAMICS["density"], dt=DYNAMICS["dt"])
     run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, sc.proxies, sc.k_pen,
-                     **extra)
+                     interior=args.interior, nd_leaf=args.nd_leaf, **extra)
     n_proxies = int(sc.proxies.size)
     if args.proxies == "embedded":
         # four seeded proxies per top-face cell, embedded in the region tets
@@ -624,8 +629,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "slab56x56x32_kuhn", "tets": int(sc.n_tets),
-                   "nodes": int(sc.n_nodes), "region_nodes": int(m), "interior_levels": ctx.n_levels,
-                   "spheres": 16, "k_pen": sc.k_pen, "proxies": args.proxies,
+                   "nodes": int(sc.n_nodes), "region_nodes": int(m), "interior": args.interior,
+                   "interior_levels": ctx.n_levels, "spheres": 16, "k_pen": sc.k_pen, "proxies": args.proxies,
                    "n_proxies": n_proxies, "material": args.material,
                    **({"biphasic": BIPHASIC} if args.material == "biphasic" else {}),
                    "dynamics": DYNAMICS if args.dynamics else "quasistatic", "outer_per_step": 1,

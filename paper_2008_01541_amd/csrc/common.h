@@ -191,12 +191,13 @@ void gemm_nt(const double* A, long lda, const double* B, long ldb, double* C, lo
 
 // ---- nested-dissection interior factor (nd.hip) ----------------------------
 
-// One work item of the supernodal sweeps: the matrix block at moff (leading
-// dimension ldm, rows x cols), the chunk that starts at row (gemv_n) or
-// column (gemv_t) row0, and the offsets of its input and output vectors.
+// One work item of the supernodal sweeps: four columns, from col0, of the
+// matrix block at moff (leading dimension ldm, rows x cols); rows below split
+// are dotted with one vector (from xoff), the rest with another (from x2off,
+// subtracted); the results go to yoff + column.
 struct NdItem {
   int64_t moff;
-  int32_t ldm, rows, cols, row0, xoff, yoff;
+  int32_t ldm, rows, cols, col0, xoff, yoff, split, x2off;
 };
 // Adds the lower entries (r >= c) of the b x b update matrix U of a child
 // into its parent's front: i = map[r], j = map[c]; j < ns: into the front's
@@ -209,12 +210,12 @@ void nd_extend_add(const double* U, long ldu, int b, const int32_t* map, int ns,
 void nd_gather_rhs(int cnt, const int32_t* tlist, int n1, const int32_t* node_of, const double* f,
                    long ldf, const int32_t* ptr, const int32_t* slot, const double* contrib,
                    long ldc, double* dst, long ldd, hipStream_t st);
-// y = M x per item (64 rows each; lower: M lower triangular), three columns.
-void nd_gemv_n(int nitems, const NdItem* items, const double* M, const double* x, long ldx,
-               double* y, long ldy, int lower, hipStream_t st);
-// y = M^T (xa - xb) per item (4 columns each; xb may be null; lower: M lower triangular).
-void nd_gemv_t(int nitems, const NdItem* items, const double* M, const double* xa, const double* xb,
-               long ldx, double* y, long ldy, int lower, hipStream_t st);
+// y = M^T [xa; -xb] per item (see NdItem), three right-hand sides.
+void nd_gemv(int nitems, const NdItem* items, const double* M, const double* xa, long ldxa,
+             const double* xb, long ldxb, double* y, long ldy, hipStream_t st);
+// dst (cols x rows) = src^T (src rows x cols), column-major.
+void nd_transpose(const double* src, long lds, int rows, int cols, double* dst, long ldd,
+                  hipStream_t st);
 // zb[v][e] = key[e] < n1 ? z[v][key[e]] : d2[v][key[e] - n1] for the cnt entries of elist.
 void nd_gather_zb(int cnt, const int32_t* elist, const int32_t* key, int n1, const double* z,
                   long ldz, const double* d2, long ldd2, double* zb, long ldzb, hipStream_t st);

@@ -245,7 +245,8 @@ pd_status nd_prepare(pd_ctx* c, const double* rest, const std::vector<int8_t>& c
 pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector<int8_t>& cls,
                     const std::vector<int32_t>& rloc, const double* d_Ke);
 int nd_height(const pd_ctx* c);
-// nd_condense: y2 = f2 - A21 A11^-1 f1 (keeps z = L11^-1 f1 for nd_backsub);
+// nd_condense: y2 = f2 - A21 A11^-1 f1 (keeps the gathered right-hand sides
+// r_s of the supernodes for nd_backsub);
 // nd_backsub: x1 += A11^-1 (f1 - A12 delta2) on the interior nodes of x
 // (zero_w: with f1 = 0); the region part is left to the caller.
 void nd_condense(pd_ctx* c, const double* f, double* y2);

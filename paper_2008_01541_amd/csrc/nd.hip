@@ -1,9 +1,12 @@
 // Kernels of the nested-dissection (multifrontal) interior factor: extend-add
 // of a child's update matrix into its parent's front, and the batched
 // matrix-vector products of the two sweeps through the supernodes (three
-// right-hand sides).  Supernode s holds X_s = L_ss^-1 (n_s x n_s, lower) and
-// L_Bs (b_s x n_s, the rows of its boundary), column-major.  Sums run in a
-// fixed order, so the sweeps are bitwise reproducible.
+// right-hand sides).  Supernode s keeps Z_s = A_ss^-1 (n_s x n_s, symmetric)
+// stacked above W_s = F_Bs Z_s (b_s x n_s), and W_s^T, all column-major, so
+// that every product of a sweep sums down contiguous columns: the forward
+// sweep reads W_s^T (contributions W_s r_s to the boundary), the backward
+// sweep the stacked block (x_s = Z_s r_s - W_s^T zb_s).  Sums run in a fixed
+// order, so the sweeps are bitwise reproducible.
 #include "common.h"
 
 namespace pdk {
@@ -42,71 +45,51 @@ void nd_extend_add(const double* U, long ldu, int b, const int32_t* map, int ns,
 
 // dst[v][o] = f[v][node_of[t]] - sum_{e in [ptr[t], ptr[t+1])} contrib[v][slot[e]]
 // for the cnt targets t listed in tlist: t < n1 is an elimination position
-// (o = t), t >= n1 the region node t - n1 (o = t - n1).  The contributions
-// of a target are subtracted in the order of its slot list.
-__global__ void k_nd_gather_rhs(int cnt, const int32_t* __restrict__ tlist, int n1,
-                                const int32_t* __restrict__ node_of, const double* __restrict__ f,
-                                long ldf, const int32_t* __restrict__ ptr,
-                                const int32_t* __restrict__ slot, const double* __restrict__ contrib,
-                                long ldc, double* __restrict__ dst, long ldd) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  const int t = tlist[i];
-  const long node = node_of[t];
-  const int out = t < n1 ? t : t - n1;
+// (o = t), t >= n1 the region node t - n1 (o = t - n1).  Eight lanes share a
+// target: lane k adds slots k, k + 8, ..., then the eight partial sums are
+// combined by a fixed butterfly, so loads of different slots are in flight
+// together and the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_nd_gather_rhs(int cnt, const int32_t* __restrict__ tlist,
+                                                       int n1, const int32_t* __restrict__ node_of,
+                                                       const double* __restrict__ f, long ldf,
+                                                       const int32_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ slot,
+                                                       const double* __restrict__ contrib,
+                                                       long ldc, double* __restrict__ dst,
+                                                       long ldd) {
+  const int g = (int)((blockIdx.x * (long)blockDim.x + threadIdx.x) >> 3);
+  const int k = threadIdx.x & 7;
+  const bool on = g < cnt;
+  const int t = on ? tlist[g] : 0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (on) {
+    const int e1 = ptr[t + 1];
+    for (int e = ptr[t] + k; e < e1; e += 8) {
+      const long q = slot[e];
+      s0 += contrib[q];
+      s1 += contrib[ldc + q];
+      s2 += contrib[2 * ldc + q];
+    }
+  }
 #pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    double s = f[v * ldf + node];
-    for (int e = ptr[t]; e < ptr[t + 1]; ++e) s -= contrib[v * ldc + slot[e]];
-    dst[v * ldd + out] = s;
+  for (int o = 4; o > 0; o >>= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    s1 += __shfl_xor(s1, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+  }
+  if (on && k < 3) {
+    const long node = node_of[t];
+    const int out = t < n1 ? t : t - n1;
+    const double sv = k == 0 ? s0 : (k == 1 ? s1 : s2);
+    dst[k * ldd + out] = f[k * ldf + node] - sv;
   }
 }
 void nd_gather_rhs(int cnt, const int32_t* tlist, int n1, const int32_t* node_of, const double* f,
                    long ldf, const int32_t* ptr, const int32_t* slot, const double* contrib,
                    long ldc, double* dst, long ldd, hipStream_t st) {
   if (cnt > 0)
-    k_nd_gather_rhs<<<(cnt + 255) / 256, 256, 0, st>>>(cnt, tlist, n1, node_of, f, ldf, ptr, slot,
-                                                       contrib, ldc, dst, ldd);
-}
-
-// y[yoff + row0 + r] = sum_c M(row0 + r, c) x[xoff + c] (three columns of x
-// and y, strides ldx / ldy), one workgroup per item of 64 rows; lower: M is
-// lower triangular (columns c <= row).  Thread (r, g) adds columns g, g + 4,
-// ...; the four partial sums are added in a fixed order through LDS.
-__global__ __launch_bounds__(256) void k_nd_gemv_n(const NdItem* __restrict__ items,
-                                                   const double* __restrict__ Mb,
-                                                   const double* __restrict__ x, long ldx,
-                                                   double* __restrict__ y, long ldy, int lower) {
-  __shared__ double part[4][3][64];
-  const NdItem it = items[blockIdx.x];
-  if (it.rows <= 0) return;
-  const int t = threadIdx.x, r = t & 63, g = t >> 6;
-  const int row = it.row0 + r;
-  const int rr = min(row, it.rows - 1);
-  const int cend = lower ? min(it.cols, it.row0 + 64) : it.cols;
-  const double* M = Mb + it.moff + rr;
-  const double* xv = x + it.xoff;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int c = g; c < cend; c += 4) {
-    const double m = (lower && c > rr) ? 0.0 : M[(long)c * it.ldm];
-    s0 += m * xv[c];
-    s1 += m * xv[ldx + c];
-    s2 += m * xv[2 * ldx + c];
-  }
-  part[g][0][r] = s0;
-  part[g][1][r] = s1;
-  part[g][2][r] = s2;
-  __syncthreads();
-  if (t < 192) {
-    const int v = t >> 6, q = t & 63;
-    if (it.row0 + q < it.rows)
-      y[v * ldy + it.yoff + it.row0 + q] =
-          (part[0][v][q] + part[1][v][q]) + (part[2][v][q] + part[3][v][q]);
-  }
-}
-void nd_gemv_n(int nitems, const NdItem* items, const double* M, const double* x, long ldx,
-               double* y, long ldy, int lower, hipStream_t st) {
-  if (nitems > 0) k_nd_gemv_n<<<nitems, 256, 0, st>>>(items, M, x, ldx, y, ldy, lower);
+    k_nd_gather_rhs<<<(cnt + 31) / 32, 256, 0, st>>>(cnt, tlist, n1, node_of, f, ldf, ptr, slot,
+                                                     contrib, ldc, dst, ldd);
 }
 
 __device__ inline double nd_wave_sum(double v) {
@@ -115,34 +98,58 @@ __device__ inline double nd_wave_sum(double v) {
   return v;
 }
 
-// y[yoff + c] = sum_r M(r, c) (xa - xb)[xoff + r] for the four columns
-// c = col0 + w of an item (one wave each; xb may be null); lower: rows r >= c
-// only.  Each wave walks its column in 64-row steps and adds up across lanes.
-__global__ __launch_bounds__(256) void k_nd_gemv_t(const NdItem* __restrict__ items,
-                                                   const double* __restrict__ Mb,
-                                                   const double* __restrict__ xa,
-                                                   const double* __restrict__ xb, long ldx,
-                                                   double* __restrict__ y, long ldy, int lower) {
+// s += sign * sum_{r < n} M[r] x[r] (three columns of x, stride ldx) over
+// this lane's rows lane, lane + 64, ...: four rows per step, loads guarded
+// rather than branched around, so that a short column takes one step with
+// all its loads in flight.
+template <int SIGN>
+__device__ __forceinline__ void nd_dot(const double* __restrict__ M, const double* __restrict__ x,
+                                       long ldx, int n, double& s0, double& s1, double& s2) {
+  const int lane = threadIdx.x & 63;
+  for (int r = lane; r < n; r += 256) {
+    double m[4], v0[4], v1[4], v2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = r + 64 * u;
+      const bool ok = q < n;
+      m[u] = ok ? M[q] : 0.0;
+      v0[u] = ok ? x[q] : 0.0;
+      v1[u] = ok ? x[ldx + q] : 0.0;
+      v2[u] = ok ? x[2 * ldx + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (SIGN > 0) {
+        s0 += m[u] * v0[u];
+        s1 += m[u] * v1[u];
+        s2 += m[u] * v2[u];
+      } else {
+        s0 -= m[u] * v0[u];
+        s1 -= m[u] * v1[u];
+        s2 -= m[u] * v2[u];
+      }
+    }
+  }
+}
+
+// y[yoff + c] = sum_{r < split} M(r, c) xa[xoff + r] - sum_{split <= r < rows}
+// M(r, c) xb[x2off + r - split] for the four columns c = col0 + w of an item
+// (one wave each, three right-hand sides); the lanes' sums are added across
+// the wave at the end (fixed order).
+__global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ items,
+                                                 const double* __restrict__ Mb,
+                                                 const double* __restrict__ xa, long ldxa,
+                                                 const double* __restrict__ xb, long ldxb,
+                                                 double* __restrict__ y, long ldy) {
   const NdItem it = items[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = it.row0 + w;                  // row0 holds the first column of the item
+  const int c = it.col0 + w;
   if (c >= it.cols) return;
   const double* M = Mb + it.moff + (long)c * it.ldm;
-  const double* a = xa + it.xoff;
-  const double* b = xb ? xb + it.xoff : nullptr;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int r = (lower ? c : 0) + lane; r < it.rows; r += 64) {
-    const double m = M[r];
-    double v0 = a[r], v1 = a[ldx + r], v2 = a[2 * ldx + r];
-    if (b) {
-      v0 -= b[r];
-      v1 -= b[ldx + r];
-      v2 -= b[2 * ldx + r];
-    }
-    s0 += m * v0;
-    s1 += m * v1;
-    s2 += m * v2;
-  }
+  nd_dot<1>(M, xa + it.xoff, ldxa, it.split, s0, s1, s2);
+  if (it.rows > it.split)
+    nd_dot<-1>(M + it.split, xb + it.x2off, ldxb, it.rows - it.split, s0, s1, s2);
   s0 = nd_wave_sum(s0);
   s1 = nd_wave_sum(s1);
   s2 = nd_wave_sum(s2);
@@ -152,9 +159,30 @@ __global__ __launch_bounds__(256) void k_nd_gemv_t(const NdItem* __restrict__ it
     y[2 * ldy + it.yoff + c] = s2;
   }
 }
-void nd_gemv_t(int nitems, const NdItem* items, const double* M, const double* xa, const double* xb,
-               long ldx, double* y, long ldy, int lower, hipStream_t st) {
-  if (nitems > 0) k_nd_gemv_t<<<nitems, 256, 0, st>>>(items, M, xa, xb, ldx, y, ldy, lower);
+void nd_gemv(int nitems, const NdItem* items, const double* M, const double* xa, long ldxa,
+             const double* xb, long ldxb, double* y, long ldy, hipStream_t st) {
+  if (nitems > 0) k_nd_gemv<<<nitems, 256, 0, st>>>(items, M, xa, ldxa, xb, ldxb, y, ldy);
+}
+
+// dst (cols x rows, leading dimension ldd) = transpose of src (rows x cols,
+// leading dimension lds), through a 32 x 32 LDS tile.
+__global__ __launch_bounds__(256) void k_nd_transpose(const double* __restrict__ src, long lds,
+                                                      int rows, int cols,
+                                                      double* __restrict__ dst, long ldd) {
+  __shared__ double T[32][33];
+  const int tr = blockIdx.x * 32, tc = blockIdx.y * 32;
+  const int x = threadIdx.x & 31, yy = threadIdx.x >> 5;
+  for (int k = yy; k < 32; k += 8)
+    if (tr + x < rows && tc + k < cols) T[k][x] = src[(long)(tr + x) + (long)(tc + k) * lds];
+  __syncthreads();
+  for (int k = yy; k < 32; k += 8)
+    if (tc + x < cols && tr + k < rows) dst[(long)(tc + x) + (long)(tr + k) * ldd] = T[x][k];
+}
+void nd_transpose(const double* src, long lds, int rows, int cols, double* dst, long ldd,
+                  hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return;
+  dim3 grid((rows + 31) / 32, (cols + 31) / 32);
+  k_nd_transpose<<<grid, 256, 0, st>>>(src, lds, rows, cols, dst, ldd);
 }
 
 // zb[v][e] = (t < n1) ? z[v][t] : d2[v][t - n1] with t = key[e], for the

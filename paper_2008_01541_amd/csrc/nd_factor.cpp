@@ -5,13 +5,16 @@
 // with vertex separators taken from the graph of the mesh); every leaf part
 // and every separator is a supernode, eliminated children first.  Supernode s
 // (n_s nodes, boundary B_s of b_s later nodes) is factored as a dense front
-//   [F_ss  .  ]   L_ss = chol(F_ss), X_s = L_ss^-1, LB_s = F_Bs X_s^T,
-//   [F_Bs F_BB]   U_s = F_BB - LB_s LB_s^T  (added into the parent's front),
-// and the roots' updates land in S = K22 - K21 K11^-1 K12.  X_s and LB_s stay
+//   [F_ss  .  ]   L_ss = chol(F_ss), Z_s = L_ss^-T L_ss^-1 = F_ss^-1,
+//   [F_Bs F_BB]   W_s = F_Bs Z_s, U_s = F_BB - W_s F_Bs^T (into the parent),
+// and the roots' updates land in S = K22 - K21 K11^-1 K12.  Z_s and W_s stay
 // on the device for the two sweeps of every outer iteration, which run one
-// tree height at a time as batched matrix-vector products (no triangular
-// solves): the forward sweep forms z = L11^-1 f1 and y2 = f2 - L21 z, the
-// backward sweep x1 = L11^-T (z - L21^T delta2).
+// tree height at a time, each height one batch of matrix-vector products
+// (no triangular solves): the forward sweep gathers r_s = f_s minus the
+// contributions of its descendants and hands W_s r_s to its boundary (the
+// region's share gives y2 = f2 - A21 A11^-1 f1); the backward sweep forms
+// x_s = Z_s r_s - W_s^T zb_s from the solution zb_s already known on the
+// boundary (delta2 on the region), which is A11^-1 (f1 - A12 delta2) on s.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -239,11 +242,12 @@ pd_status nd_analyse(int64_t n, const double* rest, const std::vector<int8_t>& c
 struct NdFactor {
   NdSymbolic sym;
   int64_t nb = 0;
-  std::vector<int64_t> xoff, lboff;       // X_s, LB_s in fac (doubles)
-  std::vector<int32_t> ldx, ldlb;
+  // in fac (doubles): [Z_s; W_s] ((n_s + b_s) x n_s, leading dimension
+  // ldzw) and W_s^T (n_s x b_s, leading dimension ldwt)
+  std::vector<int64_t> zwoff, wtoff;
+  std::vector<int32_t> ldzw, ldwt;
   struct Level {                          // one tree height: ranges in tlist / items / elist
-    int32_t t_off, t_cnt, xn_off, xn_cnt, ln_off, ln_cnt, lt_off, lt_cnt, xt_off, xt_cnt, e_off,
-        e_cnt;
+    int32_t t_off, t_cnt, fw_off, fw_cnt, bw_off, bw_cnt, e_off, e_cnt;
   };
   std::vector<Level> levels;
   int32_t treg_off = 0;                   // region targets in tlist
@@ -252,8 +256,7 @@ struct NdFactor {
   int32_t *d_node_of = nullptr, *d_cptr = nullptr, *d_cslot = nullptr, *d_bkey = nullptr;
   int32_t *d_tlist = nullptr, *d_elist = nullptr;
   NdItem* d_items = nullptr;
-  double *d_r = nullptr, *d_z = nullptr, *d_x1 = nullptr, *d_tmp = nullptr;
-  double *d_contrib = nullptr, *d_zb = nullptr;
+  double *d_r = nullptr, *d_x1 = nullptr, *d_contrib = nullptr, *d_zb = nullptr;
 };
 
 void nd_free(NdFactor* f) { delete f; }   // device memory belongs to the context
@@ -306,13 +309,14 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
   };
 
   // layouts: fronts P_s (ld pad16(n_s + b_s), n_s columns), updates U_s
-  // (pad16(b_s) x b_s), and the kept blocks X_s (pad16(n_s) x n_s) and LB_s
-  // (pad16(b_s) x n_s); all offsets multiples of 16 doubles
+  // (pad16(b_s) x b_s), the kept blocks [Z_s; W_s] (ld pad16(n_s + b_s), n_s
+  // columns) and W_s^T (pad16(n_s) x b_s), and the work blocks of the inverse
+  // (pad16(n_s) x n_s); all offsets multiples of 16 doubles
   std::vector<int64_t> poff(ns), ldp(ns), uoff(ns), ldu(ns);
-  F->xoff.assign(ns, 0);
-  F->lboff.assign(ns, 0);
-  F->ldx.assign(ns, 0);
-  F->ldlb.assign(ns, 0);
+  F->zwoff.assign(ns, 0);
+  F->wtoff.assign(ns, 0);
+  F->ldzw.assign(ns, 0);
+  F->ldwt.assign(ns, 0);
   int64_t ptot = 0, utot = 0, mmax = 0;
   F->fac_doubles = 0;
   for (int64_t s = 0; s < ns; ++s) {
@@ -323,20 +327,21 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
     ldu[s] = pad16(b);
     uoff[s] = utot;
     utot += ldu[s] * b;
-    F->ldx[s] = (int32_t)pad16(a);
-    F->ldlb[s] = (int32_t)pad16(b);
-    F->xoff[s] = F->fac_doubles;
-    F->fac_doubles += F->ldx[s] * a;
-    F->lboff[s] = F->fac_doubles;
-    F->fac_doubles += (int64_t)F->ldlb[s] * a;
-    mmax = std::max(mmax, (int64_t)F->ldx[s] * a);
+    F->ldzw[s] = (int32_t)pad16(a + b);
+    F->ldwt[s] = (int32_t)pad16(a);
+    F->zwoff[s] = F->fac_doubles;
+    F->fac_doubles += (int64_t)F->ldzw[s] * a;
+    F->wtoff[s] = F->fac_doubles;
+    F->fac_doubles += (int64_t)F->ldwt[s] * b;
+    mmax = std::max(mmax, pad16(a) * a);
   }
-  double *d_P = nullptr, *d_U = nullptr, *d_M = nullptr;
+  double *d_P = nullptr, *d_U = nullptr, *d_M = nullptr, *d_X = nullptr;
   int32_t* d_fmap = nullptr;
   CK(c->alloc(&F->d_fac, F->fac_doubles));
   CK(c->alloc(&d_P, ptot));
   CK(c->alloc(&d_U, utot));
   CK(c->alloc(&d_M, mmax));
+  CK(c->alloc(&d_X, mmax));
   HIPCK(c, hipMemsetAsync(d_P, 0, std::max<int64_t>(ptot, 1) * sizeof(double), c->st));
   HIPCK(c, hipMemsetAsync(d_U, 0, std::max<int64_t>(utot, 1) * sizeof(double), c->st));
   HIPCK(c, hipMemsetAsync(F->d_fac, 0, std::max<int64_t>(F->fac_doubles, 1) * sizeof(double),
@@ -429,21 +434,25 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
   std::vector<std::vector<int32_t>> children(ns);
   for (int64_t s = 0; s < ns; ++s)
     if (S.parent[s] >= 0) children[S.parent[s]].push_back((int32_t)s);
+  // per supernode: L_ss = chol(F_ss), X = L_ss^-1, Z = X^T X = A_ss^-1,
+  // W = F_Bs Z, U -= W F_Bs^T (= L_Bs L_Bs^T), W^T for the forward sweep
   for (int64_t s = 0; s < ns; ++s) {
     const int a = (int)nsz(s), b = (int)bsz(s);
+    const int ldx = (int)pad16(a), lzw = F->ldzw[s];
     double* P = d_P + poff[s];
     double* U = d_U + uoff[s];
-    double* X = F->d_fac + F->xoff[s];
-    double* LB = F->d_fac + F->lboff[s];
+    double* ZW = F->d_fac + F->zwoff[s];
     for (int32_t ch : children[s])
       nd_extend_add(d_U + uoff[ch], ldu[ch], (int)bsz(ch), d_fmap + S.bptr[ch], a, P, ldp[s], U,
                     ldu[s], 0, c->st);
     potrf_dataflow(P, (int)ldp[s], a, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info,
                    c->d_err, c->n_wg, nullptr, c->st, nullptr, 0, c->d_cumarks, nullptr);
-    trtri_from_factor(P, (int)ldp[s], a, c->d_linv, d_M, X, F->ldx[s], c->st);
+    trtri_from_factor(P, (int)ldp[s], a, c->d_linv, d_M, d_X, ldx, c->st);
+    lauum_full(d_X, ldx, a, ZW, lzw, c->st);
     if (b > 0) {
-      gemm_nt(P + a, ldp[s], X, F->ldx[s], LB, F->ldlb[s], b, a, a, 1.0, 0.0, 0, 1, c->st);
-      gemm_nt(LB, F->ldlb[s], LB, F->ldlb[s], U, ldu[s], b, b, a, -1.0, 1.0, 1, 0, c->st);
+      gemm_nt(P + a, ldp[s], ZW, lzw, ZW + a, lzw, b, a, a, 1.0, 0.0, 0, 0, c->st);
+      gemm_nt(ZW + a, lzw, P + a, ldp[s], U, ldu[s], b, b, a, -1.0, 1.0, 1, 0, c->st);
+      nd_transpose(ZW + a, lzw, b, a, F->d_fac + F->wtoff[s], F->ldwt[s], c->st);
       if (S.parent[s] < 0)
         nd_extend_add(U, ldu[s], b, d_fmap + S.bptr[s], 0, nullptr, 0, c->d_S, m, 1, c->st);
     }
@@ -453,6 +462,7 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
   free_now(c, d_P);
   free_now(c, d_U);
   free_now(c, d_M);
+  free_now(c, d_X);
   free_now(c, d_fmap);
   {
     int info = 0;
@@ -490,27 +500,24 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
       }
       L.t_cnt = (int32_t)tlist.size() - L.t_off;
       L.e_cnt = (int32_t)elist.size() - L.e_off;
-      // X_s r_s (64 rows per item), LB_s z_s, LB_s^T zb_s and X_s^T (z_s - t_s) (4 columns per item)
-      auto emit = [&](int kind, int32_t& off, int32_t& cnt) {
-        off = (int32_t)items.size();
-        for (int32_t s : at[h]) {
-          const int32_t a = (int32_t)nsz(s), b = (int32_t)bsz(s);
-          const int32_t f0 = S.first[s], b0 = (int32_t)S.bptr[s];
-          if (kind == 0)
-            for (int32_t r = 0; r < a; r += 64) items.push_back({F->xoff[s], F->ldx[s], a, a, r, f0, f0});
-          else if (kind == 1)
-            for (int32_t r = 0; r < b; r += 64) items.push_back({F->lboff[s], F->ldlb[s], b, a, r, f0, b0});
-          else if (kind == 2)
-            for (int32_t q = 0; q < a; q += 4) items.push_back({F->lboff[s], F->ldlb[s], b, a, q, b0, f0});
-          else
-            for (int32_t q = 0; q < a; q += 4) items.push_back({F->xoff[s], F->ldx[s], a, a, q, f0, f0});
-        }
-        cnt = (int32_t)items.size() - off;
-      };
-      emit(0, L.xn_off, L.xn_cnt);
-      emit(1, L.ln_off, L.ln_cnt);
-      emit(2, L.lt_off, L.lt_cnt);
-      emit(3, L.xt_off, L.xt_cnt);
+      // four columns per item: the forward sweep's W_s r_s (columns of
+      // W_s^T), the backward sweep's Z_s r_s - W_s^T zb_s (columns of [Z_s; W_s])
+      L.fw_off = (int32_t)items.size();
+      for (int32_t s : at[h]) {
+        const int32_t a = (int32_t)nsz(s), b = (int32_t)bsz(s);
+        const int32_t f0 = S.first[s], b0 = (int32_t)S.bptr[s];
+        for (int32_t q = 0; q < b; q += 4)
+          items.push_back({F->wtoff[s], F->ldwt[s], a, b, q, f0, b0, a, 0});
+      }
+      L.fw_cnt = (int32_t)items.size() - L.fw_off;
+      L.bw_off = (int32_t)items.size();
+      for (int32_t s : at[h]) {
+        const int32_t a = (int32_t)nsz(s), b = (int32_t)bsz(s);
+        const int32_t f0 = S.first[s], b0 = (int32_t)S.bptr[s];
+        for (int32_t q = 0; q < a; q += 4)
+          items.push_back({F->zwoff[s], F->ldzw[s], a + b, a, q, f0, f0, a, b0});
+      }
+      L.bw_cnt = (int32_t)items.size() - L.bw_off;
     }
     F->treg_off = (int32_t)tlist.size();
     for (int64_t r = 0; r < m; ++r) tlist.push_back((int32_t)(n1 + r));
@@ -525,9 +532,7 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
     CK(c->upload(&F->d_items, items));
     const int64_t v1 = 3 * std::max<int64_t>(n1, 1), vb = 3 * std::max<int64_t>(nb, 1);
     CK(c->alloc(&F->d_r, v1));
-    CK(c->alloc(&F->d_z, v1));
     CK(c->alloc(&F->d_x1, v1));
-    CK(c->alloc(&F->d_tmp, v1));
     CK(c->alloc(&F->d_contrib, vb));
     CK(c->alloc(&F->d_zb, vb));
   }
@@ -540,11 +545,12 @@ void nd_condense(pd_ctx* c, const double* f, double* y2) {
   const int n1 = F->sym.n1, m = F->sym.m;
   const long nb = (long)F->nb;
   for (const NdFactor::Level& L : F->levels) {
-    // r = f1 - (contributions of the descendants), z = X r, contributions LB z
+    // r = f1 - (contributions of the descendants), then the contributions
+    // W r of this height to its boundary
     nd_gather_rhs(L.t_cnt, F->d_tlist + L.t_off, n1, F->d_node_of, f, c->n, F->d_cptr,
                   F->d_cslot, F->d_contrib, nb, F->d_r, n1, c->st);
-    nd_gemv_n(L.xn_cnt, F->d_items + L.xn_off, F->d_fac, F->d_r, n1, F->d_z, n1, 1, c->st);
-    nd_gemv_n(L.ln_cnt, F->d_items + L.ln_off, F->d_fac, F->d_z, n1, F->d_contrib, nb, 0, c->st);
+    nd_gemv(L.fw_cnt, F->d_items + L.fw_off, F->d_fac, F->d_r, n1, nullptr, 0, F->d_contrib, nb,
+            c->st);
   }
   nd_gather_rhs(m, F->d_tlist + F->treg_off, n1, F->d_node_of, f, c->n, F->d_cptr, F->d_cslot,
                 F->d_contrib, nb, y2, m, c->st);
@@ -555,17 +561,15 @@ void nd_backsub(pd_ctx* c, const double* delta2, double* x, bool zero_w) {
   const int n1 = F->sym.n1, m = F->sym.m;
   const long nb = (long)F->nb;
   if (n1 == 0) return;
-  if (zero_w) zero_f64(3L * n1, F->d_z, c->st);
+  if (zero_w) zero_f64(3L * n1, F->d_r, c->st);
   for (size_t h = F->levels.size(); h-- > 0;) {
     const NdFactor::Level& L = F->levels[h];
     // zb = solution at the boundary (ancestors, or delta2 on the region),
-    // t = LB^T zb, x1 = X^T (z - t)
+    // x1 = Z r - W^T zb
     nd_gather_zb(L.e_cnt, F->d_elist + L.e_off, F->d_bkey, n1, F->d_x1, n1, delta2, m, F->d_zb,
                  nb, c->st);
-    nd_gemv_t(L.lt_cnt, F->d_items + L.lt_off, F->d_fac, F->d_zb, nullptr, nb, F->d_tmp, n1, 0,
-              c->st);
-    nd_gemv_t(L.xt_cnt, F->d_items + L.xt_off, F->d_fac, F->d_z, F->d_tmp, n1, F->d_x1, n1, 1,
-              c->st);
+    nd_gemv(L.bw_cnt, F->d_items + L.bw_off, F->d_fac, F->d_r, n1, F->d_zb, nb, F->d_x1, n1,
+            c->st);
   }
   scatter_add_rows3(n1, F->d_node_of, F->d_x1, n1, x, c->n, c->st);
 }
