@@ -474,7 +474,7 @@ def main():
     ap.add_argument("--local-step-column", action="store_true",
                     help="time only the E_alpha local step on a 28 x 28 x 768 column "
                          "(3.6M tets, working set above the 256 MB Infinity Cache)")
-    ap.add_argument("--interior", default="levels", choices=["levels", "nd"],
+    ap.add_argument("--interior", default="nd", choices=["levels", "nd"],
                     help="interior factor: breadth-first levels or nested dissection")
     ap.add_argument("--nd-leaf", type=int, default=0,
                     help="nested dissection: largest part not bisected further (0: default)")
@@ -497,7 +497,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.factor_wg <= 0:
-        args.factor_wg = 448 if args.workload == "slit64" else 384
+        args.factor_wg = 448 if args.workload == "slit64" else (512 if args.interior == "nd" else 384)
     if args.dense_chol > 0:
         return bench_dense_chol(args)
     if args.local_step_column:

@@ -80,7 +80,7 @@ def test_nd_warmstart_apply_matches_oracle(torch_cuda, name):
     om = oracle_model(sc, build_schur=False)
     ctx = gpu_context(sc, interior="nd")
     rng = np.random.default_rng(8)
-    # a condensation first, so the sweep's kept z is not zero before the call
+    # a condensation first, so the right-hand sides the sweeps keep are not zero
     ctx.condense_rhs(dev(rng.normal(size=(3, sc.n_nodes))),
                      torch_cuda.empty(3 * ctx.m, dtype=torch_cuda.float64, device="cuda"))
     d32 = rng.normal(size=(3, ctx.m)).astype(np.float32)
@@ -142,3 +142,79 @@ def test_nd_rejects_bad_options(torch_cuda):
     with pytest.raises(PDError):
         PDContext(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, interior="nd",
                   nd_leaf=10000)
+
+
+def test_nd_slit_alg1_matches_oracle(torch_cuda):
+    """Self-contact of a slit (region in the middle of the mesh, interior on
+    both sides, both faces prescribed) with the nested-dissection factor:
+    Alg. 1 step by step against the oracle, on one stream and pipelined."""
+    from paper_2008_01541_amd.driver import Alg1Runner
+    from oracle import collision as ocol
+    torch = torch_cuda
+    sc = P.scene_slit(10, 10, 8, 4, 6, seed=5, steps=6)
+    om = opd.PDModel(sc.rest, sc.tets, sc.mu, sc.dirichlet, sc.region)
+    pl = sc.pairs_local()
+    det = lambda x2: ocol.detect_pairs(x2, pl, sc.k_pen)
+    run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, np.zeros(0, np.int64),
+                     sc.k_pen, interior="nd", nd_leaf=20)
+    run.use_pairs(sc.pairs)
+    x_or = sc.rest.copy()
+    worst, active = 0.0, 0
+    for step in range(1, 5):
+        x_or = sc.prescribed(x_or, step)
+        run.set_positions(sc.prescribed(run.positions(), step))
+        for _ in range(2):
+            run.outer_iteration(n_inner=2)
+            x_or = opd.alg1_outer_iteration(om, x_or, det, n_inner=2)
+            active = max(active, int((host(run.c) > 0).sum()))
+            worst = max(worst, np.abs(run.positions() - x_or).max() /
+                        np.abs(x_or - sc.rest).max())
+    run.close()
+    assert active > 0 and worst <= 1e-9
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        run = Alg1Runner(sc.rest, sc.tets, sc.region, sc.dirichlet, sc.mu, np.zeros(0, np.int64),
+                         sc.k_pen, interior="nd")
+        run.use_pairs(sc.pairs)
+        steps = [1 + k // 2 for k in range(8)]
+        bottom = torch.tensor(sc.bottom, device="cuda").long()
+        poses = [torch.tensor(sc.prescribed(sc.rest, st)[:, sc.bottom], device="cuda")
+                 for st in steps]
+
+        def before_local(k):
+            run.x.view(3, -1)[:, bottom] = poses[k]
+
+        run.run_pipelined(8, n_workgroups=8, factor_stream=torch.cuda.Stream(),
+                          before_local=before_local)
+    torch.cuda.synchronize()
+    x_or = sc.rest.copy()
+    for st in steps:
+        x_or = sc.prescribed(x_or, st)
+        x_or = opd.alg1_outer_iteration(om, x_or, det, n_inner=1)
+    assert np.abs(run.positions() - x_or).max() / np.abs(x_or - sc.rest).max() <= 1e-9
+    run.close()
+
+
+def test_nd_build_and_sweeps_bitwise_reproducible(torch_cuda):
+    """Two builds of one mesh give the same S bit for bit, and their sweeps the
+    same y2 and x (fixed summation orders throughout)."""
+    sc = SCENES["irregular_large"]()
+    rng = np.random.default_rng(17)
+    f = dev(rng.normal(size=(3, sc.n_nodes)))
+    d2 = None
+    outs = []
+    for _ in range(2):
+        ctx = gpu_context(sc, interior="nd", nd_leaf=64)
+        S = torch_cuda.empty(ctx.m * ctx.m, dtype=torch_cuda.float64, device="cuda")
+        ctx.get_schur(S)
+        y2 = torch_cuda.empty(3 * ctx.m, dtype=torch_cuda.float64, device="cuda")
+        ctx.condense_rhs(f, y2)
+        if d2 is None:
+            d2 = dev(rng.normal(size=(3, ctx.m)))
+        x = torch_cuda.zeros(3 * sc.n_nodes, dtype=torch_cuda.float64, device="cuda")
+        ctx.backsub(d2, x)
+        torch_cuda.cuda.synchronize()
+        outs.append((S.clone(), y2.clone(), x.clone()))
+        ctx.close()
+    for a, b in zip(*outs):
+        assert torch_cuda.equal(a, b)
