@@ -191,13 +191,13 @@ void gemm_nt(const double* A, long lda, const double* B, long ldb, double* C, lo
 
 // ---- nested-dissection interior factor (nd.hip) ----------------------------
 
-// One work item of the supernodal sweeps: four columns, from col0, of the
-// matrix block at moff (leading dimension ldm, rows x cols); rows below split
-// are dotted with one vector (from xoff), the rest with another (from x2off,
-// subtracted); the results go to yoff + column.
+// One work item of the supernodal sweeps: 4 cpw columns (cpw = 1 or 4 per
+// wave), from col0, of the matrix block at moff (leading dimension ldm,
+// rows x cols); rows below split are dotted with one vector (from xoff), the
+// rest with another (from x2off, subtracted); the results go to yoff + column.
 struct NdItem {
   int64_t moff;
-  int32_t ldm, rows, cols, col0, xoff, yoff, split, x2off;
+  int32_t ldm, rows, cols, col0, xoff, yoff, split, x2off, cpw;
 };
 // Adds the lower entries (r >= c) of the b x b update matrix U of a child
 // into its parent's front: i = map[r], j = map[c]; j < ns: into the front's

@@ -132,10 +132,42 @@ __device__ __forceinline__ void nd_dot(const double* __restrict__ M, const doubl
   }
 }
 
+// The same for four columns M, M + ldm, M + 2 ldm, M + 3 ldm at once (nc of
+// them valid): the vector entries are loaded once for the four, two rows
+// per lane and step.
+template <int SIGN>
+__device__ __forceinline__ void nd_dot4(const double* __restrict__ M, long ldm, int nc,
+                                        const double* __restrict__ x, long ldx, int n,
+                                        double (&s)[4][3]) {
+  const int lane = threadIdx.x & 63;
+  for (int r = lane; r < n; r += 128) {
+    double m[2][4], v[2][3];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = r + 64 * u;
+      const bool ok = q < n;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[u][k] = ok ? x[k * ldx + q] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) m[u][c] = (ok && c < nc) ? M[c * ldm + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (SIGN > 0) s[c][k] += m[u][c] * v[u][k];
+          else s[c][k] -= m[u][c] * v[u][k];
+        }
+  }
+}
+
 // y[yoff + c] = sum_{r < split} M(r, c) xa[xoff + r] - sum_{split <= r < rows}
-// M(r, c) xb[x2off + r - split] for the four columns c = col0 + w of an item
-// (one wave each, three right-hand sides); the lanes' sums are added across
-// the wave at the end (fixed order).
+// M(r, c) xb[x2off + r - split] for the columns of an item (three right-hand
+// sides): cpw = 1, one column per wave (columns col0 + w); cpw = 4, four per
+// wave (col0 + 4 w .. + 3), for short columns, whose loads are then shared.
+// The lanes' sums are added across the wave at the end (fixed order).
 __global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ items,
                                                  const double* __restrict__ Mb,
                                                  const double* __restrict__ xa, long ldxa,
@@ -143,20 +175,48 @@ __global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ item
                                                  double* __restrict__ y, long ldy) {
   const NdItem it = items[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int c = it.col0 + w;
-  if (c >= it.cols) return;
-  const double* M = Mb + it.moff + (long)c * it.ldm;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  nd_dot<1>(M, xa + it.xoff, ldxa, it.split, s0, s1, s2);
+  if (it.cpw == 1) {
+    const int c = it.col0 + w;
+    if (c >= it.cols) return;
+    const double* M = Mb + it.moff + (long)c * it.ldm;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    nd_dot<1>(M, xa + it.xoff, ldxa, it.split, s0, s1, s2);
+    if (it.rows > it.split)
+      nd_dot<-1>(M + it.split, xb + it.x2off, ldxb, it.rows - it.split, s0, s1, s2);
+    s0 = nd_wave_sum(s0);
+    s1 = nd_wave_sum(s1);
+    s2 = nd_wave_sum(s2);
+    if (lane == 0) {
+      y[it.yoff + c] = s0;
+      y[ldy + it.yoff + c] = s1;
+      y[2 * ldy + it.yoff + c] = s2;
+    }
+    return;
+  }
+  const int c0 = it.col0 + 4 * w;
+  if (c0 >= it.cols) return;
+  const int nc = min(4, it.cols - c0);
+  const double* M = Mb + it.moff + (long)c0 * it.ldm;
+  double s[4][3];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[c][k] = 0.0;
+  nd_dot4<1>(M, it.ldm, nc, xa + it.xoff, ldxa, it.split, s);
   if (it.rows > it.split)
-    nd_dot<-1>(M + it.split, xb + it.x2off, ldxb, it.rows - it.split, s0, s1, s2);
-  s0 = nd_wave_sum(s0);
-  s1 = nd_wave_sum(s1);
-  s2 = nd_wave_sum(s2);
+    nd_dot4<-1>(M + it.split, it.ldm, nc, xb + it.x2off, ldxb, it.rows - it.split, s);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s[c][k] = nd_wave_sum(s[c][k]);
   if (lane == 0) {
-    y[it.yoff + c] = s0;
-    y[ldy + it.yoff + c] = s1;
-    y[2 * ldy + it.yoff + c] = s2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c < nc) {
+        y[it.yoff + c0 + c] = s[c][0];
+        y[ldy + it.yoff + c0 + c] = s[c][1];
+        y[2 * ldy + it.yoff + c0 + c] = s[c][2];
+      }
   }
 }
 void nd_gemv(int nitems, const NdItem* items, const double* M, const double* xa, long ldxa,
