@@ -276,28 +276,19 @@ pd_status pd_set_refinement(pd_ctx *ctx, int32_t max_steps, double tol, int32_t 
  * pd_use_stream).  n_workgroups > 0 caps the persistent workgroups of the
  * factorization (default 2 per compute unit; fewer leave room for kernels of
  * the other stream); <= 0 keeps the default.
- * supply_rhs = 0: a following pd_global_solve(PD_FP64) runs both triangular
- * solves.  supply_rhs = 1: the forward substitution is fused into the
- * factorization for a right-hand side handed over while it runs with
- * pd_supply_rhs, which must be enqueued on another stream before anything
- * waits for the factorization (otherwise its waits time out and the
- * factorization reports PD_ERR_HIP); the following pd_global_solve then only
- * runs the backward substitution, for that right-hand side (its g argument
- * is not read).  supply_rhs = 2: the following pd_global_solve(PD_FP64) may
- * be enqueued on another stream without waiting for the factorization: its
+ * overlap_forward = 0: a following pd_global_solve(PD_FP64) runs both
+ * triangular solves after the factorization.  overlap_forward = 1: the
+ * following pd_global_solve(PD_FP64) may be enqueued on another stream
+ * without waiting for the factorization (after this call returns): its
  * forward substitution starts at once and follows the factorization's tile
  * flags row block by row block, and its backward substitution waits for the
  * factorization's end (both through events the library records); nothing
- * else may use the context's factor in between.  Other values:
- * PD_ERR_INVALID.  A no-op when the factor is current.  Non-positive pivots
- * are reported by a later pd_global_solve with info. */
-pd_status pd_factor(pd_ctx *ctx, int32_t n_workgroups, int32_t supply_rhs);
-
-/* Hands the right-hand side g (dev [3][m]) to a factorization started with
- * pd_factor(..., supply_rhs != 0); a no-op otherwise.  Enqueued on the
- * context's current stream (pd_use_stream), which must not wait for the
- * factorization before this call. */
-pd_status pd_supply_rhs(pd_ctx *ctx, const double *g);
+ * else may use the context's factor in between.  The factorization itself
+ * never waits for work of another stream (streams may share a hardware
+ * queue, which runs in order).  Other values: PD_ERR_INVALID.  A no-op when
+ * the factor is current.  Non-positive pivots are reported by a later
+ * pd_global_solve with info. */
+pd_status pd_factor(pd_ctx *ctx, int32_t n_workgroups, int32_t overlap_forward);
 
 /* Inner update (Alg. 1 steps 4.6-4.7): x2 += u2, delta2 += u2 and
  * ft -= Sigma_alpha u2 with Sigma_alpha = S - A22^(beta).  All dev [3][m]. */
@@ -369,15 +360,13 @@ pd_status pd_chol_factor_noalloc(double *A, int64_t lda, int64_t n, int32_t n_wo
  * factorization of H = S + P in pd_global_solve / pd_factor), for checking
  * its index ranges on the host (no GPU work; the kernels decode their
  * tickets with the same code).  For order n (tiles of 64, nt = ceil(n/64)),
- * rhs = 1 when the three right-hand sides ride along as an extra tile row,
- * supplied = 1 when that row is given during the factorization (its tasks
- * then come after all tiles): *ntask receives the number of tasks, and for
- * 0 <= q < *ntask the tile (*i, *j) of ticket q (*i == nt: the right-hand-side
- * row) and *kend, the number of 64-column steps the task accumulates.
- * n < 1, rhs or supplied not 0/1, supplied without rhs, or q outside
- * [0, *ntask) (q < 0 only queries the count) -> PD_ERR_INVALID. */
-pd_status pd_dataflow_task(int64_t n, int32_t rhs, int32_t supplied, int64_t q, int32_t *i,
-                           int32_t *j, int32_t *kend, int64_t *ntask);
+ * rhs = 1 when the three right-hand sides ride along as an extra tile row:
+ * *ntask receives the number of tasks, and for 0 <= q < *ntask the tile
+ * (*i, *j) of ticket q (*i == nt: the right-hand-side row) and *kend, the
+ * number of 64-column steps the task accumulates.  n < 1, rhs not 0/1, or q
+ * outside [0, *ntask) (q < 0 only queries the count) -> PD_ERR_INVALID. */
+pd_status pd_dataflow_task(int64_t n, int32_t rhs, int64_t q, int32_t *i, int32_t *j,
+                           int32_t *kend, int64_t *ntask);
 
 /* The nested-dissection ordering and symbolic factorization that
  * pd_schur_build uses for interior_order = 1 (host only, no GPU work;

@@ -72,7 +72,7 @@ _SIGS = {
     "pd_chol_factor": [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32)],
     "pd_chol_destroy": [_P],
     "pd_nd_analyse": [C.POINTER(pd_mesh), C.c_int32, _P, _P, _P, _P, _P, _P],
-    "pd_dataflow_task": [C.c_int64, C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
+    "pd_dataflow_task": [C.c_int64, C.c_int32, C.c_int64, C.POINTER(C.c_int32),
                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64)],
     "pd_chol_factor_noalloc": [_P, C.c_int64, C.c_int64, C.c_int32, _P, C.POINTER(C.c_int32)],
     "pd_displacement_change": [_P, _P, _P, _P],
@@ -84,7 +84,6 @@ _SIGS = {
     "pd_use_stream": [_P, _P],
     "pd_factor": [_P, C.c_int32, C.c_int32],
     "pd_set_refinement": [_P, C.c_int32, C.c_double, C.c_int32],
-    "pd_supply_rhs": [_P, _P],
     "pd_set_timing": [_P, C.c_int],
     "pd_get_timings": [_P, _P, _P],
     "pd_destroy": [_P],
@@ -401,18 +400,11 @@ class PDContext(_Handle):
         self._chk(self._lib.pd_set_refinement(self._ctx, int(max_steps), float(tol),
                                               int(fallback)))
 
-    def factor(self, n_workgroups=0, supply_rhs=False, overlap_forward=False):
+    def factor(self, n_workgroups=0, overlap_forward=False):
         """FP64 factorization of H ahead of global_solve (pd_factor); with
         overlap_forward the next global_solve may be enqueued on another stream
-        while it runs (mode 2), with supply_rhs the forward solve is fused in
-        (mode 1)."""
-        mode = 2 if overlap_forward else (1 if supply_rhs else 0)
-        self._chk(self._lib.pd_factor(self._ctx, int(n_workgroups), mode))
-
-    def supply_rhs(self, g):
-        """Right-hand side for a factorization started with supply_rhs=True."""
-        import torch
-        self._chk(self._lib.pd_supply_rhs(self._ctx, _ptr(g, torch.float64, 3 * self.m, "g")))
+        while it runs."""
+        self._chk(self._lib.pd_factor(self._ctx, int(n_workgroups), 1 if overlap_forward else 0))
 
     def inner_update(self, u2, x2, delta2, ft):
         import torch

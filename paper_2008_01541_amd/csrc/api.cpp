@@ -74,10 +74,10 @@ namespace {
 // multiple of 16 so tiles start on 128-byte lines); tile inverses to d_linv,
 // transpose of the factor in the upper triangle.
 void cholesky(pd_ctx* c, double* A, int lda, int n, double* Yt = nullptr, int n_wg = 0,
-              const int* gflag = nullptr, int gepoch = 0, hipEvent_t after_reset = nullptr) {
+              hipEvent_t after_reset = nullptr) {
   potrf_dataflow(A, lda, n, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info, c->d_err,
-                 n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, gflag, gepoch,
-                 c->d_cumarks, after_reset);
+                 n_wg > 0 ? std::min(n_wg, c->n_wg) : c->n_wg, Yt, c->st, c->d_cumarks,
+                 after_reset);
 }
 
 inline int pad_to(int64_t v, int q) { return (int)((v + q - 1) / q * q); }
@@ -593,8 +593,6 @@ pd_status build_impl(pd_ctx* c, const pd_mesh* M) {
   CK(c->alloc(&c->d_xs, 3 * std::max<int64_t>(1, c->n1)));
   CK(c->alloc(&c->d_tmp, 3 * std::max<int64_t>(1, c->maxw)));
   CK(c->alloc(&c->d_P, std::max(sweep_workspace(c->maxw), sweep_workspace(m))));
-  CK(c->alloc(&c->d_gflag, 1));
-  HIPCK(c, hipMemsetAsync(c->d_gflag, 0, sizeof(int), c->st));
   HIPCK(c, hipStreamSynchronize(c->st));
   return PD_OK;
 }
@@ -1057,15 +1055,10 @@ pd_status pd_global_solve(pd_ctx* c, const double* g, double* u, pd_precision pr
     }
     {
       PhaseTimer tmsolve(c, PD_PHASE_SOLVE);
-      if (fused || c->deferred) {
-        // the forward substitution ran inside the factorization (for a
-        // deferred right-hand side: the one given to pd_supply_rhs)
-        if (c->deferred && !c->rhs_supplied)
-          return c->fail(PD_ERR_STATE, "pd_factor(supply_rhs) needs pd_supply_rhs before the solve");
+      if (fused) {
+        // the forward substitution ran inside the factorization
         rhs_unpack(m, c->d_Yt, c->d_ys, m, c->st);
         sentinel_fill(3 * m, u, c->st);     // the backward solve publishes u by value
-        c->deferred = false;
-        c->rhs_supplied = false;
       } else if (c->overlap) {
         // the factorization may still run on another stream: the forward
         // solve follows its tile flags, the backward one waits for its end
@@ -1192,14 +1185,13 @@ pd_status pd_set_refinement(pd_ctx* c, int32_t max_steps, double tol, int32_t fa
   return PD_OK;
 }
 
-pd_status pd_factor(pd_ctx* c, int32_t n_workgroups, int32_t supply_rhs) {
+pd_status pd_factor(pd_ctx* c, int32_t n_workgroups, int32_t overlap_forward) {
   if (bad_ctx(c)) return PD_ERR_INVALID;
   if (c->broken) return PD_ERR_HIP;
+  if (overlap_forward != 0 && overlap_forward != 1)
+    return c->fail(PD_ERR_INVALID, "overlap_forward must be 0 or 1 (got %d)", (int)overlap_forward);
   if (!c->stale) return PD_OK;
-  if (supply_rhs < 0 || supply_rhs > 2)
-    return c->fail(PD_ERR_INVALID, "supply_rhs must be 0, 1 or 2 (got %d)", (int)supply_rhs);
-  const bool defer = supply_rhs == 1;
-  const bool overlap = supply_rhs == 2;
+  const bool overlap = overlap_forward == 1;
   if (overlap && !c->ev_fstart) {
     HIPCK(c, hipEventCreateWithFlags(&c->ev_fstart, hipEventDisableTiming));
     HIPCK(c, hipEventCreateWithFlags(&c->ev_fdone, hipEventDisableTiming));
@@ -1208,32 +1200,14 @@ pd_status pd_factor(pd_ctx* c, int32_t n_workgroups, int32_t supply_rhs) {
   zero_int(c->d_info, c->st);
   {
     PhaseTimer tm(c, PD_PHASE_FACTOR);
-    if (defer) {
-      ++c->g_epoch;
-      cholesky(c, c->d_H, c->ldH, (int)c->m, c->d_Yt, n_workgroups, c->d_gflag, c->g_epoch);
-    } else {
-      cholesky(c, c->d_H, c->ldH, (int)c->m, nullptr, n_workgroups, nullptr, 0,
-               overlap ? c->ev_fstart : nullptr);
-    }
+    cholesky(c, c->d_H, c->ldH, (int)c->m, nullptr, n_workgroups,
+             overlap ? c->ev_fstart : nullptr);
   }
   if (overlap) HIPCK(c, hipEventRecord(c->ev_fdone, c->st));
-  c->deferred = defer;
   c->overlap = overlap;
-  c->rhs_supplied = false;
   c->stale = false;
   c->lp_stale = true;             // d_H was rebuilt
   return c->check("pd_factor");
-}
-
-pd_status pd_supply_rhs(pd_ctx* c, const double* g) {
-  if (bad_ctx(c) || !g) return PD_ERR_INVALID;
-  if (c->broken) return PD_ERR_HIP;
-  if (!c->deferred) return PD_OK;
-  PhaseTimer tm(c, PD_PHASE_ASSEMBLE);
-  rhs_pack((int)c->m, g, (int)c->m, c->d_Yt, c->st);
-  set_flag(c->d_gflag, c->g_epoch, c->st);
-  c->rhs_supplied = true;
-  return c->check("pd_supply_rhs");
 }
 
 pd_status pd_inner_update(pd_ctx* c, const double* u2, double* x2, double* delta2, double* ft) {

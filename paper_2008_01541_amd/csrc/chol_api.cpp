@@ -123,7 +123,7 @@ pd_status pd_chol_factor(pd_chol* h, double* A, int64_t lda, int64_t n, int32_t 
   zero_int(h->err, h->st);
   const int nwg = n_workgroups > 0 ? std::min<int>(n_workgroups, h->n_wg) : h->n_wg;
   potrf_dataflow(A, (int)lda, (int)n, h->linv, h->sbuf, h->flags, h->ticket, h->info, h->err, nwg,
-                 nullptr, h->st, nullptr, 0, h->marks, nullptr);
+                 nullptr, h->st, h->marks, nullptr);
   if (hipGetLastError() != hipSuccess) return PD_ERR_HIP;
   if (!info_host) return PD_OK;
   int hinfo = 0, herr = 0;
@@ -170,7 +170,7 @@ pd_status pd_chol_factor_noalloc(double* A, int64_t lda, int64_t n, int32_t n_wo
   zero_int(err, st);
   const int nwg = n_workgroups > 0 ? std::min<int>(n_workgroups, d->n_wg) : d->n_wg;
   potrf_dataflow(A, (int)lda, (int)n, linv, sbuf, flags, ticket, info, err, nwg, nullptr, st,
-                 nullptr, 0, marks, nullptr);
+                 marks, nullptr);
   if (hipGetLastError() != hipSuccess) return PD_ERR_HIP;
   if (!info_host) return PD_OK;
   int hinfo = 0, herr = 0;
@@ -190,17 +190,15 @@ pd_status pd_chol_destroy(pd_chol* h) {
   return PD_OK;
 }
 
-pd_status pd_dataflow_task(int64_t n, int32_t rhs, int32_t supplied, int64_t q, int32_t* i,
-                           int32_t* j, int32_t* kend, int64_t* ntask) {
-  if (n < 1 || n > 46340 || (rhs != 0 && rhs != 1) || (supplied != 0 && supplied != 1) ||
-      (supplied && !rhs) || !ntask)
-    return PD_ERR_INVALID;
+pd_status pd_dataflow_task(int64_t n, int32_t rhs, int64_t q, int32_t* i, int32_t* j,
+                           int32_t* kend, int64_t* ntask) {
+  if (n < 1 || n > 46340 || (rhs != 0 && rhs != 1) || !ntask) return PD_ERR_INVALID;
   const int nt = (int)((n + NB - 1) / NB);
   *ntask = df_task_count(nt, rhs);
   if (q < 0) return PD_OK;
   if (q >= *ntask || !i || !j || !kend) return PD_ERR_INVALID;
   int ti, tj;
-  df_task_of_ticket((int)q, nt, rhs, supplied != 0, ti, tj);
+  df_task_of_ticket((int)q, nt, rhs, ti, tj);
   *i = ti;
   *j = tj;
   *kend = df_task_kend(ti, tj);

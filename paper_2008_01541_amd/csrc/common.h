@@ -21,9 +21,8 @@ void copy_lower_tiles(const double* S, int lds, double* H, int ldh, int n, hipSt
 // the epoch on the device (safe under graph replay).  sbuf: nt * NB * NB
 // doubles of workspace (partial sums of the first sub-diagonal tiles).
 // With Yt (64 x n, rows 0..2 = g^T) the forward substitution L^-1 g is fused
-// in (result in the same rows).  With gflag, Yt is filled while the
-// factorization runs: its tasks come after all tiles and wait until *gflag
-// equals gepoch (set with set_flag after Yt is written, e.g. on another stream).
+// in (result in the same rows).  A task never waits for work enqueued on
+// another stream: streams may share a hardware queue, which runs in order.
 // cu_marks (optional): potrf_cu_slots() zero-initialised ints, the per-unit
 // marks by which tasks off the critical path yield to a diagonal task.
 // after_reset (optional): recorded once the launch epoch is advanced, before
@@ -31,10 +30,9 @@ void copy_lower_tiles(const double* S, int lds, double* H, int ldh, int n, hipSt
 // poll the tile flags of the running factorization).
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
                     unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
-                    const int* gflag = nullptr, int gepoch = 0, int* cu_marks = nullptr,
+                    int* cu_marks = nullptr,
                     hipEvent_t after_reset = nullptr);
 int potrf_cu_slots();
-void set_flag(int* f, int v, hipStream_t st);
 void rhs_pack(int n, const double* g, int ldg, double* Yt, hipStream_t st);
 void rhs_unpack(int n, const double* Yt, double* y, int ldy, hipStream_t st);
 // Fill kernels (used instead of memset so the calls can be graph-captured).

@@ -110,10 +110,6 @@ struct pd_ctx {
   const double* d_target = nullptr;  // caller's inertial target x_n + dt v_n
   bool have_condense = false;
   double* d_P = nullptr;              // tile parts of a level's (or S's) dense product
-  int* d_gflag = nullptr;             // right-hand side supplied to a running factorization
-  int g_epoch = 0;                    // last value stored to d_gflag
-  bool deferred = false;              // the current factor awaits / holds a supplied RHS
-  bool rhs_supplied = false;          // pd_supply_rhs was called for it
   bool overlap = false;               // the forward solve may overlap the running factorization
   hipEvent_t ev_fstart = nullptr;     // factorization epoch advanced (its flags may be polled)
   hipEvent_t ev_fdone = nullptr;      // factorization finished

@@ -269,8 +269,7 @@ __device__ inline void stage_tile(double (*T)[LDS_LD], const double* __restrict_
 __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, int n, int nt,
                                                            double* linv_ws, double* sbuf,
                                                            int* flags, unsigned* ticket, int* info,
-                                                           int* err, double* Yt, const int* gflag,
-                                                           int gepoch, int* cu_marks) {
+                                                           int* err, double* Yt, int* cu_marks) {
   const int epoch = (int)ticket[1];
   const int rhs = Yt != nullptr ? 1 : 0;
   int* const mark = cu_marks ? cu_marks + cu_slot() : nullptr;
@@ -292,14 +291,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
     const int q = s_task;
     if (q >= ntask) return;
     int i, j;
-    df_task_of_ticket(q, nt, rhs, gflag != nullptr, i, j);
-    if (gflag && i == nt) {
-      // right-hand side supplied during the factorization: its row comes
-      // after all tiles, and each of its tasks first waits for it
-      if (t == 0 && !df_wait(gflag, gepoch, err)) s_ok = 0;
-      __syncthreads();
-      if (!s_ok) return;
-    }
+    df_task_of_ticket(q, nt, rhs, i, j);
     const bool rrow = (i == nt);
     const bool diag = (i == j), sub = !rrow && i == j + 1;
     double* Ai = rrow ? Yt : A;
@@ -479,20 +471,15 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
 
 void potrf_dataflow(double* A, int lda, int n, double* linv_ws, double* sbuf, int* flags,
                     unsigned* ticket, int* info, int* err, int n_wg, double* Yt, hipStream_t st,
-                    const int* gflag, int gepoch, int* cu_marks, hipEvent_t after_reset) {
+                    int* cu_marks, hipEvent_t after_reset) {
   const int nt = (n + NB - 1) / NB;
   const int ntask = df_task_count(nt, Yt ? 1 : 0);
   k_reset_counter<<<1, 1, 0, st>>>(ticket);
   if (after_reset) (void)hipEventRecord(after_reset, st);
   k_potrf_dataflow<<<std::min(ntask, n_wg), 256, 0, st>>>(A, lda, n, nt, linv_ws, sbuf, flags,
-                                                          ticket, info, err, Yt,
-                                                          Yt ? gflag : nullptr, gepoch, cu_marks);
+                                                          ticket, info, err, Yt, cu_marks);
 }
 
-__global__ void k_set_flag(int* f, int v) {
-  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-void set_flag(int* f, int v, hipStream_t st) { k_set_flag<<<1, 1, 0, st>>>(f, v); }
 int potrf_cu_slots() { return CU_SLOTS; }
 
 // Yt[v + r * 64] = g[v * ldg + r] (v < 3) and back.

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow_lp(float* A, int lda,
     const int q = s_task;
     if (q >= ntask) return;
     int i, j;
-    df_task_of_ticket(q, nt, 0, false, i, j);
+    df_task_of_ticket(q, nt, 0, i, j);
     const bool diag = (i == j), sub = (i == j + 1);
     const bool critical = diag || sub;
     const int r0 = i * NB, c0 = j * NB;

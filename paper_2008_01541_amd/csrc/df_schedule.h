@@ -10,20 +10,10 @@ namespace pdk {
 
 // Ticket q -> tile (i, j), 0 <= j <= i < nt, i == nt for the right-hand-side
 // row.  Tickets go column by column; in column j the diagonal tile first,
-// then the tiles below it in order, then (rhs = 1, inline) the right-hand-side
-// row.  With supplied = true (right-hand side given while the factorization
-// runs) the right-hand-side row comes after all tiles.
-__host__ __device__ inline void df_task_of_ticket(int q, int nt, int rhs, bool supplied, int& i,
-                                                  int& j) {
-  const int per = supplied ? 0 : rhs;
-  const int ntile = nt * (nt + 1) / 2;
-  if (supplied && q >= ntile) {
-    i = nt;
-    j = q - ntile;
-    return;
-  }
+// then the tiles below it in order, then (rhs = 1) the right-hand-side row.
+__host__ __device__ inline void df_task_of_ticket(int q, int nt, int rhs, int& i, int& j) {
   int jj = 0, start = 0;
-  while (start + (nt - jj + per) <= q) start += nt - jj++ + per;
+  while (start + (nt - jj + rhs) <= q) start += nt - jj++ + rhs;
   j = jj;
   i = jj + (q - start);
 }

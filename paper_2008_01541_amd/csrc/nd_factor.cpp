@@ -450,7 +450,7 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
       nd_extend_add(d_U + uoff[ch], ldu[ch], (int)bsz(ch), d_fmap + S.bptr[ch], a, P, ldp[s], U,
                     ldu[s], 0, c->st);
     potrf_dataflow(P, (int)ldp[s], a, c->d_linv, c->d_sbuf, c->d_tflags, c->d_tticket, c->d_info,
-                   c->d_err, c->n_wg, nullptr, c->st, nullptr, 0, c->d_cumarks, nullptr);
+                   c->d_err, c->n_wg, nullptr, c->st, c->d_cumarks, nullptr);
     trtri_from_factor(P, (int)ldp[s], a, c->d_linv, d_M, d_X, ldx, c->st);
     lauum_full(d_X, ldx, a, ZW, lzw, c->st);
     if (b > 0) {

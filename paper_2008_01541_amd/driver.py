@@ -173,31 +173,26 @@ class Alg1Runner:
         return infos
 
     def run_pipelined(self, n_iters, spheres_of=None, n_workgroups=0, factor_stream=None,
-                      fuse_forward=False, overlap_forward=True, before_local=None):
+                      overlap_forward=True, before_local=None):
         """n_iters outer iterations with one inner iteration each, pipelined
         over two streams.  The factorization side of iteration k (detection,
         penalties, region local step, H = S + W^T C W and its Cholesky factor)
         needs only the region positions after the inner update of iteration
         k - 1, so it runs on a second stream while the back substitution of
         k - 1, the full local step and the condensation of k run on the context
-        stream.  With fuse_forward the right-hand side, once assembled, is
-        handed to the running factorization (pd_supply_rhs), which then also
-        does the forward substitution (its tasks follow all tiles, so this only
-        pays off when the right-hand side arrives early); with overlap_forward
-        (the default) the forward solve is enqueued on the context stream
-        without waiting for the factorization and follows its tile flags, and
-        the backward solve waits for its end; otherwise both triangular solves
-        follow the factorization.  The solves and the inner update join both
-        streams.  The arithmetic is that of
-        outer_iteration(n_inner=1) (without fuse_forward the forward
-        substitution is a separate solve), except that the region positions
-        are carried over from the inner update instead of being gathered from
-        x after the back substitution (the same values: delta2 holds the
-        single update).  spheres_of(k) gives the obstacle spheres of
-        iteration k (None keeps the current ones); before_local(k), if given,
-        runs on the context stream between the back substitution of k - 1 and
-        the full local step of k (e.g. to move prescribed Dirichlet nodes in
-        x, as a caller of outer_iteration would before each call)."""
+        stream.  With overlap_forward (the default) the forward solve is
+        enqueued on the context stream without waiting for the factorization
+        and follows its tile flags, and the backward solve waits for its end;
+        otherwise both triangular solves follow the factorization.  The solves
+        and the inner update join both streams.  The arithmetic is that of
+        outer_iteration(n_inner=1), except that the region positions are
+        carried over from the inner update instead of being gathered from x
+        after the back substitution (the same values: delta2 holds the single
+        update).  spheres_of(k) gives the obstacle spheres of iteration k
+        (None keeps the current ones); before_local(k), if given, runs on the
+        context stream between the back substitution of k - 1 and the full
+        local step of k (e.g. to move prescribed Dirichlet nodes in x, as a
+        caller of outer_iteration would before each call)."""
         torch = self.torch
         c = self.ctx
         s_main = c.stream
@@ -216,8 +211,7 @@ class Alg1Runner:
             c.local_step_region(self.x2, self.fb)
             ev_pen = torch.cuda.Event()          # penalties and f_beta ready
             ev_pen.record(s_fac)
-            overlap = overlap_forward and not fuse_forward
-            c.factor(n_workgroups, supply_rhs=fuse_forward, overlap_forward=overlap)
+            c.factor(n_workgroups, overlap_forward=overlap_forward)
             ev_fac = torch.cuda.Event()
             ev_fac.record(s_fac)
             # sweep side: finish iteration k - 1, start iteration k
@@ -233,9 +227,7 @@ class Alg1Runner:
                 self.delta2.zero_()
             s_main.wait_event(ev_pen)
             c.assemble_rhs(self.ft, self.fb, self.fcol, self.g)
-            if fuse_forward:
-                c.supply_rhs(self.g)
-            if not overlap:
+            if not overlap_forward:
                 s_main.wait_event(ev_fac)
             c.global_solve(self.g, self.u)
             c.inner_update(self.u, self.x2, self.delta2, self.ft)

@@ -198,12 +198,11 @@ def test_alg1_iterations_match_oracle(torch_cuda, name, inner):
     assert worst <= 1e-9
 
 
-@pytest.mark.parametrize("name,n_wg,fuse,overlap", [("g9x7x6", 0, True, False),
-                                                     ("g16x15x8", 64, False, False),
-                                                     ("g16x15x8", 64, True, False),
-                                                     ("g16x15x8", 64, False, True),
-                                                     ("g16x15x8", 0, False, True)])
-def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg, fuse, overlap):
+@pytest.mark.parametrize("name,n_wg,overlap", [("g9x7x6", 0, False),
+                                                ("g16x15x8", 64, False),
+                                                ("g16x15x8", 64, True),
+                                                ("g16x15x8", 0, True)])
+def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg, overlap):
     """Two-stream pipelined iterations (the factorization of iteration k
     overlapping the back substitution of k - 1 and the condensation of k;
     with overlap the forward solve also runs during the factorization,
@@ -220,7 +219,7 @@ def test_pipelined_iterations_match_oracle(torch_cuda, name, n_wg, fuse, overlap
         sph[f] = run.spheres
     torch_cuda.cuda.synchronize()
     run.run_pipelined(len(frames), spheres_of=lambda k: sph[frames[k]], n_workgroups=n_wg,
-                      fuse_forward=fuse, overlap_forward=overlap)
+                      overlap_forward=overlap)
     x_or = sc.rest.copy()
     for f in frames:
         det = opd.sphere_detector(om, sc.proxy_local(), sc.spheres.centers(f), sc.spheres.radii,
@@ -483,7 +482,7 @@ def test_factor_modes(torch_cuda):
     ctx.global_solve(g, u_ref)
     ctx.collision_update(dev(idx), dev(w), dev(c), dev(t), x2, fcol)    # factor stale again
     from paper_2008_01541_amd import PDError
-    assert ctx._lib.pd_factor(ctx._ctx, 0, 3) == -1
+    assert ctx._lib.pd_factor(ctx._ctx, 0, 2) == -1     # modes: 0 and 1 (overlap) only
     with pytest.raises(PDError):
         ctx._chk(ctx._lib.pd_factor(ctx._ctx, 0, -1))
     ctx.factor(overlap_forward=True)

@@ -18,14 +18,14 @@ def _lib():
     return load_library()
 
 
-def schedule(n, rhs, supplied=0):
+def schedule(n, rhs):
     """[(i, j, kend)] of every ticket, from the library."""
     lib = _lib()
     i, j, kend, ntask = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
-    assert lib.pd_dataflow_task(n, rhs, supplied, -1, None, None, None, C.byref(ntask)) == 0
+    assert lib.pd_dataflow_task(n, rhs, -1, None, None, None, C.byref(ntask)) == 0
     out = []
     for q in range(ntask.value):
-        st = lib.pd_dataflow_task(n, rhs, supplied, q, C.byref(i), C.byref(j), C.byref(kend),
+        st = lib.pd_dataflow_task(n, rhs, q, C.byref(i), C.byref(j), C.byref(kend),
                                   C.byref(ntask))
         assert st == 0
         out.append((i.value, j.value, kend.value))
@@ -36,11 +36,10 @@ def test_schedule_rejects_bad_arguments():
     lib = _lib()
     i, j, kend, ntask = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
     args = (C.byref(i), C.byref(j), C.byref(kend), C.byref(ntask))
-    assert lib.pd_dataflow_task(0, 0, 0, 0, *args) == -1
-    assert lib.pd_dataflow_task(100, 2, 0, 0, *args) == -1
-    assert lib.pd_dataflow_task(100, 0, 1, 0, *args) == -1          # supplied without rhs
-    assert lib.pd_dataflow_task(100, 0, 0, 3, *args) == -1          # 2 tiles -> 3 tasks: q = 3 out
-    assert lib.pd_dataflow_task(100, 0, 0, 2, *args) == 0
+    assert lib.pd_dataflow_task(0, 0, 0, *args) == -1
+    assert lib.pd_dataflow_task(100, 2, 0, *args) == -1
+    assert lib.pd_dataflow_task(100, 0, 3, *args) == -1          # 2 tiles -> 3 tasks: q = 3 out
+    assert lib.pd_dataflow_task(100, 0, 2, *args) == 0
     assert (i.value, j.value, kend.value, ntask.value) == (1, 1, 0, 3)
 
 
@@ -109,14 +108,13 @@ def test_dataflow_indices_in_bounds(n, rhs):
 
 
 @pytest.mark.parametrize("n", [1, 64, 130, 200, 3249, 6498])
-@pytest.mark.parametrize("rhs,supplied", [(0, 0), (1, 0), (1, 1)])
-def test_ticket_order_respects_dependencies(n, rhs, supplied):
+@pytest.mark.parametrize("rhs", [0, 1])
+def test_ticket_order_respects_dependencies(n, rhs):
     """A task only waits on tasks with smaller tickets (so a persistent launch
     cannot deadlock): tiles (i, k), (j, k) for k < kend, Linv_j, the partial
     sum and tile (j, j - 1) of a diagonal task, and the right-hand-side row's
     earlier steps."""
-    nt = (n + NB - 1) // NB
-    sched = schedule(n, rhs, supplied)
+    sched = schedule(n, rhs)
     pos = {(i, j): q for q, (i, j, _) in enumerate(sched)}
     for q, (i, j, kend) in enumerate(sched):
         deps = [(j, j)] if i != j else []
@@ -126,6 +124,3 @@ def test_ticket_order_respects_dependencies(n, rhs, supplied):
         for d in deps:
             if d != (i, j):
                 assert d in pos and pos[d] < q, ((i, j), d)
-    if supplied:
-        ntile = nt * (nt + 1) // 2
-        assert all(i == nt for (i, _, _) in sched[ntile:])
