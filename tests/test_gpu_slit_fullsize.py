@@ -70,3 +70,38 @@ def test_slit_refined_solves(slit, prec):
     rel = max(np.linalg.norm(r[v]) / np.linalg.norm(g[v]) for v in range(3))
     assert rel <= (1e-10 if prec == 0 else 1e-8), rel
     assert info["rel_residual"] == pytest.approx(rel, rel=0.05, abs=1e-13)
+
+
+def test_slit_nd_schur_probes_and_sweeps(slit):
+    """The nested-dissection interior factor on the full slit (interior on
+    both sides of the region): S v against the oracle's K22 v - K21 K11^-1 K12 v
+    for seeded v, and both condensation sweeps against its sparse solves."""
+    import torch
+    from oracle import schur as osch
+    sc, _, om = slit
+    ctx = gpu_context(sc, interior="nd")
+    try:
+        assert ctx.m == om.m and ctx.n1 == om.i1.size
+        S = torch.empty(ctx.m * ctx.m, dtype=torch.float64, device="cuda")
+        ctx.get_schur(S)
+        Sm = S.reshape(ctx.m, ctx.m)
+        rng = np.random.default_rng(31)
+        for _ in range(2):
+            v = rng.normal(size=ctx.m)
+            ref = osch.schur_apply(om.lu11, om.A12, om.A21, om.A22, v)
+            got = host(Sm @ torch.tensor(v, device="cuda"))
+            assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+        del S, Sm
+        f = rng.normal(size=(3, sc.n_nodes))
+        y2 = torch.empty(3 * ctx.m, dtype=torch.float64, device="cuda")
+        ctx.condense_rhs(dev(f), y2)
+        w1, y2_or = osch.forward_sub(om.lu11, om.A21, f[:, om.i1].T, f[:, om.i2].T)
+        assert np.abs(host(y2, (3, -1)) - y2_or.T).max() <= 1e-10 * np.abs(y2_or).max()
+        d2 = rng.normal(size=(3, ctx.m))
+        xd = dev(np.zeros((3, sc.n_nodes)))
+        ctx.backsub(dev(d2), xd)
+        x1_or = osch.back_sub(om.lu11, om.A12, f[:, om.i1].T, d2.T).T
+        got = host(xd, (3, -1))
+        assert np.abs(got[:, om.i1] - x1_or).max() <= 1e-10 * np.abs(x1_or).max()
+    finally:
+        ctx.close()
