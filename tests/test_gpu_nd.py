@@ -218,3 +218,44 @@ def test_nd_build_and_sweeps_bitwise_reproducible(torch_cuda):
         ctx.close()
     for a, b in zip(*outs):
         assert torch_cuda.equal(a, b)
+
+
+def test_two_bodies_one_without_region(torch_cuda):
+    """Two disjoint grids, each pinned at its bottom, the region on the top of
+    the first only: the second body's interior never couples to the region
+    (breadth-first levels: the unreachable level; nested dissection: roots
+    whose boundary is empty).  S and both sweeps against the oracle, for both
+    interior factors."""
+    from gpu_util import rel as _rel
+    from pd_inputs import kuhn_grid, layer_mask, lame_mu
+    nx, ny, nz = 6, 5, 4
+    r1, t1 = kuhn_grid(nx, ny, nz, 1.0)
+    r2, t2 = kuhn_grid(nx, ny, nz, 1.0)
+    n1 = r1.shape[1]
+    r2 = r2 + np.array([[nx + 3.0], [0.0], [0.0]])
+    rest = np.concatenate([r1, r2], axis=1)
+    tets = np.concatenate([t1, t2 + n1], axis=1).astype(np.int32)
+    bottom = layer_mask(nx, ny, nz, [0])
+    dirichlet = np.concatenate([bottom, bottom])
+    region = np.concatenate([layer_mask(nx, ny, nz, [nz - 1, nz]), np.zeros(n1, bool)])
+    mu = lame_mu()
+    om = opd.PDModel(rest, tets, mu, dirichlet, region)
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=(3, rest.shape[1]))
+    d2 = rng.normal(size=(3, om.m))
+    w1, y2_or = osch.forward_sub(om.lu11, om.A21, f[:, om.i1].T, f[:, om.i2].T)
+    x1_or = osch.back_sub(om.lu11, om.A12, f[:, om.i1].T, d2.T).T
+    from paper_2008_01541_amd import PDContext
+    for interior, leaf in [("levels", 0), ("nd", 0), ("nd", 8)]:
+        ctx = PDContext(rest, tets, region, dirichlet, mu, interior=interior, nd_leaf=leaf)
+        S = torch_cuda.empty(ctx.m * ctx.m, dtype=torch_cuda.float64, device="cuda")
+        ctx.get_schur(S)
+        assert _rel(host(S, (ctx.m, ctx.m)).T, om.schur()) <= TOL, interior
+        y2 = torch_cuda.empty(3 * ctx.m, dtype=torch_cuda.float64, device="cuda")
+        ctx.condense_rhs(dev(f), y2)
+        assert _rel(host(y2, (3, -1)), y2_or.T) <= TOL, interior
+        xd = dev(np.zeros_like(f))
+        ctx.backsub(dev(d2), xd)
+        got = host(xd, (3, -1))
+        assert _rel(got[:, om.i1], x1_or) <= TOL, interior
+        ctx.close()
