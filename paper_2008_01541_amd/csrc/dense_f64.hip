@@ -147,7 +147,8 @@ __device__ bool df_accumulate(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_L
                               int* err, int* s_ok, const int* mark) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = w >> 1, wc = w & 1;
-  const int r = t & 63, kq = t >> 6;
+  const int r = t & 63;
+  const int kq = __builtin_amdgcn_readfirstlane(t >> 6);   // the wave index, uniform: addresses stay scalar
   if (kend == 0) return true;
   double ra[16], rb[16];
   auto load_tile = [&](int k) {
@@ -225,6 +226,48 @@ __device__ inline void lds_product(Acc& acc, double (*As)[LDS_LD], double (*Bs)[
     acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
     acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
     acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
+    acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
+  }
+}
+
+// Triangular right factor: acc(r, c) = sum_k As[k][r] Bs[k][c] where
+// Bs[k][c] = 0 for k > c (Bs holds the transpose of a lower-triangular
+// tile), so column block cb only takes the k-blocks 0..cb.  The waves of
+// column half 0 own column blocks 0 and 3 and those of half 1 blocks 1 and 2
+// (40 products per wave instead of 64); accumulator block nb of this wave is
+// column block tri_cb(nb).  Only exact zeros are skipped, so the result is
+// the full product's.
+__device__ inline int tri_cb(int nb) {
+  const int wc = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) & 1;
+  return wc ? 1 + nb : 3 * nb;
+}
+__device__ inline int tri_col(int nb, int q) {
+  return 16 * tri_cb(nb) + (int)((threadIdx.x & 63) >> 4) + 4 * q;
+}
+__device__ inline void lds_product_tri(Acc& acc, double (*As)[LDS_LD], double (*Bs)[LDS_LD]) {
+  const int lane = threadIdx.x & 63;
+  const int wr = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) >> 1;
+  const int cb0 = tri_cb(0), cb1 = tri_cb(1);
+  const int kA = 4 * (cb0 + 1), kB = 4 * (cb1 + 1);     // 4-deep steps per block, kA < kB
+#pragma unroll 4
+  for (int ks = 0; ks < kA; ++ks) {
+    const int k = ks * 4 + (lane >> 4);
+    const double a0 = As[k][wr * 32 + (lane & 15)];
+    const double a1 = As[k][wr * 32 + 16 + (lane & 15)];
+    const double b0 = Bs[k][16 * cb0 + (lane & 15)];
+    const double b1 = Bs[k][16 * cb1 + (lane & 15)];
+    acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
+    acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
+    acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
+    acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
+  }
+#pragma unroll 4
+  for (int ks = kA; ks < kB; ++ks) {
+    const int k = ks * 4 + (lane >> 4);
+    const double a0 = As[k][wr * 32 + (lane & 15)];
+    const double a1 = As[k][wr * 32 + 16 + (lane & 15)];
+    const double b1 = Bs[k][16 * cb1 + (lane & 15)];
+    acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
     acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
   }
 }
@@ -370,33 +413,42 @@ __global__ __launch_bounds__(256, 2) void k_potrf_dataflow(double* A, int lda, i
       mark_unit();
       stage_tile(buf1, linv_ws + (long)(j - 1) * NB * NB);   // buf1[kk][c] = Linv(c, kk)
       __syncthreads();
-      Acc l;
+      Acc l;                                       // columns tri_col(nb, q)
       acc_zero(l);
-      lds_product(l, buf0, buf1);                  // L = S Linv^T
+      lds_product_tri(l, buf0, buf1);              // L = S Linv^T
       __syncthreads();
-      acc_to_lds(l, buf0, 1.0);
+      // L into buf1 (the tile factor's inverse slot, which takes the last
+      // rank-64 update C -= L L^T block by block while its first diagonal
+      // block is factored), C without that term into buf0
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) buf1[tri_col(nb, qq)][acc_row(mb)] = l.c[mb][nb][qq];
+      acc_to_lds(acc, buf0, -1.0);
       // the tile goes to memory straight from the registers (each lane's
-      // sixteen rows of 16-lane runs), while the LDS copy feeds the product
+      // sixteen rows of 16-lane runs); the tile factor publishes its flag
+      // once the stores have drained
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) {
-            const int r = acc_row(mb), c = acc_col(nb, qq);
+            const int r = acc_row(mb), c = tri_col(nb, qq);
             if (r < mr) coherent_store(&A[(long)(r0 + r) + (long)(cs + c) * lda], l.c[mb][nb][qq]);
           }
-      __syncthreads();
-      lds_product(acc, buf0, buf0);                // acc += L L^T, while the stores drain
-      publish_flag(&flags[j * nt + (j - 1)], epoch);
       // (its transposed copy is written after the tile, off the critical path)
+    } else {
+      __syncthreads();
+      acc_to_lds(acc, buf0, -1.0);                 // C = A_ij - sum_k L_ik L_jk^T
     }
-    __syncthreads();
-    acc_to_lds(acc, buf0, -1.0);                   // C = A_ij - sum_k L_ik L_jk^T
     __syncthreads();
     if (diag) {
       if (j == 0) mark_unit();
-      factor_tile_blocked(buf0, buf1, mr, r0, info);
+      factor_tile_blocked(buf0, buf1, mr, r0, info, j > 0 ? &flags[j * nt + (j - 1)] : nullptr,
+                          epoch);
       // only the inverse is read inside this launch: publish it first, then
       // write L (lower) and its transposed copy (strictly upper) for the solves
       double* Li = linv_ws + (long)j * NB * NB;

@@ -5,6 +5,7 @@
 // path yield to the diagonal task.  Header-only: included by each kernel file.
 #pragma once
 #include "common.h"
+#include "publish.h"
 
 namespace pdk {
 
@@ -63,15 +64,14 @@ __device__ __forceinline__ void chol16_step(double (&a)[16], double (&x)[16], do
 }
 
 // Cholesky factor and inverse of the 16 x 16 diagonal block at (b0, b0) of the
-// LDS tile T, by one wave (the four rows of 16 lanes work redundantly).  L
-// replaces the lower part of the block (zeros above), its inverse goes to the
-// same block of X (zeros above).  The first non-positive pivot j of the block
-// (inside the first mr rows) is reported in *info as gbase + b0 + j + 1, and
-// its reciprocal square root is taken as 1.
-__device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[LDS_LD], int b0,
-                                               int mr, int gbase, int* info) {
+// LDS tile T, by one wave (the four rows of 16 lanes work redundantly), into
+// registers: lane r (mod 16) ends with row r of L in a[] (zeros above the
+// diagonal) and column r of its inverse in x[].  The first non-positive pivot
+// j of the block (inside the first mr rows) is reported in *info as
+// gbase + b0 + j + 1, and its reciprocal square root is taken as 1.
+__device__ __forceinline__ void chol16_factor(double (*T)[LDS_LD], int b0, int mr, int gbase,
+                                              int* info, double (&a)[16], double (&x)[16]) {
   const int lane = threadIdx.x & 63, r = lane & 15;
-  double a[16], x[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) {
     a[c] = T[b0 + c][b0 + r];
@@ -82,12 +82,26 @@ __device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[
   if (lane == 0 && bad > 0 && b0 + bad - 1 < mr) atomicCAS(info, 0, gbase + b0 + bad);
 #pragma unroll
   for (int c = 0; c < 16; ++c) a[c] = (r >= c) ? a[c] : 0.0;
+}
+
+// L replaces the lower part of the block (zeros above), its inverse goes to
+// the same block of X (zeros above).
+__device__ __forceinline__ void chol16_store(double (*T)[LDS_LD], double (*X)[LDS_LD], int b0,
+                                             const double (&a)[16], const double (&x)[16]) {
+  const int lane = threadIdx.x & 63, r = lane & 15;
   if (lane < 16) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) T[b0 + c][b0 + r] = a[c];
 #pragma unroll
     for (int i = 0; i < 16; ++i) X[b0 + r][b0 + i] = x[i];
   }
+}
+
+__device__ __forceinline__ void chol16_inverse(double (*T)[LDS_LD], double (*X)[LDS_LD], int b0,
+                                               int mr, int gbase, int* info) {
+  double a[16], x[16];
+  chol16_factor(T, b0, mr, gbase, info, a, x);
+  chol16_store(T, X, b0, a, x);
 }
 
 // C(m, n) += sum_k A(m, k) B(n, k) over one 16-deep block, m, n, k < 16, for
@@ -120,16 +134,26 @@ __device__ inline void mma16(double4_t& acc, double (*As)[LDS_LD], int am, int a
 // non-positive pivot stores its 1-based global index gbase + j + 1 in *info
 // (first one wins) and its reciprocal square root is taken as 1 so that the
 // factorization stays finite.  Only the lower triangle of T is meaningful on return.
+//
+// With lflag != NULL, X enters holding a 64 x 64 tile B (X[k][r] = B(r, k))
+// and the tile factored is T - B B^T: wave 0 subtracts B B^T from the first
+// diagonal block and factors it at once, while waves 1-3 update the nine other
+// lower blocks; once B has been read by every wave, *lflag = epoch is
+// published (after this workgroup's earlier global stores have drained) and X
+// is reused for the inverse.  The last rank-64 update of a diagonal tile thus
+// overlaps the factorization of its first block.
 __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double (*X)[LDS_LD], int mr, int gbase,
-                                    int* info) {
+                                    int* info, int* lflag = nullptr, int epoch = 0) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   // zero the six strictly upper 16 x 16 blocks of X: X[16 jb + c][16 ib + r], ib < jb
-  for (int e = t; e < 6 * 256; e += 256) {
-    const int blk = e >> 8, r = e & 15, c = (e >> 4) & 15;
-    const int ib = blk < 3 ? 0 : (blk < 5 ? 1 : 2);
-    const int jb = blk < 3 ? blk + 1 : (blk < 5 ? blk - 1 : 3);
-    X[16 * jb + c][16 * ib + r] = 0.0;
-  }
+  const auto zero_upper_x = [&]() {
+    for (int e = t; e < 6 * 256; e += 256) {
+      const int blk = e >> 8, r = e & 15, c = (e >> 4) & 15;
+      const int ib = blk < 3 ? 0 : (blk < 5 ? 1 : 2);
+      const int jb = blk < 3 ? blk + 1 : (blk < 5 ? blk - 1 : 3);
+      X[16 * jb + c][16 * ib + r] = 0.0;
+    }
+  };
   // Y_ij into the X_ij slot / X_ij = -X_ii Y_ij in place (one wave each)
   const auto inv_stage = [&](int i, int j) {
     double4_t acc = {0.0, 0.0, 0.0, 0.0};
@@ -144,7 +168,41 @@ __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double 
 #pragma unroll
     for (int q = 0; q < 4; ++q) X[16 * j + (lane >> 4) + 4 * q][16 * i + (lane & 15)] = -acc[q];
   };
-  if (w == 0) chol16_inverse(T, X, 0, mr, gbase, info);
+  if (lflag) {
+    // T block (ib, jb) -= sum_{k < 64} B(16 ib + m, k) B(16 jb + n, k)
+    const auto b_update = [&](int ib, int jb) {
+      double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) mma16<false>(acc, X, 16 * ib, 16 * s, X, 16 * jb, 16 * s);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) T[16 * jb + (lane >> 4) + 4 * q][16 * ib + (lane & 15)] -= acc[q];
+    };
+    if (w == 0) {
+      b_update(0, 0);
+      // the block just written by other lanes of this wave is read below
+      __builtin_amdgcn_wave_barrier();
+      double a[16], x[16];
+      chol16_factor(T, 0, mr, gbase, info, a, x);
+      // L_00 in place; its inverse waits in the unused upper block (0, 1) of
+      // T (T[16 + i][r] = inverse(i, r)) until B has been read
+      chol16_store(T, T + 16, 0, a, x);
+    } else {
+      // lower blocks of block rows 1..3 in row order, three per wave:
+      // (1,0) (1,1) (2,0) | (2,1) (2,2) (3,0) | (3,1) (3,2) (3,3)
+      for (int u = 0; u < 3; ++u) {
+        const int idx = 3 * (w - 1) + u;
+        const int ib = idx < 2 ? 1 : (idx < 5 ? 2 : 3);
+        const int jb = idx - (ib == 1 ? 0 : (ib == 2 ? 2 : 5));
+        b_update(ib, jb);
+      }
+    }
+    publish_flag(lflag, epoch);           // B read by every wave: X is free
+    zero_upper_x();
+    X[t >> 4][t & 15] = T[16 + (t >> 4)][t & 15];   // X_00 (256 threads, one element each)
+  } else {
+    zero_upper_x();
+    if (w == 0) chol16_inverse(T, X, 0, mr, gbase, info);
+  }
   __syncthreads();
   for (int kb = 0; kb < 3; ++kb) {
     const int b0 = 16 * kb;
