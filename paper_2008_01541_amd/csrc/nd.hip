@@ -92,10 +92,48 @@ void nd_gather_rhs(int cnt, const int32_t* tlist, int n1, const int32_t* node_of
                                                      contrib, ldc, dst, ldd);
 }
 
-__device__ inline double nd_wave_sum(double v) {
+// Partner exchange of a transposed reduction: the lanes with bit hi set keep
+// value b and give a away, the others keep a and give b; returns kept +
+// the partner's given, i.e. the pair's sum of the value this lane keeps.
+__device__ inline double nd_xchg(double a, double b, bool hi, int mask) {
+  const double give = hi ? a : b, keep = hi ? b : a;
+  return keep + __shfl_xor(give, mask, 64);
+}
+
+// Wave sums of the twelve values s[0..11]: every exchange halves the values
+// a lane still carries (6 -> 3 -> 2 -> 1, then two plain rounds), 14
+// exchanges instead of 72.  Value idx = 6 b5 + 3 b4 + 2 b3 + b2 (bits of the
+// lane; b3 = b2 = 1 carries padding) ends, summed over the wave in a fixed
+// order, in the four lanes with those bits.
+__device__ inline double nd_wave_sum12(const double (&s)[12], int& idx) {
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+  double t[6], u[3];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  for (int k = 0; k < 6; ++k) t[k] = nd_xchg(s[k], s[6 + k], b5, 32);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) u[k] = nd_xchg(t[k], t[3 + k], b4, 16);
+  const double w0 = nd_xchg(u[0], u[2], b3, 8);
+  const double w1 = nd_xchg(u[1], 0.0, b3, 8);
+  double x = nd_xchg(w0, w1, b2, 4);
+  x += __shfl_xor(x, 2, 64);
+  x += __shfl_xor(x, 1, 64);
+  idx = (b5 ? 6 : 0) + (b4 ? 3 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
+  return x;
+}
+
+// The same for three values: value idx = 2 b5 + b4 (b5 = b4 = 1: padding)
+// ends in the sixteen lanes with those bits.
+__device__ inline double nd_wave_sum3(double s0, double s1, double s2, int& idx) {
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16;
+  const double w0 = nd_xchg(s0, s2, b5, 32);
+  const double w1 = nd_xchg(s1, 0.0, b5, 32);
+  double x = nd_xchg(w0, w1, b4, 16);
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  idx = (b5 ? 2 : 0) + (b4 ? 1 : 0);
+  return x;
 }
 
 // s += sign * sum_{r < n} M[r] x[r] (three columns of x, stride ldx) over
@@ -133,7 +171,7 @@ __device__ __forceinline__ void nd_dot(const double* __restrict__ M, const doubl
 }
 
 // The same for four columns M, M + ldm, M + 2 ldm, M + 3 ldm at once (nc of
-// them valid): the vector entries are loaded once for the four, two rows
+// them valid): the vector entries are loaded once for the four, four rows
 // per lane and step.
 template <int SIGN>
 __device__ __forceinline__ void nd_dot4(const double* __restrict__ M, long ldm, int nc,
@@ -183,14 +221,9 @@ __global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ item
     nd_dot<1>(M, xa + it.xoff, ldxa, it.split, s0, s1, s2);
     if (it.rows > it.split)
       nd_dot<-1>(M + it.split, xb + it.x2off, ldxb, it.rows - it.split, s0, s1, s2);
-    s0 = nd_wave_sum(s0);
-    s1 = nd_wave_sum(s1);
-    s2 = nd_wave_sum(s2);
-    if (lane == 0) {
-      y[it.yoff + c] = s0;
-      y[ldy + it.yoff + c] = s1;
-      y[2 * ldy + it.yoff + c] = s2;
-    }
+    int k;
+    const double v = nd_wave_sum3(s0, s1, s2, k);
+    if ((lane & 15) == 0 && k < 3) y[k * ldy + it.yoff + c] = v;
     return;
   }
   const int c0 = it.col0 + 4 * w;
@@ -205,19 +238,15 @@ __global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ item
   nd_dot4<1>(M, it.ldm, nc, xa + it.xoff, ldxa, it.split, s);
   if (it.rows > it.split)
     nd_dot4<-1>(M + it.split, it.ldm, nc, xb + it.x2off, ldxb, it.rows - it.split, s);
+  double sf[12];
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s[c][k] = nd_wave_sum(s[c][k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (c < nc) {
-        y[it.yoff + c0 + c] = s[c][0];
-        y[ldy + it.yoff + c0 + c] = s[c][1];
-        y[2 * ldy + it.yoff + c0 + c] = s[c][2];
-      }
-  }
+    for (int k = 0; k < 3; ++k) sf[3 * c + k] = s[c][k];
+  int idx;
+  const double v = nd_wave_sum12(sf, idx);
+  const int c = idx / 3, k = idx - 3 * c;
+  if ((lane & 3) == 0 && (lane & 12) != 12 && c < nc) y[k * ldy + it.yoff + c0 + c] = v;
 }
 void nd_gemv(int nitems, const NdItem* items, const double* M, const double* xa, long ldxa,
              const double* xb, long ldxb, double* y, long ldy, hipStream_t st) {
