@@ -197,25 +197,35 @@ struct NdItem {
   int64_t moff;
   int32_t ldm, rows, cols, col0, xoff, yoff, split, x2off, cpw;
 };
+// A target of the right-hand-side gather: the node whose force it starts
+// from, its output index, and the range [c0, c1) of its contributions in the
+// target-major contribution vector.
+struct alignas(16) NdTarget {
+  int32_t node, out, c0, c1;
+};
+// An entry of the boundary gather: boundary entry e and its key.
+struct alignas(8) NdEntry {
+  int32_t e, key;
+};
 // Adds the lower entries (r >= c) of the b x b update matrix U of a child
 // into its parent's front: i = map[r], j = map[c]; j < ns: into the front's
 // first ns columns P (F_ss entries mirrored to the upper triangle), else into
 // the trailing update block Uo at (i - ns, j - ns) (mirrored when mirror).
 void nd_extend_add(const double* U, long ldu, int b, const int32_t* map, int ns, double* P,
                    long ldp, double* Uo, long lduo, int mirror, hipStream_t st);
-// dst[v][t or t - n1] = f[v][node_of[t]] - sum_{e in [ptr[t], ptr[t+1])} contrib[v][slot[e]]
-// for the cnt targets t of tlist (t < n1: elimination position; t >= n1: region index t - n1).
-void nd_gather_rhs(int cnt, const int32_t* tlist, int n1, const int32_t* node_of, const double* f,
-                   long ldf, const int32_t* ptr, const int32_t* slot, const double* contrib,
-                   long ldc, double* dst, long ldd, hipStream_t st);
-// y = M^T [xa; -xb] per item (see NdItem), three right-hand sides.
+// dst[v][out] = f[v][node] - sum_{c0 <= e < c1} contrib[v][e] for the cnt targets of trec.
+void nd_gather_rhs(int cnt, const NdTarget* trec, const double* f, long ldf,
+                   const double* contrib, long ldc, double* dst, long ldd, hipStream_t st);
+// y = M^T [xa; -xb] per item (see NdItem), three right-hand sides; the result
+// of column index q = yoff + column goes to y[ymap[q]] (ymap may be null: y[q]).
 void nd_gemv(int nitems, const NdItem* items, const double* M, const double* xa, long ldxa,
-             const double* xb, long ldxb, double* y, long ldy, hipStream_t st);
+             const double* xb, long ldxb, double* y, long ldy, const int32_t* ymap,
+             hipStream_t st);
 // dst (cols x rows) = src^T (src rows x cols), column-major.
 void nd_transpose(const double* src, long lds, int rows, int cols, double* dst, long ldd,
                   hipStream_t st);
-// zb[v][e] = key[e] < n1 ? z[v][key[e]] : d2[v][key[e] - n1] for the cnt entries of elist.
-void nd_gather_zb(int cnt, const int32_t* elist, const int32_t* key, int n1, const double* z,
-                  long ldz, const double* d2, long ldd2, double* zb, long ldzb, hipStream_t st);
+// zb[v][e] = key < n1 ? z[v][key] : d2[v][key - n1] for the cnt entries (e, key) of erec.
+void nd_gather_zb(int cnt, const NdEntry* erec, int n1, const double* z, long ldz,
+                  const double* d2, long ldd2, double* zb, long ldzb, hipStream_t st);
 
 }  // namespace pdk

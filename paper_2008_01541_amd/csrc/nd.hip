@@ -43,33 +43,28 @@ void nd_extend_add(const double* U, long ldu, int b, const int32_t* map, int ns,
                                                                    lduo, mirror);
 }
 
-// dst[v][o] = f[v][node_of[t]] - sum_{e in [ptr[t], ptr[t+1])} contrib[v][slot[e]]
-// for the cnt targets t listed in tlist: t < n1 is an elimination position
-// (o = t), t >= n1 the region node t - n1 (o = t - n1).  Eight lanes share a
-// target: lane k adds slots k, k + 8, ..., then the eight partial sums are
-// combined by a fixed butterfly, so loads of different slots are in flight
-// together and the result does not depend on timing.
-__global__ __launch_bounds__(256) void k_nd_gather_rhs(int cnt, const int32_t* __restrict__ tlist,
-                                                       int n1, const int32_t* __restrict__ node_of,
+// dst[v][out] = f[v][node] - sum_{c0 <= e < c1} contrib[v][e] for the cnt
+// targets of trec (the forward products store their contributions
+// target-major, so each target's are contiguous).  Eight lanes share a
+// target: lane k adds entries k, k + 8, ..., then the eight partial sums are
+// combined by a fixed butterfly, so loads of different entries are in flight
+// together and the result does not depend on timing.  A target costs two
+// dependent loads: its record, then its contributions and force.
+__global__ __launch_bounds__(256) void k_nd_gather_rhs(int cnt, const NdTarget* __restrict__ trec,
                                                        const double* __restrict__ f, long ldf,
-                                                       const int32_t* __restrict__ ptr,
-                                                       const int32_t* __restrict__ slot,
                                                        const double* __restrict__ contrib,
                                                        long ldc, double* __restrict__ dst,
                                                        long ldd) {
   const int g = (int)((blockIdx.x * (long)blockDim.x + threadIdx.x) >> 3);
   const int k = threadIdx.x & 7;
   const bool on = g < cnt;
-  const int t = on ? tlist[g] : 0;
+  const NdTarget tr = on ? trec[g] : NdTarget{0, 0, 0, 0};
+  const double fv = (on && k < 3) ? f[k * ldf + tr.node] : 0.0;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (on) {
-    const int e1 = ptr[t + 1];
-    for (int e = ptr[t] + k; e < e1; e += 8) {
-      const long q = slot[e];
-      s0 += contrib[q];
-      s1 += contrib[ldc + q];
-      s2 += contrib[2 * ldc + q];
-    }
+  for (int e = tr.c0 + k; e < tr.c1; e += 8) {
+    s0 += contrib[e];
+    s1 += contrib[ldc + e];
+    s2 += contrib[2 * ldc + e];
   }
 #pragma unroll
   for (int o = 4; o > 0; o >>= 1) {
@@ -77,19 +72,12 @@ __global__ __launch_bounds__(256) void k_nd_gather_rhs(int cnt, const int32_t* _
     s1 += __shfl_xor(s1, o, 64);
     s2 += __shfl_xor(s2, o, 64);
   }
-  if (on && k < 3) {
-    const long node = node_of[t];
-    const int out = t < n1 ? t : t - n1;
-    const double sv = k == 0 ? s0 : (k == 1 ? s1 : s2);
-    dst[k * ldd + out] = f[k * ldf + node] - sv;
-  }
+  if (on && k < 3) dst[k * ldd + tr.out] = fv - (k == 0 ? s0 : (k == 1 ? s1 : s2));
 }
-void nd_gather_rhs(int cnt, const int32_t* tlist, int n1, const int32_t* node_of, const double* f,
-                   long ldf, const int32_t* ptr, const int32_t* slot, const double* contrib,
-                   long ldc, double* dst, long ldd, hipStream_t st) {
+void nd_gather_rhs(int cnt, const NdTarget* trec, const double* f, long ldf,
+                   const double* contrib, long ldc, double* dst, long ldd, hipStream_t st) {
   if (cnt > 0)
-    k_nd_gather_rhs<<<(cnt + 31) / 32, 256, 0, st>>>(cnt, tlist, n1, node_of, f, ldf, ptr, slot,
-                                                     contrib, ldc, dst, ldd);
+    k_nd_gather_rhs<<<(cnt + 31) / 32, 256, 0, st>>>(cnt, trec, f, ldf, contrib, ldc, dst, ldd);
 }
 
 // Partner exchange of a transposed reduction: the lanes with bit hi set keep
@@ -201,21 +189,26 @@ __device__ __forceinline__ void nd_dot4(const double* __restrict__ M, long ldm, 
   }
 }
 
-// y[yoff + c] = sum_{r < split} M(r, c) xa[xoff + r] - sum_{split <= r < rows}
-// M(r, c) xb[x2off + r - split] for the columns of an item (three right-hand
-// sides): cpw = 1, one column per wave (columns col0 + w); cpw = 4, four per
-// wave (col0 + 4 w .. + 3), for short columns, whose loads are then shared.
-// The lanes' sums are added across the wave at the end (fixed order).
+// y[q] (q = yoff + c, or ymap[q]) = sum_{r < split} M(r, c) xa[xoff + r] -
+// sum_{split <= r < rows} M(r, c) xb[x2off + r - split] for the columns of an
+// item (three right-hand sides): cpw = 1, one column per wave (columns
+// col0 + w); cpw = 4, four per wave (col0 + 4 w .. + 3), for short columns,
+// whose loads are then shared.  The lanes' sums are added across the wave at
+// the end (fixed order); the storing lanes read their output index first.
 __global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ items,
                                                  const double* __restrict__ Mb,
                                                  const double* __restrict__ xa, long ldxa,
                                                  const double* __restrict__ xb, long ldxb,
-                                                 double* __restrict__ y, long ldy) {
+                                                 double* __restrict__ y, long ldy,
+                                                 const int32_t* __restrict__ ymap) {
   const NdItem it = items[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (it.cpw == 1) {
     const int c = it.col0 + w;
     if (c >= it.cols) return;
+    // lanes 0, 16, 32 store the three sums (nd_wave_sum3)
+    const bool store = (lane & 15) == 0 && (lane >> 4) < 3;
+    const int o = store ? (ymap ? ymap[it.yoff + c] : it.yoff + c) : 0;
     const double* M = Mb + it.moff + (long)c * it.ldm;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     nd_dot<1>(M, xa + it.xoff, ldxa, it.split, s0, s1, s2);
@@ -223,12 +216,18 @@ __global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ item
       nd_dot<-1>(M + it.split, xb + it.x2off, ldxb, it.rows - it.split, s0, s1, s2);
     int k;
     const double v = nd_wave_sum3(s0, s1, s2, k);
-    if ((lane & 15) == 0 && k < 3) y[k * ldy + it.yoff + c] = v;
+    if (store) y[k * ldy + o] = v;
     return;
   }
   const int c0 = it.col0 + 4 * w;
   if (c0 >= it.cols) return;
   const int nc = min(4, it.cols - c0);
+  // the lane that stores sum idx (nd_wave_sum12): column idx / 3, component idx % 3
+  const int sidx = ((lane & 32) ? 6 : 0) + ((lane & 16) ? 3 : 0) + ((lane & 8) ? 2 : 0) +
+                   ((lane & 4) ? 1 : 0);
+  const int sc = sidx / 3;
+  const bool store = (lane & 3) == 0 && (lane & 12) != 12 && sc < nc;
+  const int o = store ? (ymap ? ymap[it.yoff + c0 + sc] : it.yoff + c0 + sc) : 0;
   const double* M = Mb + it.moff + (long)c0 * it.ldm;
   double s[4][3];
 #pragma unroll
@@ -245,12 +244,12 @@ __global__ __launch_bounds__(256) void k_nd_gemv(const NdItem* __restrict__ item
     for (int k = 0; k < 3; ++k) sf[3 * c + k] = s[c][k];
   int idx;
   const double v = nd_wave_sum12(sf, idx);
-  const int c = idx / 3, k = idx - 3 * c;
-  if ((lane & 3) == 0 && (lane & 12) != 12 && c < nc) y[k * ldy + it.yoff + c0 + c] = v;
+  if (store) y[(idx - 3 * sc) * ldy + o] = v;
 }
 void nd_gemv(int nitems, const NdItem* items, const double* M, const double* xa, long ldxa,
-             const double* xb, long ldxb, double* y, long ldy, hipStream_t st) {
-  if (nitems > 0) k_nd_gemv<<<nitems, 256, 0, st>>>(items, M, xa, ldxa, xb, ldxb, y, ldy);
+             const double* xb, long ldxb, double* y, long ldy, const int32_t* ymap,
+             hipStream_t st) {
+  if (nitems > 0) k_nd_gemv<<<nitems, 256, 0, st>>>(items, M, xa, ldxa, xb, ldxb, y, ldy, ymap);
 }
 
 // dst (cols x rows, leading dimension ldd) = transpose of src (rows x cols,
@@ -274,25 +273,24 @@ void nd_transpose(const double* src, long lds, int rows, int cols, double* dst, 
   k_nd_transpose<<<grid, 256, 0, st>>>(src, lds, rows, cols, dst, ldd);
 }
 
-// zb[v][e] = (t < n1) ? z[v][t] : d2[v][t - n1] with t = key[e], for the
-// cnt boundary entries e listed in elist.
-__global__ void k_nd_gather_zb(int cnt, const int32_t* __restrict__ elist,
-                               const int32_t* __restrict__ key, int n1,
+// zb[v][e] = (key < n1) ? z[v][key] : d2[v][key - n1] for the cnt entries
+// (e, key) of erec.
+__global__ void k_nd_gather_zb(int cnt, const NdEntry* __restrict__ erec, int n1,
                                const double* __restrict__ z, long ldz,
                                const double* __restrict__ d2, long ldd2, double* __restrict__ zb,
                                long ldzb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
-  const int e = elist[i], t = key[e];
+  const NdEntry en = erec[i];
+  const int t = en.key;
 #pragma unroll
   for (int v = 0; v < 3; ++v)
-    zb[v * ldzb + e] = t < n1 ? z[v * ldz + t] : d2[v * ldd2 + (t - n1)];
+    zb[v * ldzb + en.e] = t < n1 ? z[v * ldz + t] : d2[v * ldd2 + (t - n1)];
 }
-void nd_gather_zb(int cnt, const int32_t* elist, const int32_t* key, int n1, const double* z,
-                  long ldz, const double* d2, long ldd2, double* zb, long ldzb, hipStream_t st) {
+void nd_gather_zb(int cnt, const NdEntry* erec, int n1, const double* z, long ldz,
+                  const double* d2, long ldd2, double* zb, long ldzb, hipStream_t st) {
   if (cnt > 0)
-    k_nd_gather_zb<<<(cnt + 255) / 256, 256, 0, st>>>(cnt, elist, key, n1, z, ldz, d2, ldd2,
-                                                      zb, ldzb);
+    k_nd_gather_zb<<<(cnt + 255) / 256, 256, 0, st>>>(cnt, erec, n1, z, ldz, d2, ldd2, zb, ldzb);
 }
 
 }  // namespace pdk

@@ -257,8 +257,9 @@ struct NdFactor {
   int32_t treg_off = 0;                   // region targets in tlist
   int64_t fac_doubles = 0;
   double* d_fac = nullptr;
-  int32_t *d_node_of = nullptr, *d_cptr = nullptr, *d_cslot = nullptr, *d_bkey = nullptr;
-  int32_t *d_tlist = nullptr, *d_elist = nullptr;
+  int32_t *d_node_of = nullptr, *d_cpos = nullptr;
+  NdTarget* d_trec = nullptr;             // targets of the right-hand-side gathers, tlist order
+  NdEntry* d_erec = nullptr;              // entries of the boundary gathers, elist order
   NdItem* d_items = nullptr;
   double *d_r = nullptr, *d_x1 = nullptr, *d_contrib = nullptr, *d_zb = nullptr;
 };
@@ -476,7 +477,8 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
   }
 
   // sweep structures: node of every target, the contributions of every
-  // target (boundary entries in increasing order), the per-height lists
+  // target (boundary entries in increasing order, stored target-major by the
+  // forward products: cpos[e] is entry e's position), the per-height lists
   {
     std::vector<int32_t> node_of(S.elim);
     node_of.insert(node_of.end(), c->region_ids.begin(), c->region_ids.end());
@@ -529,14 +531,19 @@ pd_status nd_factor(pd_ctx* c, const int32_t* tets, int64_t T, const std::vector
     }
     F->treg_off = (int32_t)tlist.size();
     for (int64_t r = 0; r < m; ++r) tlist.push_back((int32_t)(n1 + r));
-    std::vector<int32_t> bkey(S.bkey);
-    if (bkey.empty()) bkey.push_back(0);
+    std::vector<int32_t> cpos(std::max<int64_t>(nb, 1), 0);
+    for (int64_t q = 0; q < nb; ++q) cpos[cslot[q]] = (int32_t)q;
+    std::vector<NdTarget> trec(std::max<size_t>(tlist.size(), 1), NdTarget{0, 0, 0, 0});
+    for (size_t g = 0; g < tlist.size(); ++g) {
+      const int32_t t = tlist[g];
+      trec[g] = NdTarget{node_of[t], t < n1 ? t : (int32_t)(t - n1), cptr[t], cptr[t + 1]};
+    }
+    std::vector<NdEntry> erec(std::max<size_t>(elist.size(), 1), NdEntry{0, 0});
+    for (size_t i = 0; i < elist.size(); ++i) erec[i] = NdEntry{elist[i], S.bkey[elist[i]]};
     CK(c->upload(&F->d_node_of, node_of));
-    CK(c->upload(&F->d_cptr, cptr));
-    CK(c->upload(&F->d_cslot, cslot));
-    CK(c->upload(&F->d_bkey, bkey));
-    CK(c->upload(&F->d_tlist, tlist));
-    CK(c->upload(&F->d_elist, elist));
+    CK(c->upload(&F->d_cpos, cpos));
+    CK(c->upload(&F->d_trec, trec));
+    CK(c->upload(&F->d_erec, erec));
     CK(c->upload(&F->d_items, items));
     const int64_t v1 = 3 * std::max<int64_t>(n1, 1), vb = 3 * std::max<int64_t>(nb, 1);
     CK(c->alloc(&F->d_r, v1));
@@ -555,13 +562,11 @@ void nd_condense(pd_ctx* c, const double* f, double* y2) {
   for (const NdFactor::Level& L : F->levels) {
     // r = f1 - (contributions of the descendants), then the contributions
     // W r of this height to its boundary
-    nd_gather_rhs(L.t_cnt, F->d_tlist + L.t_off, n1, F->d_node_of, f, c->n, F->d_cptr,
-                  F->d_cslot, F->d_contrib, nb, F->d_r, n1, c->st);
+    nd_gather_rhs(L.t_cnt, F->d_trec + L.t_off, f, c->n, F->d_contrib, nb, F->d_r, n1, c->st);
     nd_gemv(L.fw_cnt, F->d_items + L.fw_off, F->d_fac, F->d_r, n1, nullptr, 0, F->d_contrib, nb,
-            c->st);
+            F->d_cpos, c->st);
   }
-  nd_gather_rhs(m, F->d_tlist + F->treg_off, n1, F->d_node_of, f, c->n, F->d_cptr, F->d_cslot,
-                F->d_contrib, nb, y2, m, c->st);
+  nd_gather_rhs(m, F->d_trec + F->treg_off, f, c->n, F->d_contrib, nb, y2, m, c->st);
 }
 
 void nd_backsub(pd_ctx* c, const double* delta2, double* x, bool zero_w) {
@@ -574,10 +579,9 @@ void nd_backsub(pd_ctx* c, const double* delta2, double* x, bool zero_w) {
     const NdFactor::Level& L = F->levels[h];
     // zb = solution at the boundary (ancestors, or delta2 on the region),
     // x1 = Z r - W^T zb
-    nd_gather_zb(L.e_cnt, F->d_elist + L.e_off, F->d_bkey, n1, F->d_x1, n1, delta2, m, F->d_zb,
-                 nb, c->st);
+    nd_gather_zb(L.e_cnt, F->d_erec + L.e_off, n1, F->d_x1, n1, delta2, m, F->d_zb, nb, c->st);
     nd_gemv(L.bw_cnt, F->d_items + L.bw_off, F->d_fac, F->d_r, n1, F->d_zb, nb, F->d_x1, n1,
-            c->st);
+            nullptr, c->st);
   }
   scatter_add_rows3(n1, F->d_node_of, F->d_x1, n1, x, c->n, c->st);
 }
