@@ -159,7 +159,7 @@ __device__ __forceinline__ void nd_dot(const double* __restrict__ M, const doubl
 }
 
 // The same for four columns M, M + ldm, M + 2 ldm, M + 3 ldm at once (nc of
-// them valid): the vector entries are loaded once for the four, four rows
+// them valid): the vector entries are loaded once for the four, two rows
 // per lane and step.
 template <int SIGN>
 __device__ __forceinline__ void nd_dot4(const double* __restrict__ M, long ldm, int nc,
