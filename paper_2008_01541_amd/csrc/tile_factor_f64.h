@@ -184,7 +184,8 @@ __device__ __forceinline__ void factor_tile_blocked(double (*T)[LDS_LD], double 
       double a[16], x[16];
       chol16_factor(T, 0, mr, gbase, info, a, x);
       // L_00 in place; its inverse waits in the unused upper block (0, 1) of
-      // T (T[16 + i][r] = inverse(i, r)) until B has been read
+      // T, in the layout of X (T[16 + c][r] = inverse(r, c)), until B has
+      // been read
       chol16_store(T, T + 16, 0, a, x);
     } else {
       // lower blocks of block rows 1..3 in row order, three per wave:
